@@ -1,0 +1,168 @@
+/*
+ * fr.h -- C ABI of the MI355X (gfx950) flux-reconstruction residual library
+ * for the artificial compressibility method with hyperbolised diffusion
+ * (ACM-HD) on constant-Jacobian tensor-product hexahedra.
+ *
+ * Method: Trojak, Watson, Witherden, "Hyperbolic Diffusion in Flux
+ * Reconstruction: Optimisation through Kernel Fusion within Tensor-Product
+ * Elements", arXiv:2107.14027.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * State layout ("element-major SoA"): one state array holds
+ *     ne * 13 * m^3 scalars,  m = p + 1,  ne = nx * ny * nz,
+ * indexed U[e][v][k][j][i] with i (the xi_1 point index) fastest and
+ * e = ex + nx * (ey + ny * ez).  Variables v, in order:
+ *     P, u, v, w, q_x, q_y, q_z, r_x, r_y, r_z, s_x, s_y, s_z
+ * where q = grad u, r = grad v, s = grad w (the auxiliary variables of the
+ * hyperbolised diffusion, paper Sec. 2.2, eq. acmhd_nd).  Solution points are
+ * the Gauss-Legendre points of each element.  The lattice is periodic in all
+ * three directions; element (ex, ey, ez) is the image of the reference cube
+ * [-1, 1]^3 under x = J (xi + 1 + 2 (ex, ey, ez)) with one constant Jacobian J.
+ *
+ * Pointers named U, R, G, Un, ... are DEVICE pointers, owned by the caller,
+ * contiguous, at least 16-byte aligned (256 recommended).  Arrays of the
+ * plan's working precision are float or double as selected with
+ * FR_OPT_PRECISION; arrays typed double are always double.  Every call
+ * enqueues its work on the caller's stream `s` (NULL = the null stream) and
+ * returns without synchronising, except where stated.  A plan may be used by
+ * one stream at a time: calls that overlap on one plan race on its scratch.
+ * No call throws across the ABI; failures return a negative fr_status and
+ * fr_last_error() (per thread) describes the last one.
+ */
+#ifndef FR_H
+#define FR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ABI-compatible with hipStream_t. */
+typedef struct ihipStream_t *fr_stream_t;
+typedef struct fr_plan fr_plan;
+
+typedef enum fr_status {
+    FR_OK = 0,
+    FR_EINVAL = -1,       /* bad argument (NULL, out of range, misaligned)           */
+    FR_ENOMEM = -2,       /* device or host allocation failed                        */
+    FR_EHIP = -3,         /* a HIP runtime call or kernel launch failed              */
+    FR_ENONFINITE = -4,   /* a residual norm became NaN or Inf                        */
+    FR_ENOCONV = -5,      /* pseudo-time iteration hit max_iters before the tolerance */
+    FR_EUNSUPPORTED = -6  /* option not available for this order / precision          */
+} fr_status;
+
+typedef enum fr_option {
+    FR_OPT_PRECISION = 1, /* FR_F64 (default) or FR_F32: working precision of the residual */
+    FR_OPT_VARIANT = 2,   /* FR_FUSED (default) or FR_UNFUSED                              */
+    FR_OPT_BLOCK = 3      /* elements per workgroup of the fused kernel; 0 = tuned default  */
+} fr_option;
+
+enum { FR_F64 = 0, FR_F32 = 1 };
+enum { FR_FUSED = 0, FR_UNFUSED = 1 };
+
+/*
+ * fr_plan_create -- build the 1D operators (Sec. 2.1: Gauss-Legendre solution
+ * points, Lagrange derivative matrix, DG correction functions, and the
+ * partially corrected divergence operator of Sec. 3 / Table 1 stage 3) and
+ * the constant geometry for a periodic nx*ny*nz lattice of order-p hexahedra.
+ *   p          polynomial order, 1..6
+ *   nx,ny,nz   lattice size, each >= 1 (1 means the element is its own neighbour)
+ *   jac        constant dx/dxi, row-major 3x3 with det > 0; NULL selects the
+ *              periodic box [0, 2 pi]^3, i.e. J = diag(pi/nx, pi/ny, pi/nz)
+ *   acm_zeta   artificial compressibility parameter zeta > 0 (Sec. 2.2)
+ *   hd_relax   {nu, T}: kinematic viscosity nu >= 0 and relaxation time T > 0 of
+ *              the hyperbolised diffusion (Sec. 2.2, eq. acmhd_nd)
+ * Host memory is allocated; device memory for operators is allocated on the
+ * current HIP device, scratch buffers lazily on first use.
+ * Returns NULL on error (fr_last_error() says why).  Thread-safe.
+ */
+fr_plan *fr_plan_create(int p, int nx, int ny, int nz, const double jac[9], double acm_zeta,
+                        const double hd_relax[2]);
+
+/* Set / read an fr_option.  Changing the precision or variant frees scratch
+ * that no longer applies.  FR_EINVAL for an unknown key or value. */
+int fr_plan_set_int(fr_plan *plan, int key, int value);
+int fr_plan_get_int(const fr_plan *plan, int key, int *value);
+
+/* Release the plan and all device memory it owns (waits for the device). */
+void fr_plan_destroy(fr_plan *plan);
+
+/* Number of scalars in one state array, ne * 13 * (p+1)^3. */
+size_t fr_state_len(const fr_plan *plan);
+
+/*
+ * fr_residual -- R = -div F + S(U), the FR right-hand side of ACM-HD
+ * (Table 1, stages 1-6; dU/dtau = R).  U and R are state arrays of the plan's
+ * precision, must not overlap.  Interface fluxes: Rusanov on (P, V), mean of
+ * the two normal fluxes for the auxiliary variables (Sec. 5).
+ * FR_FUSED runs two kernels: a face-trace projection (stage 1) and one fused
+ * kernel for stages 2-6 (flux, partially corrected divergence, common flux,
+ * correction, source); FR_UNFUSED runs the six stages as six kernels through
+ * HBM, as in Table 1.  Allocates the plan's trace scratch on first use.
+ */
+int fr_residual(fr_plan *plan, const void *U, void *R, fr_stream_t s);
+
+/*
+ * fr_rk_step -- nsteps classical fourth-order Runge-Kutta steps of size dt of
+ * dU/dtau = R(U) on all 13 variables.  U is a double state array updated in
+ * place; the stage accumulators are double; in FR_F32 precision each stage
+ * state is rounded to float for the residual.  Allocates scratch (three state
+ * arrays) on first use.
+ */
+int fr_rk_step(fr_plan *plan, double *U, double dt, int nsteps, fr_stream_t s);
+
+/*
+ * fr_dual_step -- one physical time step by dual time stepping (Sec. 5):
+ * pseudo-time RK4 steps of size dtau on dU/dtau = R*(U) with the BDF physical
+ * source on the velocity only (Sec. 2.2 time-derivative masks):
+ *     R*(U) = R(U) - M_V (3U - 4Un + Unm1) / (2 dt)     (Unm1 != NULL, BDF2)
+ *     R*(U) = R(U) - M_V (U - Un) / dt                  (Unm1 == NULL, BDF1)
+ * until the root mean square over all points of the three velocity
+ * components of R* falls below tol, tested on the first-stage residual of each
+ * pseudo-step (every `check_every` steps; 1 = every step).  The BDF terms and
+ * the norm are evaluated in double in either precision.
+ *   U       in: initial guess, out: last iterate (double state array)
+ *   iters   out: completed pseudo-steps;  resid: out: last norm computed
+ * Synchronises the stream at every convergence check (the norm is read back).
+ * Returns FR_OK, FR_ENOCONV (max_iters reached, U holds the last iterate) or
+ * FR_ENONFINITE.
+ */
+int fr_dual_step(fr_plan *plan, double *U, const double *Un, const double *Unm1, double dt,
+                 double dtau, double tol, int max_iters, int check_every, int *iters,
+                 double *resid, fr_stream_t s);
+
+/*
+ * fr_guess_extrap -- initial guess for the next physical step by polynomial
+ * extrapolation in time of the past states (double state arrays):
+ *   order 1: G = 2 Un - Unm1;   order 2: G = 3 Un - 3 Unm1 + Unm2.
+ * Unm2 may be NULL for order 1.  G may alias none of the inputs.
+ */
+int fr_guess_extrap(fr_plan *plan, const double *Un, const double *Unm1, const double *Unm2,
+                    int order, double *G, fr_stream_t s);
+
+/* Status text, and the description of the last failure on this thread. */
+const char *fr_strerror(int code);
+const char *fr_last_error(void);
+
+/*
+ * fr_plan_operators -- host-only copy of the plan's double-precision 1D
+ * operators for inspection (no device work).  out receives, in order:
+ *   x[m], w[m]            Gauss-Legendre points and weights
+ *   D[m][m]               D[i][k] = l_k'(x_i)
+ *   lm[m], lp[m]          l_k(-1), l_k(+1)
+ *   gl[m], gr[m]          derivatives of the left / right DG correction
+ *                         functions at the points (Sec. 2.1)
+ *   Dt[m][m]              partially corrected divergence operator
+ *                         D - gl lm^T - gr lp^T (Table 1, stage 3)
+ * i.e. m*(6 + 2m) doubles.  Returns FR_EINVAL for p outside 1..6.
+ */
+int fr_plan_operators(int p, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FR_H */

@@ -1,0 +1,208 @@
+"""ctypes binding of libfr.so (include/fr.h): same entry-point names, argument
+marshalling only.  Device arrays are torch tensors on a ROCm device; every step
+of the computation runs in the HIP library.  There is no fallback: if the
+library is not built, or a call fails, an exception is raised."""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfr.so")
+
+FR_OK, FR_EINVAL, FR_ENOMEM, FR_EHIP, FR_ENONFINITE, FR_ENOCONV, FR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FR_OPT_PRECISION, FR_OPT_VARIANT, FR_OPT_BLOCK = 1, 2, 3
+FR_F64, FR_F32 = 0, 1
+FR_FUSED, FR_UNFUSED = 0, 1
+NV = 13
+
+EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_destroy",
+            "fr_state_len", "fr_residual", "fr_rk_step", "fr_dual_step", "fr_guess_extrap",
+            "fr_strerror", "fr_last_error", "fr_plan_operators")
+
+
+class FrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_strerror(code), code, msg))
+        self.code = code
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """Load libfr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfr.so is not built (run: python -m paper_2107_14027_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        I, D = ctypes.c_int, ctypes.c_double
+        L.fr_plan_create.argtypes = [I, I, I, I, _dp, D, _dp]
+        L.fr_plan_create.restype = _vp
+        L.fr_plan_set_int.argtypes = [_vp, I, I]
+        L.fr_plan_get_int.argtypes = [_vp, I, ctypes.POINTER(I)]
+        L.fr_plan_destroy.argtypes = [_vp]
+        L.fr_plan_destroy.restype = None
+        L.fr_state_len.argtypes = [_vp]
+        L.fr_state_len.restype = ctypes.c_size_t
+        L.fr_residual.argtypes = [_vp, _vp, _vp, _vp]
+        L.fr_rk_step.argtypes = [_vp, _vp, D, I, _vp]
+        L.fr_dual_step.argtypes = [_vp, _vp, _vp, _vp, D, D, D, I, I, ctypes.POINTER(I), _dp, _vp]
+        L.fr_guess_extrap.argtypes = [_vp, _vp, _vp, _vp, I, _vp, _vp]
+        L.fr_strerror.argtypes = [I]
+        L.fr_strerror.restype = ctypes.c_char_p
+        L.fr_last_error.argtypes = []
+        L.fr_last_error.restype = ctypes.c_char_p
+        L.fr_plan_operators.argtypes = [I, _dp]
+        for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step",
+                  "fr_dual_step", "fr_guess_extrap", "fr_plan_operators"):
+            getattr(L, n).restype = I
+        _lib = L
+    return _lib
+
+
+def _strerror(code):
+    try:
+        return lib().fr_strerror(code).decode()
+    except Exception:  # pragma: no cover
+        return "error"
+
+
+def _check(rc):
+    if rc != FR_OK:
+        raise FrError(rc, lib().fr_last_error().decode())
+    return rc
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _vp(s.cuda_stream)
+
+
+def _dev(t, dtype=None, n=None, name="array"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a torch tensor on the GPU" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if n is not None and t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return _vp(t.data_ptr())
+
+
+# --------------------------------------------------------------------------- entry points
+def fr_plan_create(p, nx, ny, nz, jac, acm_zeta, hd_relax):
+    j = None if jac is None else np.ascontiguousarray(jac, dtype=np.float64).reshape(9)
+    h = np.ascontiguousarray(hd_relax, dtype=np.float64).reshape(2)
+    ptr = lib().fr_plan_create(p, nx, ny, nz, None if j is None else j.ctypes.data_as(_dp),
+                               float(acm_zeta), h.ctypes.data_as(_dp))
+    if not ptr:
+        raise FrError(FR_EINVAL, lib().fr_last_error().decode())
+    return ptr
+
+
+def fr_plan_set_int(plan, key, value):
+    return _check(lib().fr_plan_set_int(plan, key, value))
+
+
+def fr_plan_get_int(plan, key):
+    v = ctypes.c_int()
+    _check(lib().fr_plan_get_int(plan, key, ctypes.byref(v)))
+    return v.value
+
+
+def fr_plan_destroy(plan):
+    lib().fr_plan_destroy(plan)
+
+
+def fr_state_len(plan):
+    return lib().fr_state_len(plan)
+
+
+def fr_residual(plan, U, R, stream=None):
+    import torch
+    n = fr_state_len(plan)
+    dt = torch.float64 if fr_plan_get_int(plan, FR_OPT_PRECISION) == FR_F64 else torch.float32
+    return _check(lib().fr_residual(plan, _dev(U, dt, n, "U"), _dev(R, dt, n, "R"),
+                                    _stream(stream)))
+
+
+def fr_rk_step(plan, U, dt, nsteps, stream=None):
+    import torch
+    n = fr_state_len(plan)
+    return _check(lib().fr_rk_step(plan, _dev(U, torch.float64, n, "U"), float(dt), int(nsteps),
+                                   _stream(stream)))
+
+
+def fr_dual_step(plan, U, Un, Unm1, dt, dtau, tol, max_iters, check_every=1, stream=None,
+                 raise_on_error=True):
+    """Returns (status, iters, resid)."""
+    import torch
+    n = fr_state_len(plan)
+    it = ctypes.c_int()
+    res = ctypes.c_double()
+    rc = lib().fr_dual_step(plan, _dev(U, torch.float64, n, "U"), _dev(Un, torch.float64, n, "Un"),
+                            None if Unm1 is None else _dev(Unm1, torch.float64, n, "Unm1"),
+                            float(dt), float(dtau), float(tol), int(max_iters), int(check_every),
+                            ctypes.byref(it), ctypes.byref(res), _stream(stream))
+    if raise_on_error and rc not in (FR_OK, FR_ENOCONV):
+        _check(rc)
+    return rc, it.value, res.value
+
+
+def fr_guess_extrap(plan, Un, Unm1, Unm2, order, G, stream=None):
+    import torch
+    n = fr_state_len(plan)
+    f = lambda t, nm: None if t is None else _dev(t, torch.float64, n, nm)
+    return _check(lib().fr_guess_extrap(plan, f(Un, "Un"), f(Unm1, "Unm1"), f(Unm2, "Unm2"),
+                                        int(order), f(G, "G"), _stream(stream)))
+
+
+def fr_plan_operators(p):
+    """Host-only: dict of the plan's double-precision 1D operators."""
+    m = p + 1
+    out = np.zeros(m * (6 + 2 * m))
+    _check(lib().fr_plan_operators(p, out.ctypes.data_as(_dp)))
+    o, r = 0, {}
+    for name, size, shape in (("x", m, (m,)), ("w", m, (m,)), ("D", m * m, (m, m)),
+                              ("lm", m, (m,)), ("lp", m, (m,)), ("gl", m, (m,)), ("gr", m, (m,)),
+                              ("Dt", m * m, (m, m))):
+        r[name] = out[o:o + size].reshape(shape)
+        o += size
+    return r
+
+
+class Plan:
+    """Owning wrapper around an fr_plan handle."""
+
+    def __init__(self, p, n, zeta, nu, T, jac=None, precision=FR_F64, variant=FR_FUSED, block=0):
+        self.p, self.n = p, tuple(n)
+        self.handle = fr_plan_create(p, n[0], n[1], n[2], jac, zeta, (nu, T))
+        fr_plan_set_int(self.handle, FR_OPT_PRECISION, precision)
+        fr_plan_set_int(self.handle, FR_OPT_VARIANT, variant)
+        if block:
+            fr_plan_set_int(self.handle, FR_OPT_BLOCK, block)
+
+    @property
+    def state_len(self):
+        return fr_state_len(self.handle)
+
+    def set(self, key, value):
+        fr_plan_set_int(self.handle, key, value)
+
+    def close(self):
+        if self.handle:
+            fr_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,92 @@
+// Internal declarations shared by the host plan code and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/fr.h"
+
+namespace fr {
+
+constexpr int NV = 13;   // P, V(3), grad V (9)
+constexpr int NTR = 7;   // face trace values: P, V(3), (S n_hat)(3)
+constexpr int PMAX = 6;
+
+// Geometry and physics constants handed to every kernel by value.
+template <typename T>
+struct Consts {
+    T nvec[3][3];  // n_d = det(J) J^{-T} e_d  (row d)
+    T nmag[3];     // |n_d|
+    T nhat[3][3];  // n_d / |n_d|
+    T inv_det;     // 1 / det(J)
+    T zeta, nu, invT;
+};
+
+// Operator block in device memory, precision T, for order p (m = p + 1):
+//   Dt[m][m]  partially corrected divergence operator
+//   gl[m], gr[m]  correction function derivatives at the points
+//   lm[m], lp[m]  Lagrange basis at xi = -1, +1
+template <int M>
+struct OpsLayout {
+    static constexpr int Dt = 0, gl = M * M, gr = M * M + M, lm = M * M + 2 * M,
+                         lp = M * M + 3 * M, size = M * M + 4 * M;
+};
+
+struct Scratch {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace fr
+
+struct fr_plan {
+    int p, m, nx, ny, nz;
+    int64_t ne;
+    double zeta, nu, T;
+    double J[9], Jinv[9], detJ;
+    int precision;  // FR_F64 / FR_F32
+    int variant;    // FR_FUSED / FR_UNFUSED
+    int block;      // elements per workgroup override (0 = default)
+    int device;
+    // host copies of the operators (double)
+    double x[8], w[8], D[64], lm[8], lp[8], gl[8], gr[8], Dt[64];
+    // device operator blocks
+    void *ops64 = nullptr, *ops32 = nullptr;
+    fr::Consts<double> c64;
+    fr::Consts<float> c32;
+    // scratch
+    fr::Scratch traces;     // [6][ne][7][m^2] of the working precision
+    fr::Scratch unfused;    // stage buffers of the unfused pipeline
+    fr::Scratch rk;         // acc (double), stage (T), k (T)
+    fr::Scratch dual;       // BDF constant part (double, velocity only)
+    fr::Scratch norm;       // partial sums (double)
+    double *norm_host = nullptr;  // pinned host word for the norm read-back
+};
+
+namespace fr {
+
+// error helpers (host)
+int set_error(int code, const char *fmt, ...);
+int check_hip(hipError_t e, const char *what);
+int ensure_scratch(Scratch &s, size_t bytes);
+void free_scratch(Scratch &s);
+
+// launchers (return FR_OK or an error code)
+int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s);
+int launch_residual_unfused(fr_plan *pl, const void *U, void *R, hipStream_t s);
+
+// time integration kernels (timeint.hip)
+int stage_blocks(int64_t n);
+int launch_stage(fr_plan *pl, bool bdf, bool norm, double *U, double *acc, double *st64,
+                 void *stT, const void *k, const double *B, double a, double b, double cnext,
+                 int first, int last, double *partial, hipStream_t s);
+int launch_to_precision(fr_plan *pl, const double *U, void *out, int64_t n, hipStream_t s);
+int launch_bdf_const(fr_plan *pl, const double *Un, const double *Unm1, double dt, double *B,
+                     hipStream_t s);
+int launch_final_sum(const double *partial, int nblocks, double *out, hipStream_t s);
+int launch_extrap(const double *Un, const double *Unm1, const double *Unm2, int order,
+                  double *G, int64_t n, hipStream_t s);
+
+}  // namespace fr

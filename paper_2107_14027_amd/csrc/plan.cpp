@@ -1,0 +1,369 @@
+// Host side of the library: plan construction (1D FR operators and constant
+// geometry, in double precision), option handling, scratch management and
+// error reporting.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "fr_internal.h"
+
+namespace fr {
+
+static thread_local char g_last_error[512] = "";
+
+int set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return FR_OK;
+    return set_error(e == hipErrorOutOfMemory ? FR_ENOMEM : FR_EHIP, "%s: %s", what,
+                     hipGetErrorString(e));
+}
+
+int ensure_scratch(Scratch &s, size_t bytes)
+{
+    if (s.bytes >= bytes && s.ptr) return FR_OK;
+    if (s.ptr) {
+        hipDeviceSynchronize();
+        hipFree(s.ptr);
+        s.ptr = nullptr;
+        s.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&s.ptr, bytes);
+    if (e != hipSuccess) {
+        s.ptr = nullptr;
+        return check_hip(e, "hipMalloc(scratch)");
+    }
+    s.bytes = bytes;
+    return FR_OK;
+}
+
+void free_scratch(Scratch &s)
+{
+    if (s.ptr) hipFree(s.ptr);
+    s.ptr = nullptr;
+    s.bytes = 0;
+}
+
+// --------------------------------------------------------------------------
+// 1D operators (Sec. 2.1).  Built independently of any reference code:
+//  - Gauss-Legendre points by Newton's method on P_m in long double,
+//  - Lagrange derivatives and endpoint values from the barycentric forms,
+//  - DG correction-function derivatives from the lifting identity on Gauss
+//    points: g_R'(x_i) = l_i(1) / w_i, g_L'(x_i) = -l_i(-1) / w_i,
+//  - partially corrected operator Dt = D - g_L l(-1)^T - g_R l(1)^T.
+// --------------------------------------------------------------------------
+struct Ops1D {
+    int m;
+    double x[8], w[8], D[64], lm[8], lp[8], gl[8], gr[8], Dt[64];
+};
+
+static void legendre_ld(int n, long double t, long double &P, long double &dP)
+{
+    long double a = 1.0L, b = t;
+    for (int k = 2; k <= n; ++k) {
+        long double c = ((2 * k - 1) * t * b - (k - 1) * a) / k;
+        a = b;
+        b = c;
+    }
+    P = (n == 0) ? 1.0L : b;
+    // P_n'(t) = n (t P_n - P_{n-1}) / (t^2 - 1); t is never +-1 for interior roots
+    dP = (n == 0) ? 0.0L : n * (t * P - a) / (t * t - 1.0L);
+}
+
+static void build_ops(int p, Ops1D &o)
+{
+    const int m = p + 1;
+    o.m = m;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < m; ++i) {
+        long double t = -cosl(pi * (4 * i + 3) / (4 * m + 2));
+        long double P, dP;
+        for (int it = 0; it < 60; ++it) {
+            legendre_ld(m, t, P, dP);
+            long double dt = P / dP;
+            t -= dt;
+            if (fabsl(dt) < 1e-19L) break;
+        }
+        legendre_ld(m, t, P, dP);
+        o.x[i] = (double)t;
+        o.w[i] = (double)(2.0L / ((1.0L - t * t) * dP * dP));
+    }
+    double lam[8];
+    for (int k = 0; k < m; ++k) {
+        long double s = 1.0L;
+        for (int j = 0; j < m; ++j)
+            if (j != k) s *= (long double)o.x[k] - o.x[j];
+        lam[k] = (double)(1.0L / s);
+    }
+    for (int i = 0; i < m; ++i) {
+        long double diag = 0.0L;
+        for (int k = 0; k < m; ++k) {
+            if (k == i) continue;
+            long double v = ((long double)lam[k] / lam[i]) / ((long double)o.x[i] - o.x[k]);
+            o.D[i * m + k] = (double)v;
+            diag -= v;
+        }
+        o.D[i * m + i] = (double)diag;
+    }
+    for (int side = 0; side < 2; ++side) {
+        long double t = side ? 1.0L : -1.0L, den = 0.0L;
+        for (int k = 0; k < m; ++k) den += (long double)lam[k] / (t - o.x[k]);
+        for (int k = 0; k < m; ++k) {
+            double v = (double)(((long double)lam[k] / (t - o.x[k])) / den);
+            (side ? o.lp : o.lm)[k] = v;
+        }
+    }
+    for (int i = 0; i < m; ++i) {
+        o.gr[i] = o.lp[i] / o.w[i];
+        o.gl[i] = -o.lm[i] / o.w[i];
+    }
+    for (int i = 0; i < m; ++i)
+        for (int k = 0; k < m; ++k)
+            o.Dt[i * m + k] = o.D[i * m + k] - o.gl[i] * o.lm[k] - o.gr[i] * o.lp[k];
+}
+
+template <typename T>
+static void fill_consts(const fr_plan *pl, Consts<T> &c)
+{
+    for (int d = 0; d < 3; ++d) {
+        double s = 0.0;
+        double nv[3];
+        for (int j = 0; j < 3; ++j) {
+            nv[j] = pl->detJ * pl->Jinv[3 * d + j];
+            s += nv[j] * nv[j];
+        }
+        double mag = std::sqrt(s);
+        c.nmag[d] = (T)mag;
+        for (int j = 0; j < 3; ++j) {
+            c.nvec[d][j] = (T)nv[j];
+            c.nhat[d][j] = (T)(nv[j] / mag);
+        }
+    }
+    c.inv_det = (T)(1.0 / pl->detJ);
+    c.zeta = (T)pl->zeta;
+    c.nu = (T)pl->nu;
+    c.invT = (T)(1.0 / pl->T);
+}
+
+template <typename T>
+static void pack_ops(const fr_plan *pl, T *buf)
+{
+    const int m = pl->m;
+    int o = 0;
+    for (int i = 0; i < m * m; ++i) buf[o++] = (T)pl->Dt[i];
+    for (int i = 0; i < m; ++i) buf[o++] = (T)pl->gl[i];
+    for (int i = 0; i < m; ++i) buf[o++] = (T)pl->gr[i];
+    for (int i = 0; i < m; ++i) buf[o++] = (T)pl->lm[i];
+    for (int i = 0; i < m; ++i) buf[o++] = (T)pl->lp[i];
+}
+
+}  // namespace fr
+
+using namespace fr;
+
+extern "C" {
+
+const char *fr_last_error(void) { return g_last_error; }
+
+const char *fr_strerror(int code)
+{
+    switch (code) {
+        case FR_OK: return "ok";
+        case FR_EINVAL: return "invalid argument";
+        case FR_ENOMEM: return "out of memory";
+        case FR_EHIP: return "HIP runtime error";
+        case FR_ENONFINITE: return "non-finite residual";
+        case FR_ENOCONV: return "pseudo-time iteration did not converge";
+        case FR_EUNSUPPORTED: return "unsupported option";
+        default: return "unknown status";
+    }
+}
+
+int fr_plan_operators(int p, double *out)
+{
+    if (p < 1 || p > PMAX || !out) return set_error(FR_EINVAL, "fr_plan_operators: p=%d", p);
+    Ops1D o;
+    build_ops(p, o);
+    const int m = p + 1;
+    double *q = out;
+    for (int i = 0; i < m; ++i) *q++ = o.x[i];
+    for (int i = 0; i < m; ++i) *q++ = o.w[i];
+    for (int i = 0; i < m * m; ++i) *q++ = o.D[i];
+    for (int i = 0; i < m; ++i) *q++ = o.lm[i];
+    for (int i = 0; i < m; ++i) *q++ = o.lp[i];
+    for (int i = 0; i < m; ++i) *q++ = o.gl[i];
+    for (int i = 0; i < m; ++i) *q++ = o.gr[i];
+    for (int i = 0; i < m * m; ++i) *q++ = o.Dt[i];
+    return FR_OK;
+}
+
+fr_plan *fr_plan_create(int p, int nx, int ny, int nz, const double jac[9], double acm_zeta,
+                        const double hd_relax[2])
+{
+    if (p < 1 || p > PMAX) {
+        set_error(FR_EINVAL, "fr_plan_create: order p=%d outside 1..%d", p, PMAX);
+        return nullptr;
+    }
+    if (nx < 1 || ny < 1 || nz < 1 || (int64_t)nx * ny * nz > (int64_t)1 << 31) {
+        set_error(FR_EINVAL, "fr_plan_create: bad lattice %d x %d x %d", nx, ny, nz);
+        return nullptr;
+    }
+    if (!hd_relax || !(acm_zeta > 0.0) || !(hd_relax[0] >= 0.0) || !(hd_relax[1] > 0.0) ||
+        !std::isfinite(acm_zeta) || !std::isfinite(hd_relax[0]) || !std::isfinite(hd_relax[1])) {
+        set_error(FR_EINVAL, "fr_plan_create: need zeta > 0, nu >= 0, T > 0");
+        return nullptr;
+    }
+    fr_plan *pl = new (std::nothrow) fr_plan();
+    if (!pl) {
+        set_error(FR_ENOMEM, "fr_plan_create: host allocation");
+        return nullptr;
+    }
+    pl->p = p;
+    pl->m = p + 1;
+    pl->nx = nx;
+    pl->ny = ny;
+    pl->nz = nz;
+    pl->ne = (int64_t)nx * ny * nz;
+    pl->zeta = acm_zeta;
+    pl->nu = hd_relax[0];
+    pl->T = hd_relax[1];
+    pl->precision = FR_F64;
+    pl->variant = FR_FUSED;
+    pl->block = 0;
+    if (jac) {
+        std::memcpy(pl->J, jac, sizeof pl->J);
+    } else {
+        std::memset(pl->J, 0, sizeof pl->J);
+        pl->J[0] = M_PI / nx;
+        pl->J[4] = M_PI / ny;
+        pl->J[8] = M_PI / nz;
+    }
+    const double *A = pl->J;
+    double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                 A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(det > 0.0) || !std::isfinite(det)) {
+        set_error(FR_EINVAL, "fr_plan_create: Jacobian determinant %g is not positive", det);
+        delete pl;
+        return nullptr;
+    }
+    pl->detJ = det;
+    double *B = pl->Jinv;  // adjugate / det
+    B[0] = (A[4] * A[8] - A[5] * A[7]) / det;
+    B[1] = (A[2] * A[7] - A[1] * A[8]) / det;
+    B[2] = (A[1] * A[5] - A[2] * A[4]) / det;
+    B[3] = (A[5] * A[6] - A[3] * A[8]) / det;
+    B[4] = (A[0] * A[8] - A[2] * A[6]) / det;
+    B[5] = (A[2] * A[3] - A[0] * A[5]) / det;
+    B[6] = (A[3] * A[7] - A[4] * A[6]) / det;
+    B[7] = (A[1] * A[6] - A[0] * A[7]) / det;
+    B[8] = (A[0] * A[4] - A[1] * A[3]) / det;
+
+    Ops1D o;
+    build_ops(p, o);
+    std::memcpy(pl->x, o.x, sizeof o.x);
+    std::memcpy(pl->w, o.w, sizeof o.w);
+    std::memcpy(pl->D, o.D, sizeof o.D);
+    std::memcpy(pl->lm, o.lm, sizeof o.lm);
+    std::memcpy(pl->lp, o.lp, sizeof o.lp);
+    std::memcpy(pl->gl, o.gl, sizeof o.gl);
+    std::memcpy(pl->gr, o.gr, sizeof o.gr);
+    std::memcpy(pl->Dt, o.Dt, sizeof o.Dt);
+    fill_consts(pl, pl->c64);
+    fill_consts(pl, pl->c32);
+
+    if (check_hip(hipGetDevice(&pl->device), "hipGetDevice")) {
+        delete pl;
+        return nullptr;
+    }
+    const int nops = pl->m * pl->m + 4 * pl->m;
+    double h64[128];
+    float h32[128];
+    pack_ops(pl, h64);
+    pack_ops(pl, h32);
+    if (check_hip(hipMalloc(&pl->ops64, nops * sizeof(double)), "hipMalloc(ops64)") ||
+        check_hip(hipMalloc(&pl->ops32, nops * sizeof(float)), "hipMalloc(ops32)") ||
+        check_hip(hipMemcpy(pl->ops64, h64, nops * sizeof(double), hipMemcpyHostToDevice),
+                  "hipMemcpy(ops64)") ||
+        check_hip(hipMemcpy(pl->ops32, h32, nops * sizeof(float), hipMemcpyHostToDevice),
+                  "hipMemcpy(ops32)")) {
+        if (pl->ops64) hipFree(pl->ops64);
+        if (pl->ops32) hipFree(pl->ops32);
+        delete pl;
+        return nullptr;
+    }
+    return pl;
+}
+
+int fr_plan_set_int(fr_plan *pl, int key, int value)
+{
+    if (!pl) return set_error(FR_EINVAL, "fr_plan_set_int: NULL plan");
+    switch (key) {
+        case FR_OPT_PRECISION:
+            if (value != FR_F64 && value != FR_F32)
+                return set_error(FR_EINVAL, "precision %d", value);
+            if (value != pl->precision) {
+                hipDeviceSynchronize();
+                free_scratch(pl->traces);
+                free_scratch(pl->unfused);
+                free_scratch(pl->rk);
+            }
+            pl->precision = value;
+            return FR_OK;
+        case FR_OPT_VARIANT:
+            if (value != FR_FUSED && value != FR_UNFUSED)
+                return set_error(FR_EINVAL, "variant %d", value);
+            pl->variant = value;
+            return FR_OK;
+        case FR_OPT_BLOCK:
+            if (value < 0 || value > 64) return set_error(FR_EINVAL, "block %d", value);
+            pl->block = value;
+            return FR_OK;
+        default:
+            return set_error(FR_EINVAL, "unknown option %d", key);
+    }
+}
+
+int fr_plan_get_int(const fr_plan *pl, int key, int *value)
+{
+    if (!pl || !value) return set_error(FR_EINVAL, "fr_plan_get_int: NULL argument");
+    switch (key) {
+        case FR_OPT_PRECISION: *value = pl->precision; return FR_OK;
+        case FR_OPT_VARIANT: *value = pl->variant; return FR_OK;
+        case FR_OPT_BLOCK: *value = pl->block; return FR_OK;
+        default: return set_error(FR_EINVAL, "unknown option %d", key);
+    }
+}
+
+void fr_plan_destroy(fr_plan *pl)
+{
+    if (!pl) return;
+    hipDeviceSynchronize();
+    free_scratch(pl->traces);
+    free_scratch(pl->unfused);
+    free_scratch(pl->rk);
+    free_scratch(pl->dual);
+    free_scratch(pl->norm);
+    if (pl->norm_host) hipHostFree(pl->norm_host);
+    if (pl->ops64) hipFree(pl->ops64);
+    if (pl->ops32) hipFree(pl->ops32);
+    delete pl;
+}
+
+size_t fr_state_len(const fr_plan *pl)
+{
+    if (!pl) return 0;
+    return (size_t)pl->ne * NV * pl->m * pl->m * pl->m;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+"""GPU parity of the residual (fused and unfused, FP64 and FP32) against the
+CPU oracle, through the C ABI, on seeded inputs: several tiles with a ragged
+tail for every order, general Jacobians, degenerate lattices, run-to-run
+determinism and invariance to the workgroup size."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_14027_amd import binding as B
+from paper_2107_14027_amd import inputs
+from gpu_util import NU, T_CFG, TOL, ZETA, gpu_residual, rel, say
+
+pytestmark = pytest.mark.gpu
+
+SKEW = np.array([[0.30, 0.05, -0.02], [0.01, 0.25, 0.04], [-0.03, 0.02, 0.35]])
+PREC = [B.FR_F64, B.FR_F32]
+VAR = [B.FR_FUSED, B.FR_UNFUSED]
+
+
+def rand_U(p, n, seed):
+    rng = np.random.default_rng(seed)
+    U = 0.3 * rng.standard_normal((n[0] * n[1] * n[2], 13, (p + 1) ** 3))
+    U[:, :4] += np.array([1.0, 0.4, -0.3, 0.2])[None, :, None]
+    return U
+
+
+@pytest.mark.parametrize("prec", PREC)
+@pytest.mark.parametrize("var", VAR)
+def test_config1_tgv_noise(prec, var):
+    """4^3 periodic box, p = 2, Taylor-Green + N(0, 1e-3) noise, zeta = 4."""
+    p, n = 2, (4, 4, 4)
+    U = inputs.tgv(p, n, noise=1e-3, seed=20210729)
+    say("config1 prec=%d var=%d" % (prec, var))
+    R = gpu_residual(p, n, U, precision=prec, variant=var)
+    Ro = oracle.residual(p, n, U, ZETA, NU, T_CFG)
+    assert rel(R, Ro) <= TOL[prec]
+
+
+# lattices sized so that every order spans several workgroups with a ragged tail
+CASES = [(1, (5, 3, 4)), (2, (3, 5, 2)), (3, (3, 2, 5)), (4, (2, 3, 3)), (5, (3, 1, 2)),
+         (6, (1, 2, 3))]
+
+
+@pytest.mark.parametrize("p,n", CASES)
+@pytest.mark.parametrize("prec", PREC)
+@pytest.mark.parametrize("var", VAR)
+@pytest.mark.parametrize("jac", [None, "skew"])
+def test_orders_ragged(p, n, prec, var, jac):
+    J = SKEW if jac == "skew" else None
+    U = rand_U(p, n, seed=100 + p)
+    say("orders p=%d n=%s prec=%d var=%d jac=%s" % (p, n, prec, var, jac))
+    R = gpu_residual(p, n, U, precision=prec, variant=var, jac=J)
+    Ro = oracle.residual(p, n, U, ZETA, NU, T_CFG, J)
+    assert rel(R, Ro) <= TOL[prec], rel(R, Ro)
+
+
+@pytest.mark.parametrize("n", [(1, 1, 1), (1, 2, 1), (2, 1, 1)])
+@pytest.mark.parametrize("prec", PREC)
+def test_degenerate_lattices(n, prec):
+    """An element can be its own neighbour across a periodic face."""
+    p = 3
+    U = rand_U(p, n, seed=7)
+    say("degenerate n=%s prec=%d" % (n, prec))
+    for var in VAR:
+        R = gpu_residual(p, n, U, precision=prec, variant=var)
+        assert rel(R, oracle.residual(p, n, U, ZETA, NU, T_CFG)) <= TOL[prec]
+
+
+def test_free_stream_and_paper_T():
+    """Uniform state gives a zero residual; the paper's own T = 5e-3, zeta = 2.5."""
+    p, n = 4, (3, 2, 2)
+    vals = np.zeros(13)
+    vals[:4] = [1.3, 0.4, -0.7, 0.2]
+    U = inputs.uniform(p, n, vals)
+    say("free stream")
+    R = gpu_residual(p, n, U, zeta=2.5, T=5e-3, jac=SKEW)
+    assert np.max(np.abs(R)) < 1e-12
+    U = inputs.tgv(p, n, noise=1e-3, seed=1)
+    R = gpu_residual(p, n, U, zeta=2.5, T=5e-3)
+    assert rel(R, oracle.residual(p, n, U, 2.5, NU, 5e-3)) <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 3, 5])
+def test_block_size_invariance_and_determinism(p):
+    """FP64 results do not depend on elements per workgroup and repeat bitwise."""
+    n = (4, 3, 3) if p < 5 else (2, 2, 3)
+    U = rand_U(p, n, seed=11)
+    say("block invariance p=%d" % p)
+    ref = gpu_residual(p, n, U)
+    again = gpu_residual(p, n, U)
+    assert np.array_equal(ref, again)
+    for E in (1, 2, 3):
+        assert np.array_equal(gpu_residual(p, n, U, block=E), ref), E
