@@ -1,0 +1,293 @@
+#!/usr/bin/env python3
+"""Throughput of the fused ACM-HD flux-reconstruction residual on one MI355X.
+
+Workload (order sweep): periodic box [0, 2 pi]^3 of 128^3, 85^3, 64^3, 51^3,
+43^3, 40^3 hexahedra for p = 1..6 (16.6-22.0 M solution points each, 13
+unknowns per point), seeded random Fourier velocity/pressure fields (|k| <= 4,
+unit RMS) with exact-gradient auxiliary variables, zeta = 4, nu = 1/1600,
+T = (1/(2 pi))^2 / nu.  One step = one fused double-precision residual
+R = -div F + S at every order, all inputs resident in HBM.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+  value      GDOF/s = sum over orders of ne (p+1)^3 13, divided by the step time
+  roofline   the dominant kernel (largest share of the step), HBM bound:
+             algorithmic bytes per launch / its mean launch time, timed with
+             HIP events on the launch stream inside the timed region
+  sweep      per order: fused vs unfused, FP64 vs FP32 GDOF/s and each kernel's
+             fraction of the 8 TB/s HBM peak
+  cpu_baseline  the serial C oracle on a bounded sample of the same workload
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LATTICE = {1: 128, 2: 85, 3: 64, 4: 51, 5: 43, 6: 40}
+ZETA, NU = 4.0, 1.0 / 1600.0
+TRELAX = (1.0 / (2.0 * 3.141592653589793)) ** 2 / NU
+HBM_PEAK_GBS = 8000.0
+NV = 13
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def fused_bytes(p, ne, esz):
+    """Algorithmic HBM bytes of one fused-kernel launch: read U and write R once
+    (26 values per point) plus the neighbours' face traces (6 faces x 7 values
+    x m^2 points per element)."""
+    m = p + 1
+    return ne * (2 * NV * m ** 3 + 6 * 7 * m * m) * esz
+
+
+def trace_bytes(p, ne, esz):
+    """Face-trace kernel: read U once, write 6 x 7 x m^2 trace values per element."""
+    m = p + 1
+    return ne * (NV * m ** 3 + 6 * 7 * m * m) * esz
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fused.hip", "fr_device.h", "fr_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2107_14027_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_name):
+    """HBM traffic per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % kernel_name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_residual(B, torch, plan, U, R, reps, warm=1):
+    for _ in range(warm):
+        B.fr_residual(plan.handle, U, R)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        B.fr_residual(plan.handle, U, R)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(orders, host_states, budget_s):
+    """Serial C oracle on a sample of elements of each order's lattice."""
+    import numpy as np
+    import oracle
+    tot_dof, tot_t, sample = 0, 0.0, []
+    per = budget_s / len(orders)
+    for p in orders:
+        N = LATTICE[p]
+        n = (N, N, N)
+        U = host_states[p]
+        m = p + 1
+        # calibrate on a few elements, then size the sample to the time budget
+        rng = np.random.default_rng(p)
+        probe = rng.choice(N ** 3, size=64, replace=False)
+        t0 = time.perf_counter()
+        oracle.residual_elems(p, n, U, probe, ZETA, NU, TRELAX)
+        dt = (time.perf_counter() - t0) / 64
+        ns = int(max(64, min(N ** 3, per / max(dt, 1e-7))))
+        sel = rng.choice(N ** 3, size=ns, replace=False)
+        t0 = time.perf_counter()
+        oracle.residual_elems(p, n, U, sel, ZETA, NU, TRELAX)
+        t = time.perf_counter() - t0
+        tot_dof += ns * NV * m ** 3
+        tot_t += t
+        sample.append("p=%d: %d of %d elements" % (p, ns, N ** 3))
+        log("cpu oracle p=%d: %d elements in %.2f s" % (p, ns, t))
+    return tot_dof / tot_t / 1e9, "; ".join(sample)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--orders", default="1,2,3,4,5,6")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the fused/unfused x FP64/FP32 table")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="run a plain device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(the multi-GPU sharding is a design note, not built)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    orders = [int(x) for x in args.orders.split(",")]
+
+    import torch
+    from paper_2107_14027_amd import binding as B
+    from paper_2107_14027_amd import inputs
+    B.lib()
+    dev = "cuda"
+    torch.cuda.init()
+
+    if args.calib_copy_gib > 0:
+        nb = int(args.calib_copy_gib * (1 << 30)) // 8
+        a = torch.ones(nb, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy of %d bytes done" % (nb * 8))
+        del a, b
+
+    work = []
+    for p in orders:
+        N = LATTICE[p]
+        n = (N, N, N)
+        t0 = time.perf_counter()
+        U = inputs.fourier(p, n, seed=1000 + p, device=dev)
+        R = torch.empty_like(U)
+        plan = B.Plan(p, n, ZETA, NU, TRELAX, precision=B.FR_F64, variant=B.FR_FUSED)
+        torch.cuda.synchronize()
+        work.append((p, n, plan, U, R))
+        log("order %d: %d^3 hexes, %.1f M points, inputs in %.1f s" %
+            (p, N, N ** 3 * (p + 1) ** 3 / 1e6, time.perf_counter() - t0))
+
+    dof_step = sum(n[0] * n[1] * n[2] * NV * (p + 1) ** 3 for p, n, *_ in work)
+
+    for _ in range(args.warmup):
+        for p, n, plan, U, R in work:
+            B.fr_residual(plan.handle, U, R)
+    torch.cuda.synchronize()
+    log("warmup done")
+    for p, n, plan, U, R in work:
+        plan.set(B.FR_OPT_PROFILE, 1)
+        B.fr_plan_kernel_stats(plan.handle, 0, reset=True)
+
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        for p, n, plan, U, R in work:
+            B.fr_residual(plan.handle, U, R)
+    e1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    value = dof_step / (ms_step * 1e-3) / 1e9
+    log("timed %d steps: %.3f ms/step, %.1f GDOF/s (wall %.3f s)" % (args.steps, ms_step, value, t_wall))
+
+    kstats = {}
+    for p, n, plan, U, R in work:
+        ne = n[0] * n[1] * n[2]
+        tr_ms, tr_n = B.fr_plan_kernel_stats(plan.handle, 0)
+        fu_ms, fu_n = B.fr_plan_kernel_stats(plan.handle, 1)
+        plan.set(B.FR_OPT_PROFILE, 0)
+        kstats[p] = dict(trace_ms=tr_ms / max(tr_n, 1), fused_ms=fu_ms / max(fu_n, 1),
+                         fused_total=fu_ms, launches=fu_n,
+                         fused_gbs=fused_bytes(p, ne, 8) / (fu_ms / max(fu_n, 1)) / 1e6,
+                         trace_gbs=trace_bytes(p, ne, 8) / (tr_ms / max(tr_n, 1)) / 1e6)
+    pdom = max(kstats, key=lambda p: kstats[p]["fused_total"])
+    Ndom = LATTICE[pdom]
+    dom_bytes = fused_bytes(pdom, Ndom ** 3, 8)
+    achieved = dom_bytes / kstats[pdom]["fused_ms"] / 1e6
+    kname = "k_fused_p%d_f64" % pdom
+    traffic = read_traffic(kname)
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "bytes_per_launch": dom_bytes,
+                "mean_launch_ms": round(kstats[pdom]["fused_ms"], 4)}
+
+    sweep = {}
+    if not args.no_sweep:
+        for p, n, plan, U, R in work:
+            ne = n[0] * n[1] * n[2]
+            dof = ne * NV * (p + 1) ** 3
+            row = {"fused_f64": dof / (kstats[p]["fused_ms"] + kstats[p]["trace_ms"]) / 1e6,
+                   "fused_kernel_f64_hbm_frac": kstats[p]["fused_gbs"] / HBM_PEAK_GBS,
+                   "trace_kernel_f64_hbm_frac": kstats[p]["trace_gbs"] / HBM_PEAK_GBS}
+            pu = B.Plan(p, n, ZETA, NU, TRELAX, precision=B.FR_F64, variant=B.FR_UNFUSED)
+            row["unfused_f64"] = dof / time_residual(B, torch, pu, U, R, 3) / 1e6
+            pu.close()
+            U32 = U.float()
+            R32 = torch.empty_like(U32)
+            for var, key in ((B.FR_FUSED, "fused_f32"), (B.FR_UNFUSED, "unfused_f32")):
+                pf = B.Plan(p, n, ZETA, NU, TRELAX, precision=B.FR_F32, variant=var)
+                pf.set(B.FR_OPT_PROFILE, 1)
+                row[key] = dof / time_residual(B, torch, pf, U32, R32, 3) / 1e6
+                if var == B.FR_FUSED:
+                    fu_ms, fu_n = B.fr_plan_kernel_stats(pf.handle, 1)
+                    row["fused_kernel_f32_hbm_frac"] = (fused_bytes(p, ne, 4) / (fu_ms / fu_n) / 1e6
+                                                        / HBM_PEAK_GBS)
+                pf.close()
+            del U32, R32
+            torch.cuda.empty_cache()
+            row["speedup_fused_vs_unfused_f64"] = row["fused_f64"] / row["unfused_f64"]
+            row["speedup_fused_vs_unfused_f32"] = row["fused_f32"] / row["unfused_f32"]
+            sweep[str(p)] = {k: round(v, 4) for k, v in row.items()}
+            log("sweep p=%d: %s" % (p, sweep[str(p)]))
+
+    cpu = None
+    if not args.no_cpu:
+        import numpy as np
+        host = {}
+        for p, n, plan, U, R in work:
+            host[p] = U.cpu().numpy()
+        val, sample = cpu_baseline(orders, host, args.cpu_seconds)
+        cpu = {"value": round(val, 6), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+               "sample": "serial C oracle residual on randomly chosen elements of the same "
+                         "lattices and fields: " + sample}
+        del host
+
+    out = {
+        "metric": "fused RHS GDOF/s vs plain FP64 (p=1..6); pseudo-iters/step learned vs extrap",
+        "value": round(value, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded random Fourier velocity and pressure (|k|<=4, unit RMS), "
+                "exact-gradient auxiliary variables",
+        "config": {"workload": "order sweep p=%s, fused FP64 ACM-HD FR residual, periodic box "
+                               "[0,2pi]^3, lattices %s hexes" %
+                               (",".join(map(str, orders)),
+                                "/".join("%d^3" % LATTICE[p] for p in orders)),
+                   "orders": orders, "points_per_order": {str(p): LATTICE[p] ** 3 * (p + 1) ** 3
+                                                          for p in orders},
+                   "dof_per_step": dof_step, "zeta": ZETA, "nu": NU, "T": TRELAX,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "sweep": sweep,
+        "kernel_ms": {str(p): {"trace": round(kstats[p]["trace_ms"], 4),
+                               "fused": round(kstats[p]["fused_ms"], 4)} for p in kstats},
+    }
+    print(json.dumps(out), flush=True)
+    for p, n, plan, U, R in work:
+        plan.close()
+
+
+if __name__ == "__main__":
+    main()

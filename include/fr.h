@@ -57,8 +57,23 @@ typedef enum fr_status {
 typedef enum fr_option {
     FR_OPT_PRECISION = 1, /* FR_F64 (default) or FR_F32: working precision of the residual */
     FR_OPT_VARIANT = 2,   /* FR_FUSED (default) or FR_UNFUSED                              */
-    FR_OPT_BLOCK = 3      /* elements per workgroup of the fused kernel; 0 = tuned default  */
+    FR_OPT_BLOCK = 3,     /* elements per workgroup of the fused kernel; 0 = tuned default  */
+    FR_OPT_PROFILE = 4    /* 1: record HIP events around every kernel launch (see below)   */
 } fr_option;
+
+/* Kernel identifiers for fr_plan_kernel_stats. */
+typedef enum fr_kernel {
+    FR_K_TRACE = 0,       /* fused path: face-trace projection (stage 1)                  */
+    FR_K_FUSED = 1,       /* fused path: stages 2-6                                       */
+    FR_K_U_PROJECT = 2,   /* unfused path, Table 1 stage 1                                */
+    FR_K_U_FLUX = 3,      /* stage 2                                                      */
+    FR_K_U_DIV = 4,       /* stage 3                                                      */
+    FR_K_U_COMMON = 5,    /* stage 4                                                      */
+    FR_K_U_CORRECT = 6,   /* stage 5                                                      */
+    FR_K_U_NEGSRC = 7,    /* stage 6                                                      */
+    FR_K_STAGE = 8,       /* RK stage update (time integrators)                           */
+    FR_K_COUNT = 9
+} fr_kernel;
 
 enum { FR_F64 = 0, FR_F32 = 1 };
 enum { FR_FUSED = 0, FR_UNFUSED = 1 };
@@ -142,6 +157,17 @@ int fr_dual_step(fr_plan *plan, double *U, const double *Un, const double *Unm1,
  */
 int fr_guess_extrap(fr_plan *plan, const double *Un, const double *Unm1, const double *Unm2,
                     int order, double *G, fr_stream_t s);
+
+/*
+ * fr_plan_kernel_stats -- with FR_OPT_PROFILE set, every kernel launch of the
+ * plan is bracketed by two HIP events recorded on the launch stream.  This call
+ * waits for the recorded events, adds their elapsed times to per-kernel totals
+ * and returns the totals since the last reset: total_ms (milliseconds) and
+ * launches for the kernel id `kernel` (fr_kernel).  reset != 0 clears the
+ * totals after reading.  Not a compute call: it only reads back timings.
+ */
+int fr_plan_kernel_stats(fr_plan *plan, int kernel, double *total_ms, int64_t *launches,
+                         int reset);
 
 /* Status text, and the description of the last failure on this thread. */
 const char *fr_strerror(int code);

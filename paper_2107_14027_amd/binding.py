@@ -11,14 +11,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfr.so")
 
 FR_OK, FR_EINVAL, FR_ENOMEM, FR_EHIP, FR_ENONFINITE, FR_ENOCONV, FR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-FR_OPT_PRECISION, FR_OPT_VARIANT, FR_OPT_BLOCK = 1, 2, 3
+FR_OPT_PRECISION, FR_OPT_VARIANT, FR_OPT_BLOCK, FR_OPT_PROFILE = 1, 2, 3, 4
+KERNELS = ("trace", "fused", "u_project", "u_flux", "u_div", "u_common", "u_correct",
+           "u_negsrc", "stage")
 FR_F64, FR_F32 = 0, 1
 FR_FUSED, FR_UNFUSED = 0, 1
 NV = 13
 
 EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_destroy",
             "fr_state_len", "fr_residual", "fr_rk_step", "fr_dual_step", "fr_guess_extrap",
-            "fr_strerror", "fr_last_error", "fr_plan_operators")
+            "fr_strerror", "fr_last_error", "fr_plan_operators", "fr_plan_kernel_stats")
 
 
 class FrError(RuntimeError):
@@ -57,8 +59,9 @@ def lib():
         L.fr_last_error.argtypes = []
         L.fr_last_error.restype = ctypes.c_char_p
         L.fr_plan_operators.argtypes = [I, _dp]
+        L.fr_plan_kernel_stats.argtypes = [_vp, I, _dp, ctypes.POINTER(ctypes.c_int64), I]
         for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step",
-                  "fr_dual_step", "fr_guess_extrap", "fr_plan_operators"):
+                  "fr_dual_step", "fr_guess_extrap", "fr_plan_operators", "fr_plan_kernel_stats"):
             getattr(L, n).restype = I
         _lib = L
     return _lib
@@ -162,6 +165,15 @@ def fr_guess_extrap(plan, Un, Unm1, Unm2, order, G, stream=None):
     f = lambda t, nm: None if t is None else _dev(t, torch.float64, n, nm)
     return _check(lib().fr_guess_extrap(plan, f(Un, "Un"), f(Unm1, "Unm1"), f(Unm2, "Unm2"),
                                         int(order), f(G, "G"), _stream(stream)))
+
+
+def fr_plan_kernel_stats(plan, kernel, reset=False):
+    """(total_ms, launches) recorded for a kernel id while FR_OPT_PROFILE was on."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().fr_plan_kernel_stats(plan, int(kernel), ctypes.byref(ms), ctypes.byref(n),
+                                      int(bool(reset))))
+    return ms.value, n.value
 
 
 def fr_plan_operators(p):

@@ -1,0 +1,121 @@
+// Device helpers shared by the residual kernels (fused and unfused paths).
+//
+// Face numbering: f = 2 d + s (d = direction, s = 0 minus / 1 plus side).
+// A face point is (a, b): the two tangential point indices in increasing
+// direction order, flattened a + m b.  Every element has the same
+// orientation, so face point (a, b) of face (d, 1) meets point (a, b) of the
+// neighbour's face (d, 0).
+#pragma once
+
+#include "fr_internal.h"
+
+namespace fr {
+namespace dev {
+
+template <int M>
+__device__ __forceinline__ int qidx(int i, int j, int k) { return i + M * (j + M * k); }
+
+template <int M>
+__device__ __forceinline__ int line_pt(int d, int a, int b, int l)
+{
+    return d == 0 ? qidx<M>(l, a, b) : (d == 1 ? qidx<M>(a, l, b) : qidx<M>(a, b, l));
+}
+
+__device__ __forceinline__ int64_t neighbour(int64_t e, int f, int nx, int ny, int nz)
+{
+    int ex = (int)(e % nx);
+    int64_t r = e / nx;
+    int ey = (int)(r % ny);
+    int ez = (int)(r / ny);
+    const int d = f >> 1, up = f & 1;
+    if (d == 0) ex = up ? (ex + 1 == nx ? 0 : ex + 1) : (ex == 0 ? nx - 1 : ex - 1);
+    else if (d == 1) ey = up ? (ey + 1 == ny ? 0 : ey + 1) : (ey == 0 ? ny - 1 : ey - 1);
+    else ez = up ? (ez + 1 == nz ? 0 : ez + 1) : (ez == 0 ? nz - 1 : ez - 1);
+    return (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
+}
+
+// One face-trace value of one element at face point (a, b) of direction d,
+// using the endpoint basis values lf[] (l(-1) or l(+1)):
+//   c = 0..3   P, u, v, w projected to the face
+//   c = 4..6   (S n_hat)_i projected to the face, S_ik = d u_i / d x_k
+// Written as one explicit fma chain so that every kernel that computes the
+// same trace value produces the same bits.
+template <int M, typename T>
+__device__ __forceinline__ T trace_value(const T *__restrict__ Ue, int d, int a, int b,
+                                         const T *__restrict__ lf, const T nh[3], int c)
+{
+    constexpr int NS = M * M * M;
+    T acc = T(0);
+    if (c < 4) {
+#pragma unroll
+        for (int l = 0; l < M; ++l) acc = fma(lf[l], Ue[c * NS + line_pt<M>(d, a, b, l)], acc);
+    } else {
+        const int i = c - 4;
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            const int q = line_pt<M>(d, a, b, l);
+            T sn = Ue[(4 + 3 * i) * NS + q] * nh[0];
+            sn = fma(Ue[(5 + 3 * i) * NS + q], nh[1], sn);
+            sn = fma(Ue[(6 + 3 * i) * NS + q], nh[2], sn);
+            acc = fma(lf[l], sn, acc);
+        }
+    }
+    return acc;
+}
+
+// Common normal flux through a face of direction d between the state L on the
+// minus side and R on the plus side (normal n_hat_d pointing from L to R),
+// already multiplied by |n_d| (the reference-face scaling).  Outputs:
+//   out[0]     Rusanov dissipation on P: -|n| lambda (P_R - P_L) / 2
+//              (the central part of the P flux, zeta n.V_mean, is carried by
+//               the corrected velocity derivatives)
+//   out[1..3]  momentum common flux
+//   out[4..6]  mean velocity (V_L + V_R) / 2 (the auxiliary equations' mean flux
+//              is -(1/T) n_d,k V_mean_i)
+template <typename T>
+__device__ __forceinline__ void common_flux(const T L[NTR], const T R[NTR], const T nh[3],
+                                            T nmag, T zeta, T nu, T out[NTR])
+{
+    T vnl = L[1] * nh[0];
+    vnl = fma(L[2], nh[1], vnl);
+    vnl = fma(L[3], nh[2], vnl);
+    T vnr = R[1] * nh[0];
+    vnr = fma(R[2], nh[1], vnr);
+    vnr = fma(R[3], nh[2], vnr);
+    const T al = fabs(vnl) + sqrt(fma(vnl, vnl, zeta));
+    const T ar = fabs(vnr) + sqrt(fma(vnr, vnr, zeta));
+    const T lam = al > ar ? al : ar;
+    const T hm = T(0.5) * nmag;
+    out[0] = -hm * lam * (R[0] - L[0]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        T fl = fma(L[1 + i], vnl, fma(L[0], nh[i], -nu * L[4 + i]));
+        T fr = fma(R[1 + i], vnr, fma(R[0], nh[i], -nu * R[4 + i]));
+        out[1 + i] = hm * (fl + fr - lam * (R[1 + i] - L[1 + i]));
+        out[4 + i] = T(0.5) * (L[1 + i] + R[1 + i]);
+    }
+}
+
+// Full 13-variable physical flux dotted with a vector nv (transformed when
+// nv = n_d): out[v] = sum_j F_j,v nv_j.
+template <typename T>
+__device__ __forceinline__ void flux_dot(const T U[NV], const T nv[3], T zeta, T nu, T invT,
+                                         T out[NV])
+{
+    T vn = U[1] * nv[0];
+    vn = fma(U[2], nv[1], vn);
+    vn = fma(U[3], nv[2], vn);
+    out[0] = zeta * vn;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        T sn = U[4 + 3 * i] * nv[0];
+        sn = fma(U[5 + 3 * i], nv[1], sn);
+        sn = fma(U[6 + 3 * i], nv[2], sn);
+        out[1 + i] = fma(U[1 + i], vn, fma(U[0], nv[i], -nu * sn));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[4 + 3 * i + k] = -invT * U[1 + i] * nv[k];
+    }
+}
+
+}  // namespace dev
+}  // namespace fr

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/fr.h"
 
@@ -39,6 +40,11 @@ struct Scratch {
     size_t bytes = 0;
 };
 
+struct ProfRec {
+    int kid;
+    hipEvent_t a, b;
+};
+
 }  // namespace fr
 
 struct fr_plan {
@@ -63,6 +69,11 @@ struct fr_plan {
     fr::Scratch dual;       // BDF constant part (double, velocity only)
     fr::Scratch norm;       // partial sums (double)
     double *norm_host = nullptr;  // pinned host word for the norm read-back
+    // optional per-kernel event timing
+    int profile = 0;
+    std::vector<fr::ProfRec> prof;
+    double prof_ms[FR_K_COUNT] = {};
+    int64_t prof_n[FR_K_COUNT] = {};
 };
 
 namespace fr {
@@ -72,6 +83,17 @@ int set_error(int code, const char *fmt, ...);
 int check_hip(hipError_t e, const char *what);
 int ensure_scratch(Scratch &s, size_t bytes);
 void free_scratch(Scratch &s);
+
+// Brackets one kernel launch with HIP events when the plan profiles.
+struct ProfScope {
+    fr_plan *pl;
+    int kid;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(fr_plan *p, int k, hipStream_t st);
+    ~ProfScope();
+};
+void prof_harvest(fr_plan *pl);
 
 // launchers (return FR_OK or an error code)
 int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s);

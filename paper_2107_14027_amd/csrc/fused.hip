@@ -1,0 +1,450 @@
+// Fused residual kernels for gfx950: R = -div F + S of ACM-HD by flux
+// reconstruction on constant-Jacobian hexahedra (paper Sec. 2.1, 2.2;
+// Table 1 stages 1-6, with the fusion of Sec. 3: stages 2, 3 and 6 in one
+// kernel, and here stages 4 and 5 as well).
+//
+//   k_trace  stage 1 restricted to what the neighbours need: per element and
+//            face, 7 trace values per face point (P, V, (S n_hat)) written to
+//            TR[6][ne][7][m^2].  Reads U once.
+//   k_fused  stages 2-6 for a batch of E elements staged in LDS: transformed
+//            momentum flux at the points, partially corrected divergence along
+//            the three line families, own face traces recomputed on chip,
+//            Rusanov / mean common flux against the neighbour traces,
+//            correction, source.  Reads U and the neighbour traces once,
+//            writes R once.
+//
+// Both kernels loop over element batches (batch b = blockIdx.x + k gridDim.x)
+// and prefetch the next batch's global data into registers before computing
+// the current one, so every workgroup keeps a batch of loads in flight while
+// it works on LDS; the grid is sized to the number of co-resident workgroups.
+#include "fr_device.h"
+
+namespace fr {
+namespace {
+using namespace dev;
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <typename T> struct V16;
+template <> struct V16<double> { using type = d2v; };
+template <> struct V16<float> { using type = f4v; };
+
+// Launch shape per order and precision: EMAX elements per batch (a runtime
+// block size E <= EMAX may be chosen) and NT threads per workgroup.
+template <int P, typename T> struct Shape;
+template <> struct Shape<1, double> { static constexpr int EMAX = 16, NT = 128; };
+template <> struct Shape<2, double> { static constexpr int EMAX = 8, NT = 256; };
+template <> struct Shape<3, double> { static constexpr int EMAX = 4, NT = 256; };
+template <> struct Shape<4, double> { static constexpr int EMAX = 2, NT = 256; };
+template <> struct Shape<5, double> { static constexpr int EMAX = 1, NT = 256; };
+template <> struct Shape<6, double> { static constexpr int EMAX = 1, NT = 384; };
+template <> struct Shape<1, float> { static constexpr int EMAX = 32, NT = 256; };
+template <> struct Shape<2, float> { static constexpr int EMAX = 8, NT = 256; };
+template <> struct Shape<3, float> { static constexpr int EMAX = 4, NT = 256; };
+template <> struct Shape<4, float> { static constexpr int EMAX = 2, NT = 256; };
+template <> struct Shape<5, float> { static constexpr int EMAX = 1, NT = 256; };
+template <> struct Shape<6, float> { static constexpr int EMAX = 1, NT = 384; };
+
+// Register staging of one batch's contiguous state block U[e0 .. e0+nel).
+// Chunk k of W values (W = 16 bytes) belongs to thread k mod NT; a chunk is
+// one 16-byte load when the block start is 16-byte aligned, else W scalars.
+template <typename T, int NVAL, int NT>
+struct StateStage {
+    static constexpr int W = 16 / sizeof(T);
+    static constexpr int PV = (NVAL / W + 1 + NT - 1) / NT;  // chunks per thread
+    T r[PV * W];
+
+    __device__ __forceinline__ void load(const T *__restrict__ src, int count, int tid)
+    {
+        using V = typename V16<T>::type;
+        const bool al = (((uintptr_t)src) & 15) == 0;
+#pragma unroll
+        for (int i = 0; i < PV; ++i) {
+            const int v0 = (tid + i * NT) * W;
+            if (al && v0 + W <= count) {
+                V x = __builtin_nontemporal_load(reinterpret_cast<const V *>(src + v0));
+#pragma unroll
+                for (int w = 0; w < W; ++w) r[i * W + w] = x[w];
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    if (v0 + w < count) r[i * W + w] = src[v0 + w];
+            }
+        }
+    }
+    __device__ __forceinline__ void store(T *__restrict__ dst, int count, int tid) const
+    {
+        using V = typename V16<T>::type;
+#pragma unroll
+        for (int i = 0; i < PV; ++i) {
+            const int v0 = (tid + i * NT) * W;
+            if (v0 + W <= count) {
+                V x;
+#pragma unroll
+                for (int w = 0; w < W; ++w) x[w] = r[i * W + w];
+                *reinterpret_cast<V *>(dst + v0) = x;
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    if (v0 + w < count) dst[v0 + w] = r[i * W + w];
+            }
+        }
+    }
+};
+
+// The thread index, hidden from the optimiser so that index arithmetic derived
+// from it is recomputed inside the batch loop instead of being hoisted out of
+// it and kept live in registers for the whole kernel.
+__device__ __forceinline__ int opaque_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// Neighbour element of every (element, face) of a batch, into an LDS table.
+__device__ __forceinline__ void neighbour_table(int *sNb, int e0, int nel, int nx, int ny, int nz)
+{
+    const int t = threadIdx.x;
+    if (t >= 6 * nel) return;
+    const int el = t / 6, f = t - el * 6;
+    const int e = e0 + el;
+    int ex = e % nx;
+    const int r = e / nx;
+    int ey = r % ny;
+    int ez = r / ny;
+    const int d = f >> 1, up = f & 1;
+    if (d == 0) ex = up ? (ex + 1 == nx ? 0 : ex + 1) : (ex == 0 ? nx - 1 : ex - 1);
+    else if (d == 1) ey = up ? (ey + 1 == ny ? 0 : ey + 1) : (ey == 0 ? ny - 1 : ey - 1);
+    else ez = up ? (ez + 1 == nz ? 0 : ez + 1) : (ez == 0 ? nz - 1 : ez - 1);
+    sNb[t] = ex + nx * (ey + ny * ez);
+}
+
+// ---------------------------------------------------------------------------
+// k_trace
+// ---------------------------------------------------------------------------
+template <int P, typename T>
+__global__ void __launch_bounds__((Shape<P, T>::NT))
+    k_trace(const T *__restrict__ U, T *__restrict__ TR, const T *__restrict__ ops, Consts<T> c,
+            int ne, int E, int nbatch)
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M, CH = NTR * NF;
+    constexpr int EMAX = Shape<P, T>::EMAX, NT = Shape<P, T>::NT;
+    using OL = OpsLayout<M>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sU = reinterpret_cast<T *>(smem_raw);
+    T *sl = sU + EMAX * NV * NS;  // lm[M], lp[M]
+    if (threadIdx.x < 2 * M) sl[threadIdx.x] = ops[OL::lm + threadIdx.x];
+
+    StateStage<T, EMAX * NV * NS, NT> st;
+    int b = blockIdx.x;
+    if (b < nbatch) {
+        const int e0 = b * E;
+        st.load(U + (int64_t)e0 * NV * NS, min(E, ne - e0) * NV * NS, threadIdx.x);
+    }
+    for (; b < nbatch; b += gridDim.x) {
+        const int tid = opaque_tid();
+        const int e0 = b * E;
+        const int nel = min(E, ne - e0);
+        __syncthreads();
+        st.store(sU, nel * NV * NS, tid);
+        const int bn = b + gridDim.x;
+        __syncthreads();
+        if (bn < nbatch) {
+            const int en = bn * E;
+            st.load(U + (int64_t)en * NV * NS, min(E, ne - en) * NV * NS, tid);
+        }
+        // one trace value per thread, in the order of TR[f][e][c][fp] so that
+        // each face's block of the batch is written contiguously
+        for (int t = tid; t < 6 * EMAX * CH; t += NT) {
+            const int f = t / (EMAX * CH), r = t - f * (EMAX * CH);
+            const int el = r / CH, o = r - el * CH;
+            if (el >= nel) continue;
+            const int cc = o / NF, fp = o - cc * NF;
+            const int d = f >> 1, s = f & 1;
+            const T nh[3] = {c.nhat[d][0], c.nhat[d][1], c.nhat[d][2]};
+            const T v = trace_value<M, T>(sU + el * NV * NS, d, fp % M, fp / M, sl + s * M, nh, cc);
+            __builtin_nontemporal_store(v, TR + ((int64_t)f * ne + e0 + el) * CH + o);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_fused
+// LDS: sU[EMAX][13][NS] | sF[EMAX][9][NS] | sFI[EMAX][6][7][NF] | ops | geometry | sNb
+// ---------------------------------------------------------------------------
+template <int P, typename T>
+__global__ void __launch_bounds__((Shape<P, T>::NT))
+    k_fused(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
+            const T *__restrict__ ops, Consts<T> c, int nx, int ny, int nz, int E, int nbatch)
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M, CH = NTR * NF;
+    constexpr int EMAX = Shape<P, T>::EMAX, NT = Shape<P, T>::NT;
+    constexpr int PT = (6 * EMAX * CH + NT - 1) / NT;  // trace values staged per thread
+    using OL = OpsLayout<M>;
+    const int ne = nx * ny * nz;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sU = reinterpret_cast<T *>(smem_raw);
+    T *sF = sU + EMAX * NV * NS;
+    T *sFI = sF + EMAX * 9 * NS;
+    T *sop = sFI + EMAX * 6 * CH;
+    T *geo = sop + OL::size;  // n_d (row d), n_hat_d (row d), |n_d|
+    int *sNb = reinterpret_cast<int *>(geo + 24);
+    for (int t = threadIdx.x; t < OL::size; t += NT) sop[t] = ops[t];
+    if (threadIdx.x < 9) {
+        geo[threadIdx.x] = c.nvec[threadIdx.x / 3][threadIdx.x % 3];
+        geo[9 + threadIdx.x] = c.nhat[threadIdx.x / 3][threadIdx.x % 3];
+    }
+    if (threadIdx.x < 3) geo[18 + threadIdx.x] = c.nmag[threadIdx.x];
+
+    StateStage<T, EMAX * NV * NS, NT> st;
+    T rt[PT];
+    // neighbour traces of a batch: flat index t = (el * 6 + f) * CH + o, the
+    // LDS layout of sFI, loaded from TR[f^1][neighbour(e0 + el, f)][o]
+    auto load_traces = [&](int nel, int tid) {
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const int t = tid + i * NT;
+            const int j = t / CH, o = t - j * CH;
+            if (j < 6 * nel)
+                rt[i] = __builtin_nontemporal_load(
+                    TR + ((int64_t)((j % 6) ^ 1) * ne + sNb[j]) * CH + o);
+        }
+    };
+    auto store_traces = [&](int nel, int tid) {
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const int t = tid + i * NT;
+            if (t < 6 * nel * CH) sFI[t] = rt[i];
+        }
+    };
+
+    int b = blockIdx.x;
+    if (b < nbatch) {
+        const int e0 = b * E, nel = min(E, ne - e0);
+        neighbour_table(sNb, e0, nel, nx, ny, nz);
+        __syncthreads();
+        st.load(U + (int64_t)e0 * NV * NS, nel * NV * NS, threadIdx.x);
+        load_traces(nel, threadIdx.x);
+    }
+    const T *Dt = sop + OL::Dt;
+    const T *gl = sop + OL::gl;
+    const T *gr = sop + OL::gr;
+    for (; b < nbatch; b += gridDim.x) {
+        const int tid = opaque_tid();
+        const int e0 = b * E;
+        const int nel = min(E, ne - e0);
+        __syncthreads();
+        st.store(sU, nel * NV * NS, tid);
+        store_traces(nel, tid);
+        const int bn = b + gridDim.x;
+        const int en = bn * E, neln = bn < nbatch ? min(E, ne - en) : 0;
+        if (neln) neighbour_table(sNb, en, neln, nx, ny, nz);
+        __syncthreads();
+        if (neln) {
+            st.load(U + (int64_t)en * NV * NS, neln * NV * NS, tid);
+            load_traces(neln, tid);
+        }
+
+        // ---- stage 2: transformed momentum flux at every point,
+        //      Fhat_{d,i} = u_i (n_d . V) + P n_d,i - nu sum_j n_d,j S_ij
+        for (int t = tid; t < nel * NS; t += NT) {
+            const int el = t / NS, q = t - el * NS;
+            const T *Ue = sU + el * NV * NS;
+            const T u[3] = {Ue[1 * NS + q], Ue[2 * NS + q], Ue[3 * NS + q]};
+            const T Pq = Ue[q];
+            T S[9];
+#pragma unroll
+            for (int v = 0; v < 9; ++v) S[v] = Ue[(4 + v) * NS + q];
+            T *Fe = sF + el * 9 * NS;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T n0 = c.nvec[d][0], n1 = c.nvec[d][1], n2 = c.nvec[d][2];
+                T vn = u[0] * n0;
+                vn = fma(u[1], n1, vn);
+                vn = fma(u[2], n2, vn);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    T sn = S[3 * i] * n0;
+                    sn = fma(S[3 * i + 1], n1, sn);
+                    sn = fma(S[3 * i + 2], n2, sn);
+                    Fe[(3 * d + i) * NS + q] = fma(u[i], vn, fma(Pq, c.nvec[d][i], -c.nu * sn));
+                }
+            }
+        }
+        // ---- stages 1 + 4 on chip: own trace, common flux with the neighbour
+        //      trace (left state = minus side of the face), result in place
+        for (int t = tid; t < nel * 6 * NF; t += NT) {
+            const int el = t / (6 * NF), r = t - el * (6 * NF);
+            const int f = r / NF, fp = r - f * NF;
+            const int d = f >> 1, s = f & 1;
+            const int a = fp % M, bb = fp / M;
+            const T nh[3] = {geo[9 + 3 * d], geo[10 + 3 * d], geo[11 + 3 * d]};
+            const T *lf = sop + (s ? OL::lp : OL::lm);
+            T own[NTR], oth[NTR], out[NTR];
+#pragma unroll
+            for (int cc = 0; cc < NTR; ++cc) {
+                if (cc >= 4) __builtin_amdgcn_sched_barrier(0);
+                own[cc] = trace_value<M, T>(sU + el * NV * NS, d, a, bb, lf, nh, cc);
+            }
+            T *slot = sFI + ((el * 6 + f) * NTR) * NF + fp;
+#pragma unroll
+            for (int cc = 0; cc < NTR; ++cc) oth[cc] = slot[cc * NF];
+            if (s) common_flux<T>(own, oth, nh, geo[18 + d], c.zeta, c.nu, out);
+            else common_flux<T>(oth, own, nh, geo[18 + d], c.zeta, c.nu, out);
+#pragma unroll
+            for (int cc = 0; cc < NTR; ++cc) slot[cc * NF] = out[cc];
+        }
+        __syncthreads();
+
+        // ---- stages 3, 5, 6: partially corrected divergence along the three
+        //      line families, correction with the common fluxes, negate, source.
+        //      Directions run as a loop (not unrolled) to bound live registers.
+        for (int t = tid; t < nel * NS; t += NT) {
+            const int el = t / NS, q = t - el * NS;
+            const T *Ue = sU + el * NV * NS;
+            const T *Fe = sF + el * 9 * NS;
+            const T *FIe = sFI + el * 6 * CH;
+            // g[3a+k] = sum_d n_d,k (corrected d u_a / d xi_d) = det J d u_a / d x_k
+            T g[9], mom[3] = {T(0), T(0), T(0)}, dissP = T(0);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) g[k] = T(0);
+#pragma unroll 1
+            for (int d = 0; d < 3; ++d) {
+                const int str = d == 0 ? 1 : (d == 1 ? M : M * M);
+                const int id = (q / str) % M;
+                const int base = q - id * str;
+                const int fp = d == 0 ? q / M : (d == 1 ? (q % M) + M * (q / (M * M)) : q % (M * M));
+                const T *FIm = FIe + (2 * d) * CH + fp;
+                const T *FIp = FIe + (2 * d + 1) * CH + fp;
+                const T gld = gl[id], grd = gr[id];
+                const T *Fd = Fe + 3 * d * NS;
+                T du[3] = {T(0), T(0), T(0)}, df[3] = {T(0), T(0), T(0)};
+#pragma unroll
+                for (int l = 0; l < M; ++l) {
+                    const int ql = base + l * str;
+                    const T w = Dt[id * M + l];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        du[a] = fma(w, Ue[(1 + a) * NS + ql], du[a]);
+                        df[a] = fma(w, Fd[a * NS + ql], df[a]);
+                    }
+                }
+                const T n0 = geo[3 * d], n1 = geo[3 * d + 1], n2 = geo[3 * d + 2];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const T cd = fma(gld, FIm[(4 + a) * NF], fma(grd, FIp[(4 + a) * NF], du[a]));
+                    mom[a] += fma(gld, FIm[(1 + a) * NF], fma(grd, FIp[(1 + a) * NF], df[a]));
+                    g[3 * a] = fma(cd, n0, g[3 * a]);
+                    g[3 * a + 1] = fma(cd, n1, g[3 * a + 1]);
+                    g[3 * a + 2] = fma(cd, n2, g[3 * a + 2]);
+                }
+                dissP = fma(gld, FIm[0], fma(grd, FIp[0], dissP));
+            }
+            T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
+            // P: -(1/detJ) [ zeta (det J div V) + dissipation ]
+            const T divV = g[0] + g[4] + g[8];
+            __builtin_nontemporal_store(-c.inv_det * fma(c.zeta, divV, dissP), Re);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) __builtin_nontemporal_store(-c.inv_det * mom[a], Re + (1 + a) * NS);
+            // aux (a, k): (1/T) [ d u_a / d x_k - S_ak ]
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                __builtin_nontemporal_store(c.invT * fma(c.inv_det, g[k], -Ue[(4 + k) * NS + q]),
+                                            Re + (4 + k) * NS);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch
+// ---------------------------------------------------------------------------
+template <int P, typename T>
+int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<T> &c,
+               hipStream_t s)
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    constexpr int EMAX = Shape<P, T>::EMAX, NT = Shape<P, T>::NT;
+    const int ne = (int)pl->ne;
+    int E = pl->block ? pl->block : EMAX;
+    if (E > EMAX)
+        return set_error(FR_EINVAL, "fused kernel: block %d exceeds %d elements at p=%d", E, EMAX, P);
+    if (E > ne) E = ne;
+    const int nbatch = (ne + E - 1) / E;
+    const size_t lds_tr = ((size_t)EMAX * NV * NS + 2 * M) * sizeof(T);
+    const size_t lds_fu = ((size_t)EMAX * (NV + 9) * NS + (size_t)EMAX * 6 * NTR * NF +
+                           OpsLayout<M>::size + 24) * sizeof(T) + 6 * EMAX * sizeof(int);
+    static int grid_tr = 0, grid_fu = 0;
+    if (!grid_tr) {
+        int dev = 0, ncu = 0, occ_tr = 0, occ_fu = 0;
+        if (int rc = check_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
+        if (int rc = check_hip(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev),
+                               "hipDeviceGetAttribute"))
+            return rc;
+        if (int rc = check_hip(hipFuncSetAttribute((const void *)k_trace<P, T>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)lds_tr), "hipFuncSetAttribute(k_trace)"))
+            return rc;
+        if (int rc = check_hip(hipFuncSetAttribute((const void *)k_fused<P, T>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)lds_fu), "hipFuncSetAttribute(k_fused)"))
+            return rc;
+        if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                   &occ_tr, (const void *)k_trace<P, T>, NT, lds_tr),
+                               "occupancy(k_trace)"))
+            return rc;
+        if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                   &occ_fu, (const void *)k_fused<P, T>, NT, lds_fu),
+                               "occupancy(k_fused)"))
+            return rc;
+        if (occ_tr < 1 || occ_fu < 1)
+            return set_error(FR_EUNSUPPORTED, "fused kernels do not fit on a CU at p=%d", P);
+        grid_tr = ncu * occ_tr;
+        grid_fu = ncu * occ_fu;
+    }
+    const unsigned gtr = (unsigned)min(nbatch, grid_tr);
+    const unsigned gfu = (unsigned)min(nbatch, grid_fu);
+    {
+        ProfScope ps(pl, FR_K_TRACE, s);
+        hipLaunchKernelGGL((k_trace<P, T>), dim3(gtr), dim3(NT), lds_tr, s, U, TR, ops, c, ne, E,
+                           nbatch);
+    }
+    {
+        ProfScope ps(pl, FR_K_FUSED, s);
+        hipLaunchKernelGGL((k_fused<P, T>), dim3(gfu), dim3(NT), lds_fu, s, U, TR, R, ops, c,
+                           pl->nx, pl->ny, pl->nz, E, nbatch);
+    }
+    return check_hip(hipGetLastError(), "fused residual launch");
+}
+
+template <typename T>
+int dispatch_fused(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<T> &c,
+                   hipStream_t s)
+{
+    switch (pl->p) {
+        case 1: return fused_impl<1, T>(pl, U, R, TR, ops, c, s);
+        case 2: return fused_impl<2, T>(pl, U, R, TR, ops, c, s);
+        case 3: return fused_impl<3, T>(pl, U, R, TR, ops, c, s);
+        case 4: return fused_impl<4, T>(pl, U, R, TR, ops, c, s);
+        case 5: return fused_impl<5, T>(pl, U, R, TR, ops, c, s);
+        case 6: return fused_impl<6, T>(pl, U, R, TR, ops, c, s);
+    }
+    return set_error(FR_EINVAL, "order %d", pl->p);
+}
+
+}  // namespace
+
+int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s)
+{
+    const int m = pl->m;
+    const size_t esz = pl->precision == FR_F64 ? 8 : 4;
+    const size_t tr_bytes = (size_t)6 * pl->ne * NTR * m * m * esz;
+    if (int rc = ensure_scratch(pl->traces, tr_bytes)) return rc;
+    if (pl->precision == FR_F64)
+        return dispatch_fused<double>(pl, (const double *)U, (double *)R, (double *)pl->traces.ptr,
+                                      (const double *)pl->ops64, pl->c64, s);
+    return dispatch_fused<float>(pl, (const float *)U, (float *)R, (float *)pl->traces.ptr,
+                                 (const float *)pl->ops32, pl->c32, s);
+}
+
+}  // namespace fr

@@ -168,6 +168,39 @@ static void pack_ops(const fr_plan *pl, T *buf)
     for (int i = 0; i < m; ++i) buf[o++] = (T)pl->lp[i];
 }
 
+ProfScope::ProfScope(fr_plan *p, int k, hipStream_t st) : pl(p), kid(k), s(st)
+{
+    if (pl && pl->profile && hipEventCreate(&a) == hipSuccess) hipEventRecord(a, s);
+}
+
+ProfScope::~ProfScope()
+{
+    if (!a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) {
+        hipEventDestroy(a);
+        return;
+    }
+    hipEventRecord(b, s);
+    pl->prof.push_back({kid, a, b});
+    if (pl->prof.size() > 8192) prof_harvest(pl);
+}
+
+void prof_harvest(fr_plan *pl)
+{
+    for (auto &r : pl->prof) {
+        float ms = 0.f;
+        hipEventSynchronize(r.b);
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            pl->prof_ms[r.kid] += ms;
+            pl->prof_n[r.kid] += 1;
+        }
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    pl->prof.clear();
+}
+
 }  // namespace fr
 
 using namespace fr;
@@ -329,6 +362,10 @@ int fr_plan_set_int(fr_plan *pl, int key, int value)
             if (value < 0 || value > 64) return set_error(FR_EINVAL, "block %d", value);
             pl->block = value;
             return FR_OK;
+        case FR_OPT_PROFILE:
+            if (value != 0 && value != 1) return set_error(FR_EINVAL, "profile %d", value);
+            pl->profile = value;
+            return FR_OK;
         default:
             return set_error(FR_EINVAL, "unknown option %d", key);
     }
@@ -341,14 +378,31 @@ int fr_plan_get_int(const fr_plan *pl, int key, int *value)
         case FR_OPT_PRECISION: *value = pl->precision; return FR_OK;
         case FR_OPT_VARIANT: *value = pl->variant; return FR_OK;
         case FR_OPT_BLOCK: *value = pl->block; return FR_OK;
+        case FR_OPT_PROFILE: *value = pl->profile; return FR_OK;
         default: return set_error(FR_EINVAL, "unknown option %d", key);
     }
+}
+
+int fr_plan_kernel_stats(fr_plan *pl, int kernel, double *total_ms, int64_t *launches, int reset)
+{
+    if (!pl || !total_ms || !launches || kernel < 0 || kernel >= FR_K_COUNT)
+        return set_error(FR_EINVAL, "fr_plan_kernel_stats: bad argument");
+    prof_harvest(pl);
+    *total_ms = pl->prof_ms[kernel];
+    *launches = pl->prof_n[kernel];
+    if (reset)
+        for (int k = 0; k < FR_K_COUNT; ++k) {
+            pl->prof_ms[k] = 0.0;
+            pl->prof_n[k] = 0;
+        }
+    return FR_OK;
 }
 
 void fr_plan_destroy(fr_plan *pl)
 {
     if (!pl) return;
     hipDeviceSynchronize();
+    prof_harvest(pl);
     free_scratch(pl->traces);
     free_scratch(pl->unfused);
     free_scratch(pl->rk);

@@ -156,6 +156,7 @@ int launch_stage(fr_plan *pl, bool bdf, bool norm, double *U, double *acc, doubl
 {
     const int64_t n = (int64_t)fr_state_len(pl);
     const int ns = pl->m * pl->m * pl->m;
+    ProfScope ps(pl, FR_K_STAGE, s);
     if (pl->precision == FR_F64)
         return stage_dispatch<double>(bdf, norm, U, acc, st64, stT, k, B, a, b, cnext, first, last,
                                       n, ns, partial, s);

@@ -96,51 +96,64 @@ def _wavevectors(kmax):
     return K[(k2 > 0) & (k2 <= kmax * kmax)]
 
 
-def fourier(p, n, seed, kmax=4):
+def fourier(p, n, seed, kmax=4, device=None):
     """Random smooth periodic field on the box [0, 2 pi]^3 (axis-aligned lattice).
 
     Each of P, u, v, w is sum_k a_k cos(k.x) + b_k sin(k.x) over integer k with
     0 < |k|_2 <= kmax, a, b ~ N(0, 1), scaled to unit RMS over the solution
     points; the aux variables are the exact velocity gradients.  Evaluated
-    separably along the three axes so that 10^7-point lattices take seconds."""
+    separably along the three axes.  With device (a torch device string) the
+    same coefficients are synthesised with torch on that device and a float64
+    torch tensor is returned; otherwise a numpy array."""
     nx, ny, nz = n
     m = p + 1
     rng = np.random.default_rng(seed)
     K = _wavevectors(kmax)
     xi, _ = nodes(p)
-    # 1D coordinates along each axis: [n_d * m], index = e_d * m + i_d
     ax = [np.pi / nd * (xi[None, :] + 1.0 + 2.0 * np.arange(nd)[:, None]).ravel()
           for nd in (nx, ny, nz)]
     ks = np.arange(-kmax, kmax + 1)
     E = [np.exp(1j * ks[:, None] * a[None, :]) for a in ax]       # [2kmax+1][n_d m]
+    if device is not None:
+        import torch
+        lib = torch
+        E = [torch.from_numpy(e).to(device) for e in E]
+        asarr = lambda a: torch.from_numpy(a).to(device)
+        out = torch.empty((nx * ny * nz, NV, m ** 3), dtype=torch.float64, device=device)
+        meansq = lambda v: float(torch.mean(v * v))
+    else:
+        lib = np
+        asarr = lambda a: a
+        out = np.empty((nx * ny * nz, NV, m ** 3))
+        meansq = lambda v: float(np.mean(v * v))
 
     def synth(coef):
         # coef: complex [2kmax+1]^3 spectrum; field = Re sum c e^{i k.x}
-        t = np.einsum("abc,cz->abz", coef, E[2])
-        t = np.einsum("abz,by->ayz", t, E[1])
-        t = np.einsum("ayz,ax->zyx", t, E[0])
+        t = lib.einsum("abc,cz->abz", coef, E[2])
+        t = lib.einsum("abz,by->ayz", t, E[1])
+        t = lib.einsum("ayz,ax->zyx", t, E[0])
         return t.real                                            # [Z][Y][X]
 
     def to_layout(F):
         F = F.reshape(nz, m, ny, m, nx, m)                        # [ez][k][ey][j][ex][i]
-        return F.transpose(0, 2, 4, 1, 3, 5).reshape(nx * ny * nz, m ** 3)
+        return F.permute(0, 2, 4, 1, 3, 5).reshape(nx * ny * nz, m ** 3) if device is not None \
+            else F.transpose(0, 2, 4, 1, 3, 5).reshape(nx * ny * nz, m ** 3)
 
-    out = np.empty((nx * ny * nz, NV, m ** 3))
+    idx = tuple((K + kmax).T)
     for f in range(4):
         a = rng.standard_normal(len(K))
         b = rng.standard_normal(len(K))
         coef = np.zeros((2 * kmax + 1,) * 3, dtype=np.complex128)
-        idx = tuple((K + kmax).T)
         # a cos + b sin = Re[(a - i b) e^{i k.x}]
         np.add.at(coef, idx, a - 1j * b)
-        val = synth(coef)
-        scale = 1.0 / np.sqrt(np.mean(val ** 2))
+        val = synth(asarr(coef))
+        scale = 1.0 / np.sqrt(meansq(val))
         out[:, f] = to_layout(val) * scale
         if f >= 1:
             for kdir in range(3):
                 dc = np.zeros_like(coef)
                 np.add.at(dc, idx, 1j * K[:, kdir] * (a - 1j * b))
-                out[:, 4 + 3 * (f - 1) + kdir] = to_layout(synth(dc)) * scale
+                out[:, 4 + 3 * (f - 1) + kdir] = to_layout(synth(asarr(dc))) * scale
     return out
 
 

@@ -89,5 +89,9 @@ def test_block_size_invariance_and_determinism(p):
     ref = gpu_residual(p, n, U)
     again = gpu_residual(p, n, U)
     assert np.array_equal(ref, again)
+    emax = {1: 16, 2: 8, 3: 4, 4: 2, 5: 1, 6: 1}[p]   # largest batch the kernels accept
     for E in (1, 2, 3):
-        assert np.array_equal(gpu_residual(p, n, U, block=E), ref), E
+        if E <= emax:
+            assert np.array_equal(gpu_residual(p, n, U, block=E), ref), E
+    with pytest.raises(B.FrError):
+        gpu_residual(p, n, U, block=emax + 1)
