@@ -78,6 +78,30 @@ def read_traffic(kernel_name):
         return None
 
 
+def hbm_reference(torch, gib=2.0, reps=20):
+    """Measured device bandwidth of plain torch copy (read+write), fill (write) and
+    sum (read) over a `gib` GiB array: the practical ceilings for HBM streams."""
+    n = int(gib * (1 << 30)) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 16 * n), ("fill", lambda: x.fill_(2.0), 8 * n),
+                             ("read", lambda: x.sum(), 8 * n)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_gbs"] = round(nbytes / (e0.elapsed_time(e1) / reps) / 1e6, 1)
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_residual(B, torch, plan, U, R, reps, warm=1):
     for _ in range(warm):
         B.fr_residual(plan.handle, U, R)
@@ -129,6 +153,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the fused/unfused x FP64/FP32 table")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-hbm-ref", action="store_true", help="skip the copy/fill/read reference")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -153,6 +178,10 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy of %d bytes done" % (nb * 8))
         del a, b
+
+    hbm_ref = None if args.no_hbm_ref else hbm_reference(torch)
+    if hbm_ref:
+        log("reference bandwidth: %s" % hbm_ref)
 
     work = []
     for p in orders:
@@ -213,7 +242,9 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "bytes_per_launch": dom_bytes,
-                "mean_launch_ms": round(kstats[pdom]["fused_ms"], 4)}
+                "mean_launch_ms": round(kstats[pdom]["fused_ms"], 4),
+                "measured_reference_gbs": hbm_ref,
+                "frac_of_measured_copy": (round(achieved / hbm_ref["copy_gbs"], 4) if hbm_ref else None)}
 
     sweep = {}
     if not args.no_sweep:

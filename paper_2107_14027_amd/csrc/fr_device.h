@@ -34,29 +34,48 @@ __device__ __forceinline__ int64_t neighbour(int64_t e, int f, int nx, int ny, i
     return (int64_t)ex + (int64_t)nx * ((int64_t)ey + (int64_t)ny * ez);
 }
 
-// One face-trace value of one element at face point (a, b) of direction d,
-// using the endpoint basis values lf[] (l(-1) or l(+1)):
+// First point and point stride of the direction-d line through face point (a, b).
+template <int M>
+__device__ __forceinline__ void line_of(int d, int a, int b, int &base, int &stride)
+{
+    stride = d == 0 ? 1 : (d == 1 ? M : M * M);
+    base = d == 0 ? M * (a + M * b) : (d == 1 ? a + M * M * b : a + M * b);
+}
+
+// One face-trace value of one element along the line (base, stride), using the
+// endpoint basis values lf[] (l(-1) or l(+1)):
 //   c = 0..3   P, u, v, w projected to the face
 //   c = 4..6   (S n_hat)_i projected to the face, S_ik = d u_i / d x_k
 // Written as one explicit fma chain so that every kernel that computes the
 // same trace value produces the same bits.
+//
+// With diag (the reference-face normals are the coordinate axes: a diagonal
+// Jacobian) (S n_hat)_i = S_id exactly, and the product with the unit normal is
+// skipped; the result has the same bits as the general expression, whose other
+// terms are exact zeros and whose product with 1 is exact.
 template <int M, typename T>
-__device__ __forceinline__ T trace_value(const T *__restrict__ Ue, int d, int a, int b,
-                                         const T *__restrict__ lf, const T nh[3], int c)
+__device__ __forceinline__ T trace_value(const T *__restrict__ Ue, int d, int base, int stride,
+                                         const T *__restrict__ lf, const T nh[3], int c,
+                                         bool diag = false)
 {
     constexpr int NS = M * M * M;
     T acc = T(0);
     if (c < 4) {
+        const T *X = Ue + c * NS + base;
 #pragma unroll
-        for (int l = 0; l < M; ++l) acc = fma(lf[l], Ue[c * NS + line_pt<M>(d, a, b, l)], acc);
+        for (int l = 0; l < M; ++l) acc = fma(lf[l], X[l * stride], acc);
+    } else if (diag) {
+        const T *X = Ue + (4 + 3 * (c - 4) + d) * NS + base;
+#pragma unroll
+        for (int l = 0; l < M; ++l) acc = fma(lf[l], X[l * stride], acc);
     } else {
-        const int i = c - 4;
+        const T *X = Ue + (4 + 3 * (c - 4)) * NS + base;
 #pragma unroll
         for (int l = 0; l < M; ++l) {
-            const int q = line_pt<M>(d, a, b, l);
-            T sn = Ue[(4 + 3 * i) * NS + q] * nh[0];
-            sn = fma(Ue[(5 + 3 * i) * NS + q], nh[1], sn);
-            sn = fma(Ue[(6 + 3 * i) * NS + q], nh[2], sn);
+            const int q = l * stride;
+            T sn = X[q] * nh[0];
+            sn = fma(X[NS + q], nh[1], sn);
+            sn = fma(X[2 * NS + q], nh[2], sn);
             acc = fma(lf[l], sn, acc);
         }
     }
@@ -82,9 +101,11 @@ __device__ __forceinline__ void common_flux(const T L[NTR], const T R[NTR], cons
     T vnr = R[1] * nh[0];
     vnr = fma(R[2], nh[1], vnr);
     vnr = fma(R[3], nh[2], vnr);
-    const T al = fabs(vnl) + sqrt(fma(vnl, vnl, zeta));
-    const T ar = fabs(vnr) + sqrt(fma(vnr, vnr, zeta));
-    const T lam = al > ar ? al : ar;
+    // lambda = max over both sides of |v| + sqrt(v^2 + zeta); the expression is
+    // monotone in |v| (also after rounding), so it is evaluated once at the
+    // larger |v|, with the same bits as the maximum of the two evaluations.
+    const T vm = fmax(fabs(vnl), fabs(vnr));
+    const T lam = vm + sqrt(fma(vm, vm, zeta));
     const T hm = T(0.5) * nmag;
     out[0] = -hm * lam * (R[0] - L[0]);
 #pragma unroll

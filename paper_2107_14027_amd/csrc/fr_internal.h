@@ -23,6 +23,7 @@ struct Consts {
     T nhat[3][3];  // n_d / |n_d|
     T inv_det;     // 1 / det(J)
     T zeta, nu, invT;
+    int diag;      // 1 when J is diagonal: n_hat_d = e_d exactly
 };
 
 // Operator block in device memory, precision T, for order p (m = p + 1):

@@ -46,48 +46,62 @@ template <> struct Shape<5, float> { static constexpr int EMAX = 1, NT = 256; };
 template <> struct Shape<6, float> { static constexpr int EMAX = 1, NT = 384; };
 
 // Register staging of one batch's contiguous state block U[e0 .. e0+nel).
-// Chunk k of W values (W = 16 bytes) belongs to thread k mod NT; a chunk is
-// one 16-byte load when the block start is 16-byte aligned, else W scalars.
+// Chunk k of W values (W = 16 bytes) belongs to thread k mod NT.  A full batch
+// (count == NVAL) whose start is 16-byte aligned takes a branch-free path with
+// one 16-byte access per chunk; other batches check every value.
 template <typename T, int NVAL, int NT>
 struct StateStage {
     static constexpr int W = 16 / sizeof(T);
-    static constexpr int PV = (NVAL / W + 1 + NT - 1) / NT;  // chunks per thread
+    static constexpr int NCH = (NVAL + W - 1) / W;   // chunks in a full batch
+    static constexpr int PV = (NCH + NT - 1) / NT;   // chunks per thread
+    static constexpr bool EXACT = NVAL % W == 0;
     T r[PV * W];
 
     __device__ __forceinline__ void load(const T *__restrict__ src, int count, int tid)
     {
         using V = typename V16<T>::type;
-        const bool al = (((uintptr_t)src) & 15) == 0;
+        if (EXACT && count == NVAL && (((uintptr_t)src) & 15) == 0) {
+#pragma unroll
+            for (int i = 0; i < PV; ++i) {
+                const int k = tid + i * NT;
+                if ((i + 1) * NT <= NCH || k < NCH) {
+                    V x = __builtin_nontemporal_load(reinterpret_cast<const V *>(src) + k);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) r[i * W + w] = x[w];
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < PV; ++i) {
             const int v0 = (tid + i * NT) * W;
-            if (al && v0 + W <= count) {
-                V x = __builtin_nontemporal_load(reinterpret_cast<const V *>(src + v0));
 #pragma unroll
-                for (int w = 0; w < W; ++w) r[i * W + w] = x[w];
-            } else {
-#pragma unroll
-                for (int w = 0; w < W; ++w)
-                    if (v0 + w < count) r[i * W + w] = src[v0 + w];
-            }
+            for (int w = 0; w < W; ++w)
+                if (v0 + w < count) r[i * W + w] = src[v0 + w];
         }
     }
     __device__ __forceinline__ void store(T *__restrict__ dst, int count, int tid) const
     {
         using V = typename V16<T>::type;
+        if (EXACT && count == NVAL) {
+#pragma unroll
+            for (int i = 0; i < PV; ++i) {
+                const int k = tid + i * NT;
+                if ((i + 1) * NT <= NCH || k < NCH) {
+                    V x;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) x[w] = r[i * W + w];
+                    reinterpret_cast<V *>(dst)[k] = x;
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < PV; ++i) {
             const int v0 = (tid + i * NT) * W;
-            if (v0 + W <= count) {
-                V x;
 #pragma unroll
-                for (int w = 0; w < W; ++w) x[w] = r[i * W + w];
-                *reinterpret_cast<V *>(dst + v0) = x;
-            } else {
-#pragma unroll
-                for (int w = 0; w < W; ++w)
-                    if (v0 + w < count) dst[v0 + w] = r[i * W + w];
-            }
+            for (int w = 0; w < W; ++w)
+                if (v0 + w < count) dst[v0 + w] = r[i * W + w];
         }
     }
 };
@@ -163,7 +177,9 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
             const int cc = o / NF, fp = o - cc * NF;
             const int d = f >> 1, s = f & 1;
             const T nh[3] = {c.nhat[d][0], c.nhat[d][1], c.nhat[d][2]};
-            const T v = trace_value<M, T>(sU + el * NV * NS, d, fp % M, fp / M, sl + s * M, nh, cc);
+            int base, stride;
+            line_of<M>(d, fp % M, fp / M, base, stride);
+            const T v = trace_value<M, T>(sU + el * NV * NS, d, base, stride, sl + s * M, nh, cc, c.diag);
             __builtin_nontemporal_store(v, TR + ((int64_t)f * ne + e0 + el) * CH + o);
         }
     }
@@ -201,21 +217,25 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
     T rt[PT];
     // neighbour traces of a batch: flat index t = (el * 6 + f) * CH + o, the
     // LDS layout of sFI, loaded from TR[f^1][neighbour(e0 + el, f)][o]
+    constexpr int NTV = 6 * EMAX * CH;                  // trace values of a full batch
     auto load_traces = [&](int nel, int tid) {
+        const int lim = nel == EMAX ? NTV : 6 * nel * CH;
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
             const int t = tid + i * NT;
-            const int j = t / CH, o = t - j * CH;
-            if (j < 6 * nel)
+            if ((nel == EMAX && (i + 1) * NT <= NTV) || t < lim) {
+                const int j = t / CH, o = t - j * CH;
                 rt[i] = __builtin_nontemporal_load(
                     TR + ((int64_t)((j % 6) ^ 1) * ne + sNb[j]) * CH + o);
+            }
         }
     };
     auto store_traces = [&](int nel, int tid) {
+        const int lim = nel == EMAX ? NTV : 6 * nel * CH;
 #pragma unroll
         for (int i = 0; i < PT; ++i) {
             const int t = tid + i * NT;
-            if (t < 6 * nel * CH) sFI[t] = rt[i];
+            if ((nel == EMAX && (i + 1) * NT <= NTV) || t < lim) sFI[t] = rt[i];
         }
     };
 
@@ -273,25 +293,32 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
             }
         }
         // ---- stages 1 + 4 on chip: own trace, common flux with the neighbour
-        //      trace (left state = minus side of the face), result in place
-        for (int t = tid; t < nel * 6 * NF; t += NT) {
-            const int el = t / (6 * NF), r = t - el * (6 * NF);
-            const int f = r / NF, fp = r - f * NF;
-            const int d = f >> 1, s = f & 1;
-            const int a = fp % M, bb = fp / M;
+        //      trace (left state = minus side of the face), result in place.
+        //      Face points are ordered (d, el, side, fp) so that the lanes of a
+        //      wave share a direction; the side only swaps operands (no branch).
+        for (int t = tid; t < 3 * EMAX * 2 * NF; t += NT) {
+            const int d = t / (EMAX * 2 * NF), r = t - d * (EMAX * 2 * NF);
+            const int el = r / (2 * NF), r2 = r - el * (2 * NF);
+            if (el >= nel) continue;
+            const int s = r2 / NF, fp = r2 - s * NF;
+            int base, stride;
+            line_of<M>(d, fp % M, fp / M, base, stride);
             const T nh[3] = {geo[9 + 3 * d], geo[10 + 3 * d], geo[11 + 3 * d]};
             const T *lf = sop + (s ? OL::lp : OL::lm);
-            T own[NTR], oth[NTR], out[NTR];
+            T own[NTR], oth[NTR], L[NTR], Rr[NTR], out[NTR];
 #pragma unroll
             for (int cc = 0; cc < NTR; ++cc) {
                 if (cc >= 4) __builtin_amdgcn_sched_barrier(0);
-                own[cc] = trace_value<M, T>(sU + el * NV * NS, d, a, bb, lf, nh, cc);
+                own[cc] = trace_value<M, T>(sU + el * NV * NS, d, base, stride, lf, nh, cc, c.diag);
             }
-            T *slot = sFI + ((el * 6 + f) * NTR) * NF + fp;
+            T *slot = sFI + ((el * 6 + 2 * d + s) * NTR) * NF + fp;
 #pragma unroll
-            for (int cc = 0; cc < NTR; ++cc) oth[cc] = slot[cc * NF];
-            if (s) common_flux<T>(own, oth, nh, geo[18 + d], c.zeta, c.nu, out);
-            else common_flux<T>(oth, own, nh, geo[18 + d], c.zeta, c.nu, out);
+            for (int cc = 0; cc < NTR; ++cc) {
+                oth[cc] = slot[cc * NF];
+                L[cc] = s ? own[cc] : oth[cc];
+                Rr[cc] = s ? oth[cc] : own[cc];
+            }
+            common_flux<T>(L, Rr, nh, geo[18 + d], c.zeta, c.nu, out);
 #pragma unroll
             for (int cc = 0; cc < NTR; ++cc) slot[cc * NF] = out[cc];
         }

@@ -151,6 +151,9 @@ static void fill_consts(const fr_plan *pl, Consts<T> &c)
         }
     }
     c.inv_det = (T)(1.0 / pl->detJ);
+    const double *J = pl->J;
+    c.diag = (J[1] == 0.0 && J[2] == 0.0 && J[3] == 0.0 && J[5] == 0.0 && J[6] == 0.0 &&
+              J[7] == 0.0) ? 1 : 0;
     c.zeta = (T)pl->zeta;
     c.nu = (T)pl->nu;
     c.invT = (T)(1.0 / pl->T);
