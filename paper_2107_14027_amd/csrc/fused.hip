@@ -30,20 +30,180 @@ template <> struct V16<double> { using type = d2v; };
 template <> struct V16<float> { using type = f4v; };
 
 // Launch shape per order and precision: EMAX elements per batch (a runtime
-// block size E <= EMAX may be chosen) and NT threads per workgroup.
+// block size E <= EMAX may be chosen) and NT threads per workgroup.  Each
+// value can be overridden at build time (FR_E<p>_<D|F>, FR_NT<p>_<D|F>).
+#ifndef FR_E1_D
+#define FR_E1_D 8
+#endif
+#ifndef FR_NT1_D
+#define FR_NT1_D 64
+#endif
+#ifndef FR_E2_D
+#define FR_E2_D 4
+#endif
+#ifndef FR_NT2_D
+#define FR_NT2_D 128
+#endif
+#ifndef FR_E3_D
+#define FR_E3_D 1
+#endif
+#ifndef FR_NT3_D
+#define FR_NT3_D 64
+#endif
+#ifndef FR_E4_D
+#define FR_E4_D 1
+#endif
+#ifndef FR_NT4_D
+#define FR_NT4_D 128
+#endif
+#ifndef FR_E5_D
+#define FR_E5_D 1
+#endif
+#ifndef FR_NT5_D
+#define FR_NT5_D 256
+#endif
+#ifndef FR_E6_D
+#define FR_E6_D 1
+#endif
+#ifndef FR_NT6_D
+#define FR_NT6_D 256
+#endif
+#ifndef FR_E1_F
+#define FR_E1_F 8
+#endif
+#ifndef FR_NT1_F
+#define FR_NT1_F 64
+#endif
+#ifndef FR_E2_F
+#define FR_E2_F 4
+#endif
+#ifndef FR_NT2_F
+#define FR_NT2_F 128
+#endif
+#ifndef FR_E3_F
+#define FR_E3_F 1
+#endif
+#ifndef FR_NT3_F
+#define FR_NT3_F 64
+#endif
+#ifndef FR_E4_F
+#define FR_E4_F 1
+#endif
+#ifndef FR_NT4_F
+#define FR_NT4_F 128
+#endif
+#ifndef FR_E5_F
+#define FR_E5_F 1
+#endif
+#ifndef FR_NT5_F
+#define FR_NT5_F 256
+#endif
+#ifndef FR_E6_F
+#define FR_E6_F 1
+#endif
+#ifndef FR_NT6_F
+#define FR_NT6_F 256
+#endif
 template <int P, typename T> struct Shape;
-template <> struct Shape<1, double> { static constexpr int EMAX = 16, NT = 128; };
-template <> struct Shape<2, double> { static constexpr int EMAX = 8, NT = 256; };
-template <> struct Shape<3, double> { static constexpr int EMAX = 4, NT = 256; };
-template <> struct Shape<4, double> { static constexpr int EMAX = 2, NT = 256; };
-template <> struct Shape<5, double> { static constexpr int EMAX = 1, NT = 256; };
-template <> struct Shape<6, double> { static constexpr int EMAX = 1, NT = 384; };
-template <> struct Shape<1, float> { static constexpr int EMAX = 32, NT = 256; };
-template <> struct Shape<2, float> { static constexpr int EMAX = 8, NT = 256; };
-template <> struct Shape<3, float> { static constexpr int EMAX = 4, NT = 256; };
-template <> struct Shape<4, float> { static constexpr int EMAX = 2, NT = 256; };
-template <> struct Shape<5, float> { static constexpr int EMAX = 1, NT = 256; };
-template <> struct Shape<6, float> { static constexpr int EMAX = 1, NT = 384; };
+template <> struct Shape<1, double> { static constexpr int EMAX = FR_E1_D, NT = FR_NT1_D; };
+template <> struct Shape<2, double> { static constexpr int EMAX = FR_E2_D, NT = FR_NT2_D; };
+template <> struct Shape<3, double> { static constexpr int EMAX = FR_E3_D, NT = FR_NT3_D; };
+template <> struct Shape<4, double> { static constexpr int EMAX = FR_E4_D, NT = FR_NT4_D; };
+template <> struct Shape<5, double> { static constexpr int EMAX = FR_E5_D, NT = FR_NT5_D; };
+template <> struct Shape<6, double> { static constexpr int EMAX = FR_E6_D, NT = FR_NT6_D; };
+template <> struct Shape<1, float> { static constexpr int EMAX = FR_E1_F, NT = FR_NT1_F; };
+template <> struct Shape<2, float> { static constexpr int EMAX = FR_E2_F, NT = FR_NT2_F; };
+template <> struct Shape<3, float> { static constexpr int EMAX = FR_E3_F, NT = FR_NT3_F; };
+template <> struct Shape<4, float> { static constexpr int EMAX = FR_E4_F, NT = FR_NT4_F; };
+template <> struct Shape<5, float> { static constexpr int EMAX = FR_E5_F, NT = FR_NT5_F; };
+template <> struct Shape<6, float> { static constexpr int EMAX = FR_E6_F, NT = FR_NT6_F; };
+
+// Shape of the trace kernel (it carries no face data and prefers larger batches).
+#ifndef FR_TE1_D
+#define FR_TE1_D 32
+#endif
+#ifndef FR_TNT1_D
+#define FR_TNT1_D 256
+#endif
+#ifndef FR_TE2_D
+#define FR_TE2_D 8
+#endif
+#ifndef FR_TNT2_D
+#define FR_TNT2_D 256
+#endif
+#ifndef FR_TE3_D
+#define FR_TE3_D 4
+#endif
+#ifndef FR_TNT3_D
+#define FR_TNT3_D 256
+#endif
+#ifndef FR_TE4_D
+#define FR_TE4_D 2
+#endif
+#ifndef FR_TNT4_D
+#define FR_TNT4_D 256
+#endif
+#ifndef FR_TE5_D
+#define FR_TE5_D 1
+#endif
+#ifndef FR_TNT5_D
+#define FR_TNT5_D 256
+#endif
+#ifndef FR_TE6_D
+#define FR_TE6_D 1
+#endif
+#ifndef FR_TNT6_D
+#define FR_TNT6_D 256
+#endif
+#ifndef FR_TE1_F
+#define FR_TE1_F 64
+#endif
+#ifndef FR_TNT1_F
+#define FR_TNT1_F 256
+#endif
+#ifndef FR_TE2_F
+#define FR_TE2_F 8
+#endif
+#ifndef FR_TNT2_F
+#define FR_TNT2_F 256
+#endif
+#ifndef FR_TE3_F
+#define FR_TE3_F 4
+#endif
+#ifndef FR_TNT3_F
+#define FR_TNT3_F 256
+#endif
+#ifndef FR_TE4_F
+#define FR_TE4_F 2
+#endif
+#ifndef FR_TNT4_F
+#define FR_TNT4_F 256
+#endif
+#ifndef FR_TE5_F
+#define FR_TE5_F 1
+#endif
+#ifndef FR_TNT5_F
+#define FR_TNT5_F 256
+#endif
+#ifndef FR_TE6_F
+#define FR_TE6_F 1
+#endif
+#ifndef FR_TNT6_F
+#define FR_TNT6_F 256
+#endif
+template <int P, typename T> struct TraceShape;
+template <> struct TraceShape<1, double> { static constexpr int EMAX = FR_TE1_D, NT = FR_TNT1_D; };
+template <> struct TraceShape<2, double> { static constexpr int EMAX = FR_TE2_D, NT = FR_TNT2_D; };
+template <> struct TraceShape<3, double> { static constexpr int EMAX = FR_TE3_D, NT = FR_TNT3_D; };
+template <> struct TraceShape<4, double> { static constexpr int EMAX = FR_TE4_D, NT = FR_TNT4_D; };
+template <> struct TraceShape<5, double> { static constexpr int EMAX = FR_TE5_D, NT = FR_TNT5_D; };
+template <> struct TraceShape<6, double> { static constexpr int EMAX = FR_TE6_D, NT = FR_TNT6_D; };
+template <> struct TraceShape<1, float> { static constexpr int EMAX = FR_TE1_F, NT = FR_TNT1_F; };
+template <> struct TraceShape<2, float> { static constexpr int EMAX = FR_TE2_F, NT = FR_TNT2_F; };
+template <> struct TraceShape<3, float> { static constexpr int EMAX = FR_TE3_F, NT = FR_TNT3_F; };
+template <> struct TraceShape<4, float> { static constexpr int EMAX = FR_TE4_F, NT = FR_TNT4_F; };
+template <> struct TraceShape<5, float> { static constexpr int EMAX = FR_TE5_F, NT = FR_TNT5_F; };
+template <> struct TraceShape<6, float> { static constexpr int EMAX = FR_TE6_F, NT = FR_TNT6_F; };
 
 // Register staging of one batch's contiguous state block U[e0 .. e0+nel).
 // Chunk k of W values (W = 16 bytes) belongs to thread k mod NT.  A full batch
@@ -138,12 +298,12 @@ __device__ __forceinline__ void neighbour_table(int *sNb, int e0, int nel, int n
 // k_trace
 // ---------------------------------------------------------------------------
 template <int P, typename T>
-__global__ void __launch_bounds__((Shape<P, T>::NT))
+__global__ void __launch_bounds__((TraceShape<P, T>::NT))
     k_trace(const T *__restrict__ U, T *__restrict__ TR, const T *__restrict__ ops, Consts<T> c,
             int ne, int E, int nbatch)
 {
     constexpr int M = P + 1, NS = M * M * M, NF = M * M, CH = NTR * NF;
-    constexpr int EMAX = Shape<P, T>::EMAX, NT = Shape<P, T>::NT;
+    constexpr int EMAX = TraceShape<P, T>::EMAX, NT = TraceShape<P, T>::NT;
     using OL = OpsLayout<M>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sU = reinterpret_cast<T *>(smem_raw);
@@ -392,13 +552,16 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
 {
     constexpr int M = P + 1, NS = M * M * M, NF = M * M;
     constexpr int EMAX = Shape<P, T>::EMAX, NT = Shape<P, T>::NT;
+    constexpr int TEMAX = TraceShape<P, T>::EMAX, TNT = TraceShape<P, T>::NT;
     const int ne = (int)pl->ne;
     int E = pl->block ? pl->block : EMAX;
     if (E > EMAX)
         return set_error(FR_EINVAL, "fused kernel: block %d exceeds %d elements at p=%d", E, EMAX, P);
     if (E > ne) E = ne;
     const int nbatch = (ne + E - 1) / E;
-    const size_t lds_tr = ((size_t)EMAX * NV * NS + 2 * M) * sizeof(T);
+    const int TE = TEMAX < ne ? TEMAX : ne;
+    const int nbatch_tr = (ne + TE - 1) / TE;
+    const size_t lds_tr = ((size_t)TEMAX * NV * NS + 2 * M) * sizeof(T);
     const size_t lds_fu = ((size_t)EMAX * (NV + 9) * NS + (size_t)EMAX * 6 * NTR * NF +
                            OpsLayout<M>::size + 24) * sizeof(T) + 6 * EMAX * sizeof(int);
     static int grid_tr = 0, grid_fu = 0;
@@ -417,7 +580,7 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
                                                    (int)lds_fu), "hipFuncSetAttribute(k_fused)"))
             return rc;
         if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                   &occ_tr, (const void *)k_trace<P, T>, NT, lds_tr),
+                                   &occ_tr, (const void *)k_trace<P, T>, TNT, lds_tr),
                                "occupancy(k_trace)"))
             return rc;
         if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -429,12 +592,12 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
         grid_tr = ncu * occ_tr;
         grid_fu = ncu * occ_fu;
     }
-    const unsigned gtr = (unsigned)min(nbatch, grid_tr);
+    const unsigned gtr = (unsigned)min(nbatch_tr, grid_tr);
     const unsigned gfu = (unsigned)min(nbatch, grid_fu);
     {
         ProfScope ps(pl, FR_K_TRACE, s);
-        hipLaunchKernelGGL((k_trace<P, T>), dim3(gtr), dim3(NT), lds_tr, s, U, TR, ops, c, ne, E,
-                           nbatch);
+        hipLaunchKernelGGL((k_trace<P, T>), dim3(gtr), dim3(TNT), lds_tr, s, U, TR, ops, c, ne, TE,
+                           nbatch_tr);
     }
     {
         ProfScope ps(pl, FR_K_FUSED, s);
