@@ -159,6 +159,66 @@ int fr_guess_extrap(fr_plan *plan, const double *Un, const double *Unm1, const d
                     int order, double *G, fr_stream_t s);
 
 /*
+ * Learned initial guess (not in the paper: the pseudo-time iteration still
+ * decides the converged state, the guess only sets where it starts).
+ * A pointwise network 12 -> 64 -> 64 -> 4 with tanh hidden layers predicts a
+ * correction to the quadratic extrapolation of P, u, v, w:
+ *   raw features  [U^n_c, U^n_c - U^{n-1}_c, U^n_c - 2 U^{n-1}_c + U^{n-2}_c], c = P,u,v,w
+ *   x = (raw - mu) * inv_sd,   y = W3 tanh(W2 tanh(W1 x + b1) + b2) + b3
+ *   G_c = 3 U^n_c - 3 U^{n-1}_c + U^{n-2}_c + y_sd_c * y_c
+ * Weights are rounded to bfloat16 for the matrix-core products, which
+ * accumulate in float; activations are rounded to bfloat16 between layers.
+ *
+ * The network lives in one caller-owned DEVICE float array ("state") of
+ * fr_mlp_state_floats() entries:
+ *   [0, 5252)      parameters W1[64][12], b1[64], W2[64][64], b2[64], W3[4][64], b3[4]
+ *                  (row-major, output index first)
+ *   [5252, 5280)   normalisation mu[12], inv_sd[12], y_sd[4]
+ *   then           Adam first and second moments, 5252 floats each
+ * fr_mlp_init writes initial parameters (uniform Glorot W1, W2 from `seed`;
+ * W3 = b3 = 0 so that the initial guess equals the extrapolation), identity
+ * normalisation and zero moments, and synchronises the stream.
+ * Training rows: X[n][12] raw features and Y[n][4] raw targets
+ * (U^{n+1}_c minus its quadratic extrapolation), float, device memory.
+ */
+size_t fr_mlp_state_floats(void);
+int fr_mlp_init(float *state, uint64_t seed, fr_stream_t s);
+
+/* Raw training rows of the points offset + k*stride (k < n, flat index over
+ * (element, point)) from three past states and, if Unp1 != NULL, the step's
+ * converged state (else Y = 0). */
+int fr_mlp_sample(fr_plan *plan, const double *Un, const double *Unm1, const double *Unm2,
+                  const double *Unp1, int64_t offset, int64_t stride, int64_t n, float *X,
+                  float *Y, fr_stream_t s);
+
+/* Sets mu, inv_sd of the features and y_sd of the targets in `state` from the
+ * column moments of X, Y (deterministic reductions in double). */
+int fr_mlp_fit_norm(fr_plan *plan, float *state, const float *X, const float *Y, int64_t n,
+                    fr_stream_t s);
+
+/* Network outputs y (normalised units) of raw feature rows: Yout[n][4]. */
+int fr_mlp_forward(fr_plan *plan, const float *state, const float *X, int64_t n, float *Yout,
+                   fr_stream_t s);
+
+/* Gradient of L = (1/(4n)) sum (y - Y/y_sd)^2 with respect to the 5252
+ * parameters into grad (device, float, parameter layout) and L into *loss
+ * (device float, may be NULL).  Per-wavefront partial sums are reduced in a
+ * fixed order: results are deterministic. */
+int fr_mlp_grad(fr_plan *plan, const float *state, const float *X, const float *Y, int64_t n,
+                float *grad, float *loss, fr_stream_t s);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step >= 1)
+ * of the parameters in `state` on the rows (X, Y); *loss (device, may be NULL)
+ * receives the loss before the update. */
+int fr_mlp_train_step(fr_plan *plan, float *state, const float *X, const float *Y, int64_t n,
+                      float lr, int step, float *loss, fr_stream_t s);
+
+/* G (double state array) = network guess for P, u, v, w and quadratic
+ * extrapolation for the auxiliary variables. */
+int fr_mlp_guess(fr_plan *plan, const float *state, const double *Un, const double *Unm1,
+                 const double *Unm2, double *G, fr_stream_t s);
+
+/*
  * fr_plan_kernel_stats -- with FR_OPT_PROFILE set, every kernel launch of the
  * plan is bracketed by two HIP events recorded on the launch stream.  This call
  * waits for the recorded events, adds their elapsed times to per-kernel totals

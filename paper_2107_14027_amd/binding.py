@@ -20,7 +20,9 @@ NV = 13
 
 EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_destroy",
             "fr_state_len", "fr_residual", "fr_rk_step", "fr_dual_step", "fr_guess_extrap",
-            "fr_strerror", "fr_last_error", "fr_plan_operators", "fr_plan_kernel_stats")
+            "fr_strerror", "fr_last_error", "fr_plan_operators", "fr_plan_kernel_stats",
+            "fr_mlp_state_floats", "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm",
+            "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess")
 
 
 class FrError(RuntimeError):
@@ -60,8 +62,20 @@ def lib():
         L.fr_last_error.restype = ctypes.c_char_p
         L.fr_plan_operators.argtypes = [I, _dp]
         L.fr_plan_kernel_stats.argtypes = [_vp, I, _dp, ctypes.POINTER(ctypes.c_int64), I]
+        I64, F = ctypes.c_int64, ctypes.c_float
+        L.fr_mlp_state_floats.argtypes = []
+        L.fr_mlp_state_floats.restype = ctypes.c_size_t
+        L.fr_mlp_init.argtypes = [_vp, ctypes.c_uint64, _vp]
+        L.fr_mlp_sample.argtypes = [_vp, _vp, _vp, _vp, _vp, I64, I64, I64, _vp, _vp, _vp]
+        L.fr_mlp_fit_norm.argtypes = [_vp, _vp, _vp, _vp, I64, _vp]
+        L.fr_mlp_forward.argtypes = [_vp, _vp, _vp, I64, _vp, _vp]
+        L.fr_mlp_grad.argtypes = [_vp, _vp, _vp, _vp, I64, _vp, _vp, _vp]
+        L.fr_mlp_train_step.argtypes = [_vp, _vp, _vp, _vp, I64, F, I, _vp, _vp]
+        L.fr_mlp_guess.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
         for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step",
-                  "fr_dual_step", "fr_guess_extrap", "fr_plan_operators", "fr_plan_kernel_stats"):
+                  "fr_dual_step", "fr_guess_extrap", "fr_plan_operators", "fr_plan_kernel_stats",
+                  "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm", "fr_mlp_forward",
+                  "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess"):
             getattr(L, n).restype = I
         _lib = L
     return _lib
@@ -174,6 +188,92 @@ def fr_plan_kernel_stats(plan, kernel, reset=False):
     _check(lib().fr_plan_kernel_stats(plan, int(kernel), ctypes.byref(ms), ctypes.byref(n),
                                       int(bool(reset))))
     return ms.value, n.value
+
+
+# --------------------------------------------------------------------------- learned guess
+MLP_NPAR = 5252
+MLP_SHAPES = (("W1", (64, 12)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+              ("W3", (4, 64)), ("b3", (4,)))
+
+
+def fr_mlp_state_floats():
+    return lib().fr_mlp_state_floats()
+
+
+def mlp_new_state(seed=0, stream=None):
+    """A device float32 tensor holding an initialised network state."""
+    import torch
+    st = torch.zeros(fr_mlp_state_floats(), dtype=torch.float32, device="cuda")
+    _check(lib().fr_mlp_init(_vp(st.data_ptr()), int(seed), _stream(stream)))
+    return st
+
+
+def mlp_params(state):
+    """Split the parameter part of a state tensor into named views."""
+    out, o = {}, 0
+    for k, shp in MLP_SHAPES:
+        n = int(np.prod(shp))
+        out[k] = state[o:o + n].view(*shp)
+        o += n
+    return out
+
+
+def fr_mlp_sample(plan, Un, Unm1, Unm2, Unp1, offset, stride, n, X, Y, stream=None):
+    import torch
+    ns = fr_state_len(plan)
+    d = lambda t, nm: None if t is None else _dev(t, torch.float64, ns, nm)
+    return _check(lib().fr_mlp_sample(plan, d(Un, "Un"), d(Unm1, "Unm1"), d(Unm2, "Unm2"),
+                                      d(Unp1, "Unp1"), int(offset), int(stride), int(n),
+                                      _dev(X, torch.float32, 12 * n, "X"),
+                                      _dev(Y, torch.float32, 4 * n, "Y"), _stream(stream)))
+
+
+def fr_mlp_fit_norm(plan, state, X, Y, stream=None):
+    import torch
+    n = X.numel() // 12
+    return _check(lib().fr_mlp_fit_norm(plan, _dev(state, torch.float32, None, "state"),
+                                        _dev(X, torch.float32, 12 * n, "X"),
+                                        _dev(Y, torch.float32, 4 * n, "Y"), n, _stream(stream)))
+
+
+def fr_mlp_forward(plan, state, X, Yout, stream=None):
+    import torch
+    n = X.numel() // 12
+    return _check(lib().fr_mlp_forward(plan, _dev(state, torch.float32, None, "state"),
+                                       _dev(X, torch.float32, 12 * n, "X"), n,
+                                       _dev(Yout, torch.float32, 4 * n, "Yout"), _stream(stream)))
+
+
+def fr_mlp_grad(plan, state, X, Y, grad, loss=None, stream=None):
+    import torch
+    n = X.numel() // 12
+    return _check(lib().fr_mlp_grad(plan, _dev(state, torch.float32, None, "state"),
+                                    _dev(X, torch.float32, 12 * n, "X"),
+                                    _dev(Y, torch.float32, 4 * n, "Y"), n,
+                                    _dev(grad, torch.float32, MLP_NPAR, "grad"),
+                                    None if loss is None else _dev(loss, torch.float32, None, "loss"),
+                                    _stream(stream)))
+
+
+def fr_mlp_train_step(plan, state, X, Y, lr, step, loss=None, stream=None):
+    import torch
+    n = X.numel() // 12
+    return _check(lib().fr_mlp_train_step(plan, _dev(state, torch.float32, None, "state"),
+                                          _dev(X, torch.float32, 12 * n, "X"),
+                                          _dev(Y, torch.float32, 4 * n, "Y"), n, float(lr),
+                                          int(step),
+                                          None if loss is None else _dev(loss, torch.float32, None, "loss"),
+                                          _stream(stream)))
+
+
+def fr_mlp_guess(plan, state, Un, Unm1, Unm2, G, stream=None):
+    import torch
+    ns = fr_state_len(plan)
+    return _check(lib().fr_mlp_guess(plan, _dev(state, torch.float32, None, "state"),
+                                     _dev(Un, torch.float64, ns, "Un"),
+                                     _dev(Unm1, torch.float64, ns, "Unm1"),
+                                     _dev(Unm2, torch.float64, ns, "Unm2"),
+                                     _dev(G, torch.float64, ns, "G"), _stream(stream)))
 
 
 def fr_plan_operators(p):

@@ -69,6 +69,7 @@ struct fr_plan {
     fr::Scratch rk;         // acc (double), stage (T), k (T)
     fr::Scratch dual;       // BDF constant part (double, velocity only)
     fr::Scratch norm;       // partial sums (double)
+    fr::Scratch mlp;        // MLP gradient partials / moments
     double *norm_host = nullptr;  // pinned host word for the norm read-back
     // optional per-kernel event timing
     int profile = 0;

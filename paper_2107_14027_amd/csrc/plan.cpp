@@ -411,6 +411,7 @@ void fr_plan_destroy(fr_plan *pl)
     free_scratch(pl->rk);
     free_scratch(pl->dual);
     free_scratch(pl->norm);
+    free_scratch(pl->mlp);
     if (pl->norm_host) hipHostFree(pl->norm_host);
     if (pl->ops64) hipFree(pl->ops64);
     if (pl->ops32) hipFree(pl->ops32);
