@@ -18,7 +18,6 @@ Prints ONE JSON line on stdout; progress goes to stderr.
   cpu_baseline  the serial C oracle on a bounded sample of the same workload
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -52,16 +51,10 @@ def trace_bytes(p, ne, esz):
     return ne * (NV * m ** 3 + 6 * 7 * m * m) * esz
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("fused.hip", "fr_device.h", "fr_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2107_14027_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def read_traffic(kernel_name):
     """HBM traffic per launch from a committed rocprofv3 counter summary, if it was
     taken on the current kernel source; None otherwise."""
+    from paper_2107_14027_amd.rocprof_summary import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "traffic_%s.txt" % kernel_name)
     if not os.path.exists(path):
         return None
