@@ -205,6 +205,20 @@ template <> struct TraceShape<4, float> { static constexpr int EMAX = FR_TE4_F, 
 template <> struct TraceShape<5, float> { static constexpr int EMAX = FR_TE5_F, NT = FR_TNT5_F; };
 template <> struct TraceShape<6, float> { static constexpr int EMAX = FR_TE6_F, NT = FR_TNT6_F; };
 
+// Face-trace blocks in HBM, indexed by the element that consumes them:
+// TR[f][e] holds the 7 x m^2 trace values that element e needs on its face f,
+// i.e. the values of the neighbour across that face, on the neighbour's face
+// f ^ 1.  Each block is padded to a whole number of 16-byte chunks so that a
+// batch of consecutive elements reads, for every face, one contiguous and
+// aligned run of blocks.
+template <int M, typename T>
+struct TraceLayout {
+    static constexpr int NF = M * M, CH = NTR * NF;
+    static constexpr int W = 16 / sizeof(T);
+    static constexpr int CHP = (CH + W - 1) / W * W;
+    static constexpr int CHV = CHP / W;
+};
+
 // Register staging of one batch's contiguous state block U[e0 .. e0+nel).
 // Chunk k of W values (W = 16 bytes) belongs to thread k mod NT.  A full batch
 // (count == NVAL) whose start is 16-byte aligned takes a branch-free path with
@@ -266,6 +280,44 @@ struct StateStage {
     }
 };
 
+// Register staging of a batch's trace blocks: six runs (one per face) of nel
+// consecutive padded blocks, TR[f][e0 .. e0+nel), into LDS as [f][EMAX][CHP].
+// All accesses are aligned 16-byte chunks.
+template <int M, typename T, int EMAX, int NT>
+struct TraceStage {
+    using TL = TraceLayout<M, T>;
+    using V = typename V16<T>::type;
+    static constexpr int RUN = EMAX * TL::CHV;        // chunks per face run of a full batch
+    static constexpr int NCH = 6 * RUN;
+    static constexpr int PV = (NCH + NT - 1) / NT;
+    V r[PV];
+
+    __device__ __forceinline__ void load(const T *__restrict__ TR, int ne, int e0, int nel, int tid)
+    {
+        const V *src = reinterpret_cast<const V *>(TR);
+        const unsigned run = (unsigned)nel * TL::CHV;
+#pragma unroll
+        for (int i = 0; i < PV; ++i) {
+            const unsigned k = tid + i * NT;
+            const unsigned f = k / RUN, o = k - f * RUN;
+            if (((i + 1) * NT <= NCH || k < NCH) && (nel == EMAX || o < run))
+                r[i] = __builtin_nontemporal_load(
+                    src + ((int64_t)f * ne + e0) * TL::CHV + o);
+        }
+    }
+    __device__ __forceinline__ void store(T *__restrict__ dst, int nel, int tid) const
+    {
+        V *d = reinterpret_cast<V *>(dst);
+        const unsigned run = (unsigned)nel * TL::CHV;
+#pragma unroll
+        for (int i = 0; i < PV; ++i) {
+            const unsigned k = tid + i * NT;
+            const unsigned f = k / RUN, o = k - f * RUN;
+            if (((i + 1) * NT <= NCH || k < NCH) && (nel == EMAX || o < run)) d[k] = r[i];
+        }
+    }
+};
+
 // The thread index, hidden from the optimiser so that index arithmetic derived
 // from it is recomputed inside the batch loop instead of being hoisted out of
 // it and kept live in registers for the whole kernel.
@@ -276,38 +328,82 @@ __device__ __forceinline__ int opaque_tid()
     return t;
 }
 
-// Neighbour element of every (element, face) of a batch, into an LDS table.
+// Neighbour element of every (element, face) of a batch, into an LDS table of
+// 6 nel entries filled by the NT threads of the workgroup.
+template <int NT>
 __device__ __forceinline__ void neighbour_table(int *sNb, int e0, int nel, int nx, int ny, int nz)
 {
-    const int t = threadIdx.x;
-    if (t >= 6 * nel) return;
-    const int el = t / 6, f = t - el * 6;
-    const int e = e0 + el;
-    int ex = e % nx;
-    const int r = e / nx;
-    int ey = r % ny;
-    int ez = r / ny;
-    const int d = f >> 1, up = f & 1;
-    if (d == 0) ex = up ? (ex + 1 == nx ? 0 : ex + 1) : (ex == 0 ? nx - 1 : ex - 1);
-    else if (d == 1) ey = up ? (ey + 1 == ny ? 0 : ey + 1) : (ey == 0 ? ny - 1 : ey - 1);
-    else ez = up ? (ez + 1 == nz ? 0 : ez + 1) : (ez == 0 ? nz - 1 : ez - 1);
-    sNb[t] = ex + nx * (ey + ny * ez);
+    for (int t = threadIdx.x; t < 6 * nel; t += NT) {
+        const int el = t / 6, f = t - el * 6;
+        const int e = e0 + el;
+        int ex = e % nx;
+        const int r = e / nx;
+        int ey = r % ny;
+        int ez = r / ny;
+        const int d = f >> 1, up = f & 1;
+        if (d == 0) ex = up ? (ex + 1 == nx ? 0 : ex + 1) : (ex == 0 ? nx - 1 : ex - 1);
+        else if (d == 1) ey = up ? (ey + 1 == ny ? 0 : ey + 1) : (ey == 0 ? ny - 1 : ey - 1);
+        else ez = up ? (ez + 1 == nz ? 0 : ez + 1) : (ez == 0 ? nz - 1 : ez - 1);
+        sNb[t] = ex + nx * (ey + ny * ez);
+    }
+}
+
+// Common normal flux through a face of direction d, evaluated by the element
+// on one side: own = its trace, oth = the neighbour's, own_minus = the element
+// is on the minus side of the face (its + face).  Equal, bit for bit, to the
+// same flux evaluated by the neighbour, because every asymmetric term is
+// written as a signed difference oth - own whose sign is carried by an exact
+// sign flip of lambda, and every symmetric term is a commutative sum.
+//   out[0]     Rusanov dissipation on P, -|n| lambda (P_plus - P_minus) / 2
+//   out[1..3]  momentum common flux (times |n_d|)
+//   out[4..6]  mean velocity
+template <typename T>
+__device__ __forceinline__ void common_flux_sided(const T own[NTR], const T oth[NTR], bool own_minus,
+                                                  const T nh[3], T nmag, T zeta, T nu, T out[NTR])
+{
+    T vo = own[1] * nh[0];
+    vo = fma(own[2], nh[1], vo);
+    vo = fma(own[3], nh[2], vo);
+    T vt = oth[1] * nh[0];
+    vt = fma(oth[2], nh[1], vt);
+    vt = fma(oth[3], nh[2], vt);
+    // lambda = max over both sides of |v| + sqrt(v^2 + zeta), evaluated once
+    // at the larger |v| (the expression is monotone in |v| after rounding too)
+    const T vm = fmax(fabs(vo), fabs(vt));
+    const T lam = vm + sqrt(fma(vm, vm, zeta));
+    const T hm = T(0.5) * nmag;
+    // P_plus - P_minus = (own_minus ? 1 : -1) (P_oth - P_own)
+    const T slam = own_minus ? lam : -lam;
+    out[0] = (-hm * slam) * (oth[0] - own[0]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const T fo = fma(own[1 + i], vo, fma(own[0], nh[i], -nu * own[4 + i]));
+        const T ft = fma(oth[1 + i], vt, fma(oth[0], nh[i], -nu * oth[4 + i]));
+        out[1 + i] = hm * fma(oth[1 + i] - own[1 + i], -slam, fo + ft);
+        out[4 + i] = T(0.5) * (own[1 + i] + oth[1 + i]);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// k_trace
+// k_trace: per batch of consecutive elements staged in LDS, every face value
+// an element's neighbours need, written to the neighbour's receiving block.
 // ---------------------------------------------------------------------------
-template <int P, typename T>
+template <int P, typename T, bool DIAG>
 __global__ void __launch_bounds__((TraceShape<P, T>::NT))
     k_trace(const T *__restrict__ U, T *__restrict__ TR, const T *__restrict__ ops, Consts<T> c,
-            int ne, int E, int nbatch)
+            int nx, int ny, int nz, int E, int nbatch)
 {
-    constexpr int M = P + 1, NS = M * M * M, NF = M * M, CH = NTR * NF;
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    using TL = TraceLayout<M, T>;
+    constexpr int CH = TL::CH, CHV = TL::CHV, W = TL::W;
     constexpr int EMAX = TraceShape<P, T>::EMAX, NT = TraceShape<P, T>::NT;
     using OL = OpsLayout<M>;
+    using V = typename V16<T>::type;
+    const int ne = nx * ny * nz;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sU = reinterpret_cast<T *>(smem_raw);
     T *sl = sU + EMAX * NV * NS;  // lm[M], lp[M]
+    int *sNb = reinterpret_cast<int *>(sl + 2 * M);
     if (threadIdx.x < 2 * M) sl[threadIdx.x] = ops[OL::lm + threadIdx.x];
 
     StateStage<T, EMAX * NV * NS, NT> st;
@@ -316,56 +412,68 @@ __global__ void __launch_bounds__((TraceShape<P, T>::NT))
         const int e0 = b * E;
         st.load(U + (int64_t)e0 * NV * NS, min(E, ne - e0) * NV * NS, threadIdx.x);
     }
+    V *TRv = reinterpret_cast<V *>(TR);
     for (; b < nbatch; b += gridDim.x) {
         const int tid = opaque_tid();
         const int e0 = b * E;
         const int nel = min(E, ne - e0);
         __syncthreads();
         st.store(sU, nel * NV * NS, tid);
+        neighbour_table<NT>(sNb, e0, nel, nx, ny, nz);
         const int bn = b + gridDim.x;
         __syncthreads();
         if (bn < nbatch) {
             const int en = bn * E;
             st.load(U + (int64_t)en * NV * NS, min(E, ne - en) * NV * NS, tid);
         }
-        // one trace value per thread, in the order of TR[f][e][c][fp] so that
-        // each face's block of the batch is written contiguously
-        for (int t = tid; t < 6 * EMAX * CH; t += NT) {
-            const int f = t / (EMAX * CH), r = t - f * (EMAX * CH);
-            const int el = r / CH, o = r - el * CH;
-            if (el >= nel) continue;
-            const int cc = o / NF, fp = o - cc * NF;
+        // one 16-byte chunk of one (face, element) block per thread and step;
+        // the block of own face f goes to the receiving block (f ^ 1, neighbour)
+        for (unsigned t = tid; t < 6u * EMAX * CHV; t += NT) {
+            const unsigned f = t / (EMAX * CHV), r = t - f * (EMAX * CHV);
+            const unsigned el = r / CHV, k = r - el * CHV;
+            if ((int)el >= nel) continue;
             const int d = f >> 1, s = f & 1;
             const T nh[3] = {c.nhat[d][0], c.nhat[d][1], c.nhat[d][2]};
-            int base, stride;
-            line_of<M>(d, fp % M, fp / M, base, stride);
-            const T v = trace_value<M, T>(sU + el * NV * NS, d, base, stride, sl + s * M, nh, cc, c.diag);
-            __builtin_nontemporal_store(v, TR + ((int64_t)f * ne + e0 + el) * CH + o);
+            V x;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const unsigned o = k * W + w;
+                const unsigned cc = o / NF, fp = o - cc * NF;
+                const unsigned a = fp % M, bb = fp / M;
+                const int stride = d == 0 ? 1 : (d == 1 ? M : M * M);
+                const int base = d == 0 ? M * fp : (d == 1 ? a + M * M * bb : fp);
+                x[w] = o < (unsigned)CH
+                           ? trace_value<M, T>(sU + el * NV * NS, d, base, stride, sl + s * M, nh, cc, DIAG)
+                           : T(0);
+            }
+            const int nb = sNb[el * 6 + f];
+            __builtin_nontemporal_store(x, TRv + ((int64_t)(f ^ 1) * ne + nb) * CHV + k);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
 // k_fused
-// LDS: sU[EMAX][13][NS] | sF[EMAX][9][NS] | sFI[EMAX][6][7][NF] | ops | geometry | sNb
+// LDS: sU[EMAX][13][NS] | sF[EMAX][9][NS] | sFI[6][EMAX][CHP] | ops | geometry
 // ---------------------------------------------------------------------------
-template <int P, typename T>
+template <int D> struct Dir { static constexpr int value = D; };
+
+template <int P, typename T, bool DIAG>
 __global__ void __launch_bounds__((Shape<P, T>::NT))
     k_fused(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
-            const T *__restrict__ ops, Consts<T> c, int nx, int ny, int nz, int E, int nbatch)
+            const T *__restrict__ ops, Consts<T> c, int ne, int E, int nbatch)
 {
-    constexpr int M = P + 1, NS = M * M * M, NF = M * M, CH = NTR * NF;
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    using TL = TraceLayout<M, T>;
+    constexpr int CHP = TL::CHP;
     constexpr int EMAX = Shape<P, T>::EMAX, NT = Shape<P, T>::NT;
-    constexpr int PT = (6 * EMAX * CH + NT - 1) / NT;  // trace values staged per thread
     using OL = OpsLayout<M>;
-    const int ne = nx * ny * nz;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sU = reinterpret_cast<T *>(smem_raw);
     T *sF = sU + EMAX * NV * NS;
     T *sFI = sF + EMAX * 9 * NS;
-    T *sop = sFI + EMAX * 6 * CH;
+    T *sop = sFI + 6 * EMAX * CHP;
     T *geo = sop + OL::size;  // n_d (row d), n_hat_d (row d), |n_d|
-    int *sNb = reinterpret_cast<int *>(geo + 24);
     for (int t = threadIdx.x; t < OL::size; t += NT) sop[t] = ops[t];
     if (threadIdx.x < 9) {
         geo[threadIdx.x] = c.nvec[threadIdx.x / 3][threadIdx.x % 3];
@@ -374,38 +482,12 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
     if (threadIdx.x < 3) geo[18 + threadIdx.x] = c.nmag[threadIdx.x];
 
     StateStage<T, EMAX * NV * NS, NT> st;
-    T rt[PT];
-    // neighbour traces of a batch: flat index t = (el * 6 + f) * CH + o, the
-    // LDS layout of sFI, loaded from TR[f^1][neighbour(e0 + el, f)][o]
-    constexpr int NTV = 6 * EMAX * CH;                  // trace values of a full batch
-    auto load_traces = [&](int nel, int tid) {
-        const int lim = nel == EMAX ? NTV : 6 * nel * CH;
-#pragma unroll
-        for (int i = 0; i < PT; ++i) {
-            const int t = tid + i * NT;
-            if ((nel == EMAX && (i + 1) * NT <= NTV) || t < lim) {
-                const int j = t / CH, o = t - j * CH;
-                rt[i] = __builtin_nontemporal_load(
-                    TR + ((int64_t)((j % 6) ^ 1) * ne + sNb[j]) * CH + o);
-            }
-        }
-    };
-    auto store_traces = [&](int nel, int tid) {
-        const int lim = nel == EMAX ? NTV : 6 * nel * CH;
-#pragma unroll
-        for (int i = 0; i < PT; ++i) {
-            const int t = tid + i * NT;
-            if ((nel == EMAX && (i + 1) * NT <= NTV) || t < lim) sFI[t] = rt[i];
-        }
-    };
-
+    TraceStage<M, T, EMAX, NT> tt;
     int b = blockIdx.x;
     if (b < nbatch) {
         const int e0 = b * E, nel = min(E, ne - e0);
-        neighbour_table(sNb, e0, nel, nx, ny, nz);
-        __syncthreads();
         st.load(U + (int64_t)e0 * NV * NS, nel * NV * NS, threadIdx.x);
-        load_traces(nel, threadIdx.x);
+        tt.load(TR, ne, e0, nel, threadIdx.x);
     }
     const T *Dt = sop + OL::Dt;
     const T *gl = sop + OL::gl;
@@ -416,20 +498,19 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
         const int nel = min(E, ne - e0);
         __syncthreads();
         st.store(sU, nel * NV * NS, tid);
-        store_traces(nel, tid);
+        tt.store(sFI, nel, tid);
         const int bn = b + gridDim.x;
-        const int en = bn * E, neln = bn < nbatch ? min(E, ne - en) : 0;
-        if (neln) neighbour_table(sNb, en, neln, nx, ny, nz);
         __syncthreads();
-        if (neln) {
+        if (bn < nbatch) {
+            const int en = bn * E, neln = min(E, ne - en);
             st.load(U + (int64_t)en * NV * NS, neln * NV * NS, tid);
-            load_traces(neln, tid);
+            tt.load(TR, ne, en, neln, tid);
         }
 
         // ---- stage 2: transformed momentum flux at every point,
         //      Fhat_{d,i} = u_i (n_d . V) + P n_d,i - nu sum_j n_d,j S_ij
-        for (int t = tid; t < nel * NS; t += NT) {
-            const int el = t / NS, q = t - el * NS;
+        for (unsigned t = tid; t < (unsigned)nel * NS; t += NT) {
+            const unsigned el = t / NS, q = t - el * NS;
             const T *Ue = sU + el * NV * NS;
             const T u[3] = {Ue[1 * NS + q], Ue[2 * NS + q], Ue[3 * NS + q]};
             const T Pq = Ue[q];
@@ -453,64 +534,62 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
             }
         }
         // ---- stages 1 + 4 on chip: own trace, common flux with the neighbour
-        //      trace (left state = minus side of the face), result in place.
-        //      Face points are ordered (d, el, side, fp) so that the lanes of a
-        //      wave share a direction; the side only swaps operands (no branch).
-        for (int t = tid; t < 3 * EMAX * 2 * NF; t += NT) {
-            const int d = t / (EMAX * 2 * NF), r = t - d * (EMAX * 2 * NF);
-            const int el = r / (2 * NF), r2 = r - el * (2 * NF);
-            if (el >= nel) continue;
-            const int s = r2 / NF, fp = r2 - s * NF;
-            int base, stride;
-            line_of<M>(d, fp % M, fp / M, base, stride);
+        //      trace, result in place of the neighbour trace.  Face points are
+        //      ordered (d, el, side, fp) so that the lanes of a wave mostly
+        //      share a direction.
+        for (unsigned t = tid; t < 3u * EMAX * 2 * NF; t += NT) {
+            const unsigned d = t / (EMAX * 2 * NF), r = t - d * (EMAX * 2 * NF);
+            const unsigned el = r / (2 * NF), r2 = r - el * (2 * NF);
+            if ((int)el >= nel) continue;
+            const unsigned s = r2 / NF, fp = r2 - s * NF;
+            const unsigned a = fp % M, bb = fp / M;
+            const int stride = d == 0 ? 1 : (d == 1 ? M : M * M);
+            const int base = d == 0 ? M * fp : (d == 1 ? a + M * M * bb : fp);
             const T nh[3] = {geo[9 + 3 * d], geo[10 + 3 * d], geo[11 + 3 * d]};
             const T *lf = sop + (s ? OL::lp : OL::lm);
-            T own[NTR], oth[NTR], L[NTR], Rr[NTR], out[NTR];
+            T own[NTR], oth[NTR], out[NTR];
 #pragma unroll
             for (int cc = 0; cc < NTR; ++cc) {
                 if (cc >= 4) __builtin_amdgcn_sched_barrier(0);
-                own[cc] = trace_value<M, T>(sU + el * NV * NS, d, base, stride, lf, nh, cc, c.diag);
+                own[cc] = trace_value<M, T>(sU + el * NV * NS, d, base, stride, lf, nh, cc, DIAG);
             }
-            T *slot = sFI + ((el * 6 + 2 * d + s) * NTR) * NF + fp;
+            T *slot = sFI + ((2 * d + s) * EMAX + el) * CHP + fp;
 #pragma unroll
-            for (int cc = 0; cc < NTR; ++cc) {
-                oth[cc] = slot[cc * NF];
-                L[cc] = s ? own[cc] : oth[cc];
-                Rr[cc] = s ? oth[cc] : own[cc];
-            }
-            common_flux<T>(L, Rr, nh, geo[18 + d], c.zeta, c.nu, out);
+            for (int cc = 0; cc < NTR; ++cc) oth[cc] = slot[cc * NF];
+            common_flux_sided<T>(own, oth, s != 0, nh, geo[18 + d], c.zeta, c.nu, out);
 #pragma unroll
             for (int cc = 0; cc < NTR; ++cc) slot[cc * NF] = out[cc];
         }
         __syncthreads();
 
         // ---- stages 3, 5, 6: partially corrected divergence along the three
-        //      line families, correction with the common fluxes, negate, source.
-        //      Directions run as a loop (not unrolled) to bound live registers.
-        for (int t = tid; t < nel * NS; t += NT) {
-            const int el = t / NS, q = t - el * NS;
+        //      line families (compile-time strides), correction with the common
+        //      fluxes, negate, source.
+        for (unsigned t = tid; t < (unsigned)nel * NS; t += NT) {
+            const unsigned el = t / NS, q = t - el * NS;
+            const unsigned qi = q % M, qj = (q / M) % M, qk = q / (M * M);
             const T *Ue = sU + el * NV * NS;
             const T *Fe = sF + el * 9 * NS;
-            const T *FIe = sFI + el * 6 * CH;
             // g[3a+k] = sum_d n_d,k (corrected d u_a / d xi_d) = det J d u_a / d x_k
             T g[9], mom[3] = {T(0), T(0), T(0)}, dissP = T(0);
 #pragma unroll
             for (int k = 0; k < 9; ++k) g[k] = T(0);
-#pragma unroll 1
-            for (int d = 0; d < 3; ++d) {
-                const int str = d == 0 ? 1 : (d == 1 ? M : M * M);
-                const int id = (q / str) % M;
-                const int base = q - id * str;
-                const int fp = d == 0 ? q / M : (d == 1 ? (q % M) + M * (q / (M * M)) : q % (M * M));
-                const T *FIm = FIe + (2 * d) * CH + fp;
-                const T *FIp = FIe + (2 * d + 1) * CH + fp;
+            auto direction = [&](auto dc) {
+                constexpr int d = decltype(dc)::value;
+                constexpr int str = d == 0 ? 1 : (d == 1 ? M : M * M);
+                const unsigned id = d == 0 ? qi : (d == 1 ? qj : qk);
+                const unsigned base = q - id * str;
+                const unsigned fp = d == 0 ? qj + M * qk : (d == 1 ? qi + M * qk : qi + M * qj);
+                const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + fp;
+                const T *FIp = FIm + EMAX * CHP;
                 const T gld = gl[id], grd = gr[id];
                 const T *Fd = Fe + 3 * d * NS;
+                const T *Drow = Dt + id * M;
                 T du[3] = {T(0), T(0), T(0)}, df[3] = {T(0), T(0), T(0)};
 #pragma unroll
                 for (int l = 0; l < M; ++l) {
-                    const int ql = base + l * str;
-                    const T w = Dt[id * M + l];
+                    const unsigned ql = base + l * str;
+                    const T w = Drow[l];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         du[a] = fma(w, Ue[(1 + a) * NS + ql], du[a]);
@@ -527,7 +606,12 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
                     g[3 * a + 2] = fma(cd, n2, g[3 * a + 2]);
                 }
                 dissP = fma(gld, FIm[0], fma(grd, FIp[0], dissP));
-            }
+            };
+            direction(Dir<0>{});
+            __builtin_amdgcn_sched_barrier(0);
+            direction(Dir<1>{});
+            __builtin_amdgcn_sched_barrier(0);
+            direction(Dir<2>{});
             T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
             // P: -(1/detJ) [ zeta (det J div V) + dissipation ]
             const T divV = g[0] + g[4] + g[8];
@@ -546,11 +630,12 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 // ---------------------------------------------------------------------------
 // launch
 // ---------------------------------------------------------------------------
-template <int P, typename T>
+template <int P, typename T, bool DIAG>
 int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<T> &c,
                hipStream_t s)
 {
-    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    constexpr int M = P + 1, NS = M * M * M;
+    constexpr int CHP = TraceLayout<M, T>::CHP;
     constexpr int EMAX = Shape<P, T>::EMAX, NT = Shape<P, T>::NT;
     constexpr int TEMAX = TraceShape<P, T>::EMAX, TNT = TraceShape<P, T>::NT;
     const int ne = (int)pl->ne;
@@ -561,9 +646,9 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
     const int nbatch = (ne + E - 1) / E;
     const int TE = TEMAX < ne ? TEMAX : ne;
     const int nbatch_tr = (ne + TE - 1) / TE;
-    const size_t lds_tr = ((size_t)TEMAX * NV * NS + 2 * M) * sizeof(T);
-    const size_t lds_fu = ((size_t)EMAX * (NV + 9) * NS + (size_t)EMAX * 6 * NTR * NF +
-                           OpsLayout<M>::size + 24) * sizeof(T) + 6 * EMAX * sizeof(int);
+    const size_t lds_tr = ((size_t)TEMAX * NV * NS + 2 * M) * sizeof(T) + 6 * TEMAX * sizeof(int);
+    const size_t lds_fu =
+        ((size_t)EMAX * (NV + 9) * NS + (size_t)6 * EMAX * CHP + OpsLayout<M>::size + 24) * sizeof(T);
     static int grid_tr = 0, grid_fu = 0;
     if (!grid_tr) {
         int dev = 0, ncu = 0, occ_tr = 0, occ_fu = 0;
@@ -571,20 +656,20 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
         if (int rc = check_hip(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev),
                                "hipDeviceGetAttribute"))
             return rc;
-        if (int rc = check_hip(hipFuncSetAttribute((const void *)k_trace<P, T>,
+        if (int rc = check_hip(hipFuncSetAttribute((const void *)k_trace<P, T, DIAG>,
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    (int)lds_tr), "hipFuncSetAttribute(k_trace)"))
             return rc;
-        if (int rc = check_hip(hipFuncSetAttribute((const void *)k_fused<P, T>,
+        if (int rc = check_hip(hipFuncSetAttribute((const void *)k_fused<P, T, DIAG>,
                                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                                    (int)lds_fu), "hipFuncSetAttribute(k_fused)"))
             return rc;
         if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                   &occ_tr, (const void *)k_trace<P, T>, TNT, lds_tr),
+                                   &occ_tr, (const void *)k_trace<P, T, DIAG>, TNT, lds_tr),
                                "occupancy(k_trace)"))
             return rc;
         if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                   &occ_fu, (const void *)k_fused<P, T>, NT, lds_fu),
+                                   &occ_fu, (const void *)k_fused<P, T, DIAG>, NT, lds_fu),
                                "occupancy(k_fused)"))
             return rc;
         if (occ_tr < 1 || occ_fu < 1)
@@ -596,13 +681,13 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
     const unsigned gfu = (unsigned)min(nbatch, grid_fu);
     {
         ProfScope ps(pl, FR_K_TRACE, s);
-        hipLaunchKernelGGL((k_trace<P, T>), dim3(gtr), dim3(TNT), lds_tr, s, U, TR, ops, c, ne, TE,
-                           nbatch_tr);
+        hipLaunchKernelGGL((k_trace<P, T, DIAG>), dim3(gtr), dim3(TNT), lds_tr, s, U, TR, ops, c,
+                           pl->nx, pl->ny, pl->nz, TE, nbatch_tr);
     }
     {
         ProfScope ps(pl, FR_K_FUSED, s);
-        hipLaunchKernelGGL((k_fused<P, T>), dim3(gfu), dim3(NT), lds_fu, s, U, TR, R, ops, c,
-                           pl->nx, pl->ny, pl->nz, E, nbatch);
+        hipLaunchKernelGGL((k_fused<P, T, DIAG>), dim3(gfu), dim3(NT), lds_fu, s, U, TR, R, ops, c,
+                           ne, E, nbatch);
     }
     return check_hip(hipGetLastError(), "fused residual launch");
 }
@@ -611,13 +696,14 @@ template <typename T>
 int dispatch_fused(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<T> &c,
                    hipStream_t s)
 {
+    const bool dg = c.diag != 0;
     switch (pl->p) {
-        case 1: return fused_impl<1, T>(pl, U, R, TR, ops, c, s);
-        case 2: return fused_impl<2, T>(pl, U, R, TR, ops, c, s);
-        case 3: return fused_impl<3, T>(pl, U, R, TR, ops, c, s);
-        case 4: return fused_impl<4, T>(pl, U, R, TR, ops, c, s);
-        case 5: return fused_impl<5, T>(pl, U, R, TR, ops, c, s);
-        case 6: return fused_impl<6, T>(pl, U, R, TR, ops, c, s);
+        case 1: return dg ? fused_impl<1, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<1, T, false>(pl, U, R, TR, ops, c, s);
+        case 2: return dg ? fused_impl<2, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<2, T, false>(pl, U, R, TR, ops, c, s);
+        case 3: return dg ? fused_impl<3, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<3, T, false>(pl, U, R, TR, ops, c, s);
+        case 4: return dg ? fused_impl<4, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<4, T, false>(pl, U, R, TR, ops, c, s);
+        case 5: return dg ? fused_impl<5, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<5, T, false>(pl, U, R, TR, ops, c, s);
+        case 6: return dg ? fused_impl<6, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<6, T, false>(pl, U, R, TR, ops, c, s);
     }
     return set_error(FR_EINVAL, "order %d", pl->p);
 }
@@ -628,7 +714,9 @@ int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s)
 {
     const int m = pl->m;
     const size_t esz = pl->precision == FR_F64 ? 8 : 4;
-    const size_t tr_bytes = (size_t)6 * pl->ne * NTR * m * m * esz;
+    const size_t w = 16 / esz;
+    const size_t chp = (NTR * m * m + w - 1) / w * w;
+    const size_t tr_bytes = (size_t)6 * pl->ne * chp * esz;
     if (int rc = ensure_scratch(pl->traces, tr_bytes)) return rc;
     if (pl->precision == FR_F64)
         return dispatch_fused<double>(pl, (const double *)U, (double *)R, (double *)pl->traces.ptr,

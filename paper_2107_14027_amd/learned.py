@@ -1,0 +1,161 @@
+"""Learned initial guess study: pseudo-iterations per physical step with the
+MLP guess versus polynomial extrapolation, at an identical tolerance.
+
+Protocol (dual time stepping, BDF2, RK4 pseudo-steps, Taylor-Green field):
+  step 1 BDF1 from the initial state, step 2 linear extrapolation, steps >= 3
+  quadratic extrapolation; training rows (raw features, converged target) are
+  sampled from every converged step >= 3 of the training phase; the network is fitted
+  (normalisation from the rows, Adam); then the evaluation phase runs twice
+  from the identical state at the end of training: once with extrapolation,
+  once with the network, recording the completed pseudo-steps of every step.
+Every arithmetic step runs in the HIP library; torch only holds the arrays.
+"""
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import binding as B
+from . import inputs
+
+
+class Diverged(RuntimeError):
+    pass
+
+
+def log(*a):
+    print("[learned]", *a, file=sys.stderr, flush=True)
+
+
+def run(p=3, N=16, dt=1e-2, dtau=1e-3, tol=1e-6, max_iters=4000, train_steps=200,
+        eval_steps=200, samples_per_step=1 << 14, epochs=2000, lr=2e-3, batch=1 << 16,
+        zeta=4.0, Re=1600.0, Lr=1.0 / (2.0 * math.pi), seed=5, precision=B.FR_F64):
+    import torch
+    nu, T = inputs.nu_T_from_length(Re, Lr)
+    n = (N, N, N)
+    plan = B.Plan(p, n, zeta, nu, T, precision=precision)
+    ns = plan.state_len
+    npts = ns // 13
+    U0 = inputs.tgv(p, n)
+    hist = [torch.tensor(U0, device="cuda")]
+    rng = np.random.default_rng(seed)
+
+    def step(guess, Un, Unm1):
+        U = guess.clone()
+        rc, it, res = B.fr_dual_step(plan.handle, U, Un, Unm1, dt, dtau, tol, max_iters,
+                                     raise_on_error=False)
+        if rc not in (B.FR_OK, B.FR_ENOCONV):
+            raise Diverged("pseudo-iteration failed (status %d, residual %g after %d steps)"
+                           % (rc, res, it))
+        return U, it, res, rc
+
+    def initial_residual(guess, Un, Unm1):
+        U = guess.clone()
+        rc, it, res = B.fr_dual_step(plan.handle, U, Un, Unm1, dt, dtau, tol, 0,
+                                     raise_on_error=True)
+        return res
+
+    G = torch.empty_like(hist[0])
+    X = torch.zeros((train_steps * samples_per_step, 12), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((train_steps * samples_per_step, 4), dtype=torch.float32, device="cuda")
+    nrows = 0
+    train_log = []
+    t0 = time.time()
+    for s in range(1, train_steps + 1):
+        if s == 1:
+            U, it, res, rc = step(hist[-1], hist[-1], None)
+        else:
+            order = 1 if s == 2 else 2
+            B.fr_guess_extrap(plan.handle, hist[-1], hist[-2], hist[-3] if order == 2 else None,
+                              order, G)
+            U, it, res, rc = step(G, hist[-1], hist[-2])
+            if s >= 3 and samples_per_step and rc == 0:
+                stride = max(1, npts // samples_per_step)
+                k = min(samples_per_step, (npts - 1) // stride + 1)
+                off = int(rng.integers(0, npts - (k - 1) * stride))
+                B.fr_mlp_sample(plan.handle, hist[-1], hist[-2], hist[-3], U, off, stride, k,
+                                X[nrows:nrows + k], Y[nrows:nrows + k])
+                nrows += k
+        train_log.append((it, res, rc))
+        hist.append(U)
+        hist = hist[-3:]
+        if s % 10 == 0 or s <= 3:
+            log("train step %d: %d pseudo-steps, residual %.3e, rc %d (%.0f s)" %
+                (s, it, res, rc, time.time() - t0))
+    # fit the network
+    state = B.mlp_new_state(seed)
+    Xr, Yr = X[:nrows], Y[:nrows]
+    B.fr_mlp_fit_norm(plan.handle, state, Xr, Yr)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    losses = []
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    for e in range(1, epochs + 1):
+        idx = torch.randint(0, nrows, (min(batch, nrows),), device="cuda", generator=gen)
+        B.fr_mlp_train_step(plan.handle, state, Xr[idx].contiguous(), Yr[idx].contiguous(), lr, e,
+                            loss)
+        if e == 1 or e % 250 == 0:
+            torch.cuda.synchronize()
+            losses.append((e, float(loss.item())))
+    log("training loss (normalised MSE): %s" % losses)
+    # evaluation from the identical state
+    start = [h.clone() for h in hist]
+    E = torch.empty_like(G)
+    res_by = {}
+    for mode in ("extrap", "mlp"):
+        hs = [h.clone() for h in start]
+        its, r0s, rcs, fallback = [], [], [], 0
+        t1 = time.time()
+        for s in range(eval_steps):
+            B.fr_guess_extrap(plan.handle, hs[-1], hs[-2], hs[-3], 2, E)
+            r_ex = initial_residual(E, hs[-1], hs[-2])
+            guess, r0 = E, r_ex
+            if mode == "mlp":
+                B.fr_mlp_guess(plan.handle, state, hs[-1], hs[-2], hs[-3], G)
+                r_ml = initial_residual(G, hs[-1], hs[-2])
+                if r_ml <= r_ex:
+                    guess, r0 = G, r_ml
+                else:
+                    fallback += 1
+            r0s.append(r0)
+            U, it, res, rc = step(guess, hs[-1], hs[-2])
+            its.append(it)
+            rcs.append(rc)
+            hs.append(U)
+            hs = hs[-3:]
+            if s % 20 == 0:
+                log("%s step %d: %d pseudo-steps, initial residual %.3e, rc %d" % (mode, s, it, r0, rc))
+        res_by[mode] = {"iters": its, "initial_residual": r0s, "rc": rcs, "fallback": fallback,
+                        "seconds": time.time() - t1}
+        log("%s: mean %.2f pseudo-steps/step, median initial residual %.3e, %d capped, %d fallbacks" %
+            (mode, np.mean(its), np.median(r0s), sum(1 for r in rcs if r != 0), fallback))
+    plan.close()
+    ex, ml = res_by["extrap"], res_by["mlp"]
+    return {
+        "config": {"p": p, "lattice": N, "dt": dt, "dtau": dtau, "tol": tol,
+                   "max_iters": max_iters, "train_steps": train_steps, "eval_steps": eval_steps,
+                   "samples": nrows, "epochs": epochs, "lr": lr, "zeta": zeta, "nu": nu, "T": T},
+        "train_iters_mean": float(np.mean([t[0] for t in train_log])),
+        "train_capped": int(sum(1 for t in train_log if t[2] != 0)),
+        "loss_curve": losses,
+        "extrap_iters_mean": float(np.mean(ex["iters"])),
+        "mlp_iters_mean": float(np.mean(ml["iters"])),
+        "extrap_initial_residual_median": float(np.median(ex["initial_residual"])),
+        "mlp_initial_residual_median": float(np.median(ml["initial_residual"])),
+        "extrap_capped": int(sum(1 for r in ex["rc"] if r != 0)),
+        "mlp_capped": int(sum(1 for r in ml["rc"] if r != 0)),
+        "mlp_fallbacks": ml["fallback"],
+        "iters_reduction": 1.0 - float(np.mean(ml["iters"])) / max(1e-9, float(np.mean(ex["iters"]))),
+        "extrap_iters": ex["iters"], "mlp_iters": ml["iters"],
+    }
+
+
+if __name__ == "__main__":
+    kw = json.loads(sys.argv[1]) if len(sys.argv) > 1 else {}
+    try:
+        out = run(**kw)
+    except Diverged as e:
+        out = {"config": kw, "diverged": str(e)}
+    print(json.dumps(out), flush=True)
