@@ -58,7 +58,9 @@ typedef enum fr_option {
     FR_OPT_PRECISION = 1, /* FR_F64 (default) or FR_F32: working precision of the residual */
     FR_OPT_VARIANT = 2,   /* FR_FUSED (default) or FR_UNFUSED                              */
     FR_OPT_BLOCK = 3,     /* elements per workgroup of the fused kernel; 0 = tuned default  */
-    FR_OPT_PROFILE = 4    /* 1: record HIP events around every kernel launch (see below)   */
+    FR_OPT_PROFILE = 4,   /* 1: record HIP events around every kernel launch (see below)   */
+    FR_OPT_GUESS_BASE = 5 /* extrapolation the learned guess corrects: 2 quadratic (default),
+                             1 linear                                                      */
 } fr_option;
 
 /* Kernel identifiers for fr_plan_kernel_stats. */
@@ -162,10 +164,12 @@ int fr_guess_extrap(fr_plan *plan, const double *Un, const double *Unm1, const d
  * Learned initial guess (not in the paper: the pseudo-time iteration still
  * decides the converged state, the guess only sets where it starts).
  * A pointwise network 12 -> 64 -> 64 -> 4 with tanh hidden layers predicts a
- * correction to the quadratic extrapolation of P, u, v, w:
+ * correction to a polynomial extrapolation E of P, u, v, w (the plan option
+ * FR_OPT_GUESS_BASE: quadratic E = 3 U^n - 3 U^{n-1} + U^{n-2}, the default, or
+ * linear E = 2 U^n - U^{n-1}):
  *   raw features  [U^n_c, U^n_c - U^{n-1}_c, U^n_c - 2 U^{n-1}_c + U^{n-2}_c], c = P,u,v,w
  *   x = (raw - mu) * inv_sd,   y = W3 tanh(W2 tanh(W1 x + b1) + b2) + b3
- *   G_c = 3 U^n_c - 3 U^{n-1}_c + U^{n-2}_c + y_sd_c * y_c
+ *   G_c = E_c + y_sd_c * y_c
  * Weights are rounded to bfloat16 for the matrix-core products, which
  * accumulate in float; activations are rounded to bfloat16 between layers.
  *
@@ -179,7 +183,7 @@ int fr_guess_extrap(fr_plan *plan, const double *Un, const double *Unm1, const d
  * W3 = b3 = 0 so that the initial guess equals the extrapolation), identity
  * normalisation and zero moments, and synchronises the stream.
  * Training rows: X[n][12] raw features and Y[n][4] raw targets
- * (U^{n+1}_c minus its quadratic extrapolation), float, device memory.
+ * (U^{n+1}_c minus its extrapolation E_c), float, device memory.
  */
 size_t fr_mlp_state_floats(void);
 int fr_mlp_init(float *state, uint64_t seed, fr_stream_t s);
@@ -213,8 +217,8 @@ int fr_mlp_grad(fr_plan *plan, const float *state, const float *X, const float *
 int fr_mlp_train_step(fr_plan *plan, float *state, const float *X, const float *Y, int64_t n,
                       float lr, int step, float *loss, fr_stream_t s);
 
-/* G (double state array) = network guess for P, u, v, w and quadratic
- * extrapolation for the auxiliary variables. */
+/* G (double state array) = network guess for P, u, v, w and the same
+ * extrapolation E for the auxiliary variables. */
 int fr_mlp_guess(fr_plan *plan, const float *state, const double *Un, const double *Unm1,
                  const double *Unm2, double *G, fr_stream_t s);
 

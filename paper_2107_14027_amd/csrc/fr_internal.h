@@ -56,6 +56,7 @@ struct fr_plan {
     int precision;  // FR_F64 / FR_F32
     int variant;    // FR_FUSED / FR_UNFUSED
     int block;      // elements per workgroup override (0 = default)
+    int guess_base = 2;  // extrapolation order the learned guess corrects
     int device;
     // host copies of the operators (double)
     double x[8], w[8], D[64], lm[8], lp[8], gl[8], gr[8], Dt[64];

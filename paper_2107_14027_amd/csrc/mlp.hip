@@ -9,8 +9,10 @@
 //                      -> y = W3 h2 + b3 (4)
 // Features (normalised, x = (raw - mu) * inv_sd):
 //   raw = [U^n_c,  U^n_c - U^{n-1}_c,  U^n_c - 2 U^{n-1}_c + U^{n-2}_c]  for c = P, u, v, w
-// Guess:  G_c = 3 U^n_c - 3 U^{n-1}_c + U^{n-2}_c + y_sd_c * y_c        (c = P, u, v, w)
-//         G_v = 3 U^n_v - 3 U^{n-1}_v + U^{n-2}_v                       (auxiliary v)
+// Guess:  G_c = E_c + y_sd_c * y_c        (c = P, u, v, w)
+//         G_v = E_v                         (auxiliary v)
+// with E the quadratic (3 U^n - 3 U^{n-1} + U^{n-2}) or linear (2 U^n - U^{n-1})
+// extrapolation, written exactly as the plain extrapolation kernel writes it.
 //
 // Matrix-core mapping (v_mfma_f32_16x16x16_bf16, one wave = 16 points): the
 // weights are the A operand and the activations, transposed (units x points),
@@ -159,12 +161,19 @@ __device__ __forceinline__ void raw_features(const double *Un, const double *Unm
     }
 }
 
+// Polynomial extrapolation, the same expressions as the plain extrapolation kernel.
+__device__ __forceinline__ double extrap(double a, double b, double d, int order)
+{
+    return order == 1 ? 2.0 * a - b : 3.0 * (a - b) + d;
+}
+
 // Guess kernel: waves loop over 16-point tiles (flat point index over (e, q)).
 __global__ void __launch_bounds__(256) k_mlp_guess(const float *__restrict__ S,
                                                    const double *__restrict__ Un,
                                                    const double *__restrict__ Unm1,
                                                    const double *__restrict__ Unm2,
-                                                   double *__restrict__ G, int64_t npts, int ns)
+                                                   double *__restrict__ G, int64_t npts, int ns,
+                                                   int order)
 {
     const int lane = threadIdx.x & 63, g = lane >> 4, pi = lane & 15;
     Weights w;
@@ -207,24 +216,24 @@ __global__ void __launch_bounds__(256) k_mlp_guess(const float *__restrict__ S,
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int64_t i = base + (int64_t)v * ns;
-                    G[i] = 3.0 * (Un[i] - Unm1[i]) + Unm2[i] + (double)(ysd[v] * y[v]);
+                    G[i] = extrap(Un[i], Unm1[i], Unm2[i], order) + (double)(ysd[v] * y[v]);
                 }
             }
             for (int v = 4 + g; v < NV; v += 4) {
                 const int64_t i = base + (int64_t)v * ns;
-                G[i] = 3.0 * (Un[i] - Unm1[i]) + Unm2[i];
+                G[i] = extrap(Un[i], Unm1[i], Unm2[i], order);
             }
         }
     }
 }
 
-// Training samples: raw features and raw targets (U^{n+1} - extrapolation) of
+// Training samples: raw features and raw targets (U^{n+1} - extrapolation E) of
 // every point p = offset + s * stride, s < n.
 __global__ void __launch_bounds__(256) k_mlp_sample(const double *__restrict__ Un,
                                                     const double *__restrict__ Unm1,
                                                     const double *__restrict__ Unm2,
                                                     const double *__restrict__ Unp1, int64_t offset,
-                                                    int64_t stride, int64_t n, int ns,
+                                                    int64_t stride, int64_t n, int ns, int order,
                                                     float *__restrict__ X, float *__restrict__ Y)
 {
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n;
@@ -240,7 +249,7 @@ __global__ void __launch_bounds__(256) k_mlp_sample(const double *__restrict__ U
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int64_t i = base + (int64_t)c * ns;
-            Y[s * NO + c] = Unp1 ? (float)(Unp1[i] - (3.0 * (Un[i] - Unm1[i]) + Unm2[i])) : 0.0f;
+            Y[s * NO + c] = Unp1 ? (float)(Unp1[i] - extrap(Un[i], Unm1[i], Unm2[i], order)) : 0.0f;
         }
     }
 }
@@ -693,7 +702,8 @@ int fr_mlp_sample(fr_plan *pl, const double *Un, const double *Unm1, const doubl
     if (n == 0) return FR_OK;
     const int64_t g = (n + 255) / 256;
     hipLaunchKernelGGL(k_mlp_sample, dim3((unsigned)(g > 4096 ? 4096 : g)), dim3(256), 0,
-                       (hipStream_t)s, Un, Unm1, Unm2, Unp1, offset, stride, n, ns, X, Y);
+                       (hipStream_t)s, Un, Unm1, Unm2, Unp1, offset, stride, n, ns, pl->guess_base,
+                       X, Y);
     return check_hip(hipGetLastError(), "k_mlp_sample launch");
 }
 
@@ -783,7 +793,7 @@ int fr_mlp_guess(fr_plan *pl, const float *state, const double *Un, const double
     int64_t blocks = (tiles + 3) / 4;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_mlp_guess, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)s, state,
-                       Un, Unm1, Unm2, G, npts, ns);
+                       Un, Unm1, Unm2, G, npts, ns, pl->guess_base);
     return check_hip(hipGetLastError(), "k_mlp_guess launch");
 }
 

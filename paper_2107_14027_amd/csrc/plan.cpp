@@ -369,6 +369,10 @@ int fr_plan_set_int(fr_plan *pl, int key, int value)
             if (value != 0 && value != 1) return set_error(FR_EINVAL, "profile %d", value);
             pl->profile = value;
             return FR_OK;
+        case FR_OPT_GUESS_BASE:
+            if (value != 1 && value != 2) return set_error(FR_EINVAL, "guess base %d", value);
+            pl->guess_base = value;
+            return FR_OK;
         default:
             return set_error(FR_EINVAL, "unknown option %d", key);
     }
@@ -382,6 +386,7 @@ int fr_plan_get_int(const fr_plan *pl, int key, int *value)
         case FR_OPT_VARIANT: *value = pl->variant; return FR_OK;
         case FR_OPT_BLOCK: *value = pl->block; return FR_OK;
         case FR_OPT_PROFILE: *value = pl->profile; return FR_OK;
+        case FR_OPT_GUESS_BASE: *value = pl->guess_base; return FR_OK;
         default: return set_error(FR_EINVAL, "unknown option %d", key);
     }
 }

@@ -160,6 +160,10 @@ def test_sample_and_normalisation():
     X = t.zeros((ns, 12), dtype=t.float32, device="cuda")
     Y = t.zeros((ns, 4), dtype=t.float32, device="cuda")
     say("mlp sample")
+    plan.set(B.FR_OPT_GUESS_BASE, 1)
+    Y1 = t.zeros((ns, 4), dtype=t.float32, device="cuda")
+    B.fr_mlp_sample(plan.handle, Ud[2], Ud[1], Ud[0], Ud[3], 1, 2, ns, X, Y1)
+    plan.set(B.FR_OPT_GUESS_BASE, 2)
     B.fr_mlp_sample(plan.handle, Ud[2], Ud[1], Ud[0], Ud[3], 1, 2, ns, X, Y)
     t.cuda.synchronize()
     pts = 1 + 2 * np.arange(ns)
@@ -172,6 +176,8 @@ def test_sample_and_normalisation():
         tgt[:, c] = f - (3.0 * (a - b) + d)
     assert np.array_equal(X.cpu().numpy(), raw.astype(np.float32))
     assert np.array_equal(Y.cpu().numpy(), tgt.astype(np.float32))
+    tgt1 = np.stack([Us[3][e, c, q] - (2.0 * Us[2][e, c, q] - Us[1][e, c, q]) for c in range(4)], 1)
+    assert np.array_equal(Y1.cpu().numpy(), tgt1.astype(np.float32))
     st = B.mlp_new_state(0)
     B.fr_mlp_fit_norm(plan.handle, st, X, Y)
     t.cuda.synchronize()
@@ -191,11 +197,15 @@ def test_guess_is_extrapolation_plus_network():
     G = t.empty_like(Us[0])
     E = t.empty_like(Us[0])
     say("mlp guess")
-    B.fr_guess_extrap(plan.handle, Us[2], Us[1], Us[0], 2, E)
     st = B.mlp_new_state(3)
-    B.fr_mlp_guess(plan.handle, st, Us[2], Us[1], Us[0], G)
-    t.cuda.synchronize()
-    assert t.equal(G, E)       # zero last layer: exactly the extrapolation
+    for base in (1, 2):        # zero last layer: exactly the extrapolation the network corrects
+        plan.set(B.FR_OPT_GUESS_BASE, base)
+        B.fr_guess_extrap(plan.handle, Us[2], Us[1], Us[0], base, E)
+        B.fr_mlp_guess(plan.handle, st, Us[2], Us[1], Us[0], G)
+        t.cuda.synchronize()
+        assert t.equal(G, E), base
+    plan.set(B.FR_OPT_GUESS_BASE, 2)
+    B.fr_guess_extrap(plan.handle, Us[2], Us[1], Us[0], 2, E)
     st = random_state(14, scale=0.2)
     B.fr_mlp_guess(plan.handle, st, Us[2], Us[1], Us[0], G)
     npts = 12 * 64
