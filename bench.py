@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-hbm-ref", action="store_true", help="skip the copy/fill/read reference")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-guess study (pseudo-iterations per physical step)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -280,6 +282,32 @@ def main():
                          "lattices and fields: " + sample}
         del host
 
+    learned = None
+    if not args.no_learned:
+        from paper_2107_14027_amd import learned as L
+        t0 = time.perf_counter()
+        r = L.run(guess_base=1)
+        m = r["modes"]
+        learned = {
+            "unit": "pseudo-iterations per physical step (mean over the evaluation steps)",
+            "workload": "dual time stepping BDF2 + RK4 pseudo-steps, Taylor-Green Re 1600, p=%d, "
+                        "%d^3 hexes, dt=%g, dtau=%g, tol %g, cap %d; %d training steps, %d "
+                        "evaluation steps from the identical state" %
+                        (r["config"]["p"], r["config"]["lattice"], r["config"]["dt"],
+                         r["config"]["dtau"], r["config"]["tol"], r["config"]["max_iters"],
+                         r["config"]["train_steps"], r["config"]["eval_steps"]),
+            "learned": round(m["mlp"]["iters_mean"], 2),
+            "quadratic_extrap": round(m["extrap"]["iters_mean"], 2),
+            "linear_extrap": round(m["extrap1"]["iters_mean"], 2),
+            "learned_with_residual_fallback": round(m["mlp_fallback"]["iters_mean"], 2),
+            "capped": {k: m[v]["capped"] for k, v in (("learned", "mlp"), ("quadratic_extrap", "extrap"),
+                                                      ("linear_extrap", "extrap1"))},
+            "learned_vs_quadratic": round(r["mlp_vs_quadratic_iters"], 4),
+            "learned_vs_linear": round(r["mlp_vs_linear_iters"], 4),
+            "training_loss": r["loss_curve"][-1][1],
+            "seconds": round(time.perf_counter() - t0, 1)}
+        log("learned guess: %s" % learned)
+
     out = {
         "metric": "fused RHS GDOF/s vs plain FP64 (p=1..6); pseudo-iters/step learned vs extrap",
         "value": round(value, 3),
@@ -304,6 +332,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "learned_guess": learned,
         "sweep": sweep,
         "kernel_ms": {str(p): {"trace": round(kstats[p]["trace_ms"], 4),
                                "fused": round(kstats[p]["fused_ms"], 4)} for p in kstats},
