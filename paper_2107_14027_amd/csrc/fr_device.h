@@ -53,12 +53,14 @@ __device__ __forceinline__ void line_of(int d, int a, int b, int &base, int &str
 // Jacobian) (S n_hat)_i = S_id exactly, and the product with the unit normal is
 // skipped; the result has the same bits as the general expression, whose other
 // terms are exact zeros and whose product with 1 is exact.
-template <int M, typename T>
+// VS is the distance between consecutive variables of Ue (m^3 unless the
+// caller pads its lines).
+template <int M, typename T, int VS = M * M * M>
 __device__ __forceinline__ T trace_value(const T *__restrict__ Ue, int d, int base, int stride,
                                          const T *__restrict__ lf, const T nh[3], int c,
                                          bool diag = false)
 {
-    constexpr int NS = M * M * M;
+    constexpr int NS = VS;
     T acc = T(0);
     if (c < 4) {
         const T *X = Ue + c * NS + base;

@@ -219,6 +219,16 @@ struct TraceLayout {
     static constexpr int CHV = CHP / W;
 };
 
+// LDS point pitch of the trace kernel: at p = 3, 5 its x-face reads walk the
+// points with a stride of one x-line per lane; padding every x-line by one
+// value makes that stride odd, so the reads of a wave spread over the banks.
+template <int M>
+struct TracePad {
+    static constexpr int MP = (M % 2 == 0 && M >= 4) ? M + 1 : M;
+    static constexpr int NSP = MP * M * M;
+    __device__ __forceinline__ static unsigned idx(unsigned q) { return q + (MP - M) * (q / M); }
+};
+
 // Register staging of one batch's contiguous state block U[e0 .. e0+nel).
 // Chunk k of W values (W = 16 bytes) belongs to thread k mod NT.  A full batch
 // (count == NVAL) whose start is 16-byte aligned takes a branch-free path with
@@ -252,6 +262,25 @@ struct StateStage {
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 if (v0 + w < count) r[i * W + w] = src[v0 + w];
+        }
+    }
+    // store into LDS with the x-lines of every variable padded to TracePad<M>::MP
+    template <int M>
+    __device__ __forceinline__ void store_padded(T *__restrict__ dst, int count, int tid) const
+    {
+        constexpr int NS = M * M * M, NSP = TracePad<M>::NSP;
+        static_assert(TracePad<M>::MP == M || NS % W == 0, "a chunk must not straddle variables");
+        if (TracePad<M>::MP == M) {
+            store(dst, count, tid);
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < PV; ++i) {
+            const unsigned v0 = (tid + i * NT) * W;
+            const unsigned ev = v0 / NS, q = v0 - ev * NS;  // ev = element * NV + variable
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                if ((int)(v0 + w) < count) dst[ev * NSP + TracePad<M>::idx(q + w)] = r[i * W + w];
         }
     }
     __device__ __forceinline__ void store(T *__restrict__ dst, int count, int tid) const
@@ -397,12 +426,13 @@ __global__ void __launch_bounds__((TraceShape<P, T>::NT))
     using TL = TraceLayout<M, T>;
     constexpr int CH = TL::CH, CHV = TL::CHV, W = TL::W;
     constexpr int EMAX = TraceShape<P, T>::EMAX, NT = TraceShape<P, T>::NT;
+    constexpr int MP = TracePad<M>::MP, NSP = TracePad<M>::NSP;
     using OL = OpsLayout<M>;
     using V = typename V16<T>::type;
     const int ne = nx * ny * nz;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sU = reinterpret_cast<T *>(smem_raw);
-    T *sl = sU + EMAX * NV * NS;  // lm[M], lp[M]
+    T *sl = sU + EMAX * NV * NSP;  // lm[M], lp[M]
     int *sNb = reinterpret_cast<int *>(sl + 2 * M);
     if (threadIdx.x < 2 * M) sl[threadIdx.x] = ops[OL::lm + threadIdx.x];
 
@@ -418,7 +448,7 @@ __global__ void __launch_bounds__((TraceShape<P, T>::NT))
         const int e0 = b * E;
         const int nel = min(E, ne - e0);
         __syncthreads();
-        st.store(sU, nel * NV * NS, tid);
+        st.template store_padded<M>(sU, nel * NV * NS, tid);
         neighbour_table<NT>(sNb, e0, nel, nx, ny, nz);
         const int bn = b + gridDim.x;
         __syncthreads();
@@ -440,10 +470,11 @@ __global__ void __launch_bounds__((TraceShape<P, T>::NT))
                 const unsigned o = k * W + w;
                 const unsigned cc = o / NF, fp = o - cc * NF;
                 const unsigned a = fp % M, bb = fp / M;
-                const int stride = d == 0 ? 1 : (d == 1 ? M : M * M);
-                const int base = d == 0 ? M * fp : (d == 1 ? a + M * M * bb : fp);
+                const int stride = d == 0 ? 1 : (d == 1 ? MP : MP * M);
+                const int base = d == 0 ? MP * fp : (d == 1 ? a + MP * M * bb : a + MP * bb);
                 x[w] = o < (unsigned)CH
-                           ? trace_value<M, T>(sU + el * NV * NS, d, base, stride, sl + s * M, nh, cc, DIAG)
+                           ? trace_value<M, T, NSP>(sU + el * NV * NSP, d, base, stride, sl + s * M, nh,
+                                                    cc, DIAG)
                            : T(0);
             }
             const int nb = sNb[el * 6 + f];
@@ -646,7 +677,8 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
     const int nbatch = (ne + E - 1) / E;
     const int TE = TEMAX < ne ? TEMAX : ne;
     const int nbatch_tr = (ne + TE - 1) / TE;
-    const size_t lds_tr = ((size_t)TEMAX * NV * NS + 2 * M) * sizeof(T) + 6 * TEMAX * sizeof(int);
+    const size_t lds_tr =
+        ((size_t)TEMAX * NV * TracePad<M>::NSP + 2 * M) * sizeof(T) + 6 * TEMAX * sizeof(int);
     const size_t lds_fu =
         ((size_t)EMAX * (NV + 9) * NS + (size_t)6 * EMAX * CHP + OpsLayout<M>::size + 24) * sizeof(T);
     static int grid_tr = 0, grid_fu = 0;

@@ -46,7 +46,8 @@ def test_lds_fits(p, prec):
     ns = m ** 3
     te, e = shape("FR_TE%d_%s" % (p, prec)), shape("FR_E%d_%s" % (p, prec))
     nt, tnt = shape("FR_NT%d_%s" % (p, prec)), shape("FR_TNT%d_%s" % (p, prec))
-    assert (te * NV * ns + 2 * m) * esz + 6 * te * 4 <= LDS_BYTES
+    mp = m + 1 if (m % 2 == 0 and m >= 4) else m        # padded x-line pitch of k_trace
+    assert (te * NV * mp * m * m + 2 * m) * esz + 6 * te * 4 <= LDS_BYTES
     assert (e * (NV + 9) * ns + 6 * e * chp + m * m + 4 * m + 24) * esz <= LDS_BYTES
     assert nt % 64 == 0 and tnt % 64 == 0 and nt >= 2 * m and tnt >= 2 * m
 
