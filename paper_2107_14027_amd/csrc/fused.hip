@@ -120,31 +120,31 @@ template <> struct Shape<6, float> { static constexpr int EMAX = FR_E6_F, NT = F
 
 // Shape of the trace kernel (it carries no face data and prefers larger batches).
 #ifndef FR_TE1_D
-#define FR_TE1_D 32
+#define FR_TE1_D 64
 #endif
 #ifndef FR_TNT1_D
 #define FR_TNT1_D 256
 #endif
 #ifndef FR_TE2_D
-#define FR_TE2_D 8
+#define FR_TE2_D 16
 #endif
 #ifndef FR_TNT2_D
 #define FR_TNT2_D 256
 #endif
 #ifndef FR_TE3_D
-#define FR_TE3_D 4
+#define FR_TE3_D 8
 #endif
 #ifndef FR_TNT3_D
 #define FR_TNT3_D 256
 #endif
 #ifndef FR_TE4_D
-#define FR_TE4_D 2
+#define FR_TE4_D 4
 #endif
 #ifndef FR_TNT4_D
 #define FR_TNT4_D 256
 #endif
 #ifndef FR_TE5_D
-#define FR_TE5_D 1
+#define FR_TE5_D 2
 #endif
 #ifndef FR_TNT5_D
 #define FR_TNT5_D 256
@@ -153,7 +153,7 @@ template <> struct Shape<6, float> { static constexpr int EMAX = FR_E6_F, NT = F
 #define FR_TE6_D 1
 #endif
 #ifndef FR_TNT6_D
-#define FR_TNT6_D 256
+#define FR_TNT6_D 512
 #endif
 #ifndef FR_TE1_F
 #define FR_TE1_F 64
@@ -174,7 +174,7 @@ template <> struct Shape<6, float> { static constexpr int EMAX = FR_E6_F, NT = F
 #define FR_TNT3_F 256
 #endif
 #ifndef FR_TE4_F
-#define FR_TE4_F 2
+#define FR_TE4_F 4
 #endif
 #ifndef FR_TNT4_F
 #define FR_TNT4_F 256
