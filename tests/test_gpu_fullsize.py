@@ -1,0 +1,98 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times: the order sweep (p = 1..6 on 128^3 .. 40^3 hexes, seeded Fourier
+fields) in FP64 and FP32, fused and unfused, compared with the CPU oracle on
+sampled elements (periodic corners and faces included); the 64^3, p = 4
+manufactured solution; and the design order of accuracy of the GPU residual
+against the closed-form operator."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2107_14027_amd import binding as B
+from paper_2107_14027_amd import inputs
+from gpu_util import NU, T_CFG, TOL, ZETA, gpu_residual, rel, say
+from test_oracle_residual import sines_exact_residual
+
+pytestmark = pytest.mark.gpu
+
+LATTICE = {1: 128, 2: 85, 3: 64, 4: 51, 5: 43, 6: 40}
+TRELAX = T_CFG
+
+
+def sample(n, k, seed):
+    nx, ny, nz = n
+    ne = nx * ny * nz
+    corners = [0, nx - 1, nx * (ny - 1), ne - 1, ne - nx, nx * ny * (nz - 1)]
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([corners, rng.choice(ne, size=k, replace=False)]))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_order_sweep_full_size_sampled(p):
+    import torch
+    N = LATTICE[p]
+    n = (N, N, N)
+    say("full size p=%d %d^3" % (p, N))
+    Ud = inputs.fourier(p, n, seed=1000 + p, device="cuda")
+    Uh = Ud.cpu().numpy()
+    sel = sample(n, 24, seed=p)
+    # the FP32 path is compared with the oracle on the FP32-rounded state, so that
+    # only the kernel's arithmetic is measured (input rounding alone, amplified by
+    # the derivative operator, is of the order of the FP32 bound at high order)
+    Ro = {B.FR_F64: oracle.residual_elems(p, n, Uh, sel, ZETA, NU, TRELAX),
+          B.FR_F32: oracle.residual_elems(p, n, Uh.astype(np.float32).astype(np.float64), sel,
+                                          ZETA, NU, TRELAX)}
+    for prec, var in ((B.FR_F64, B.FR_FUSED), (B.FR_F32, B.FR_FUSED), (B.FR_F64, B.FR_UNFUSED)):
+        plan = B.Plan(p, n, ZETA, NU, TRELAX, precision=prec, variant=var)
+        U = Ud if prec == B.FR_F64 else Ud.float()
+        R = torch.empty_like(U)
+        B.fr_residual(plan.handle, U, R)
+        torch.cuda.synchronize()
+        Rs = R[torch.from_numpy(sel).to("cuda")].double().cpu().numpy()
+        plan.close()
+        del R
+        say("  prec=%d var=%d rel %.2e" % (prec, var, rel(Rs, Ro[prec])))
+        assert rel(Rs, Ro[prec]) <= TOL[prec], (prec, var, rel(Rs, Ro[prec]))
+    del Ud
+    torch.cuda.empty_cache()
+
+
+def test_manufactured_64cubed_p4_sampled():
+    """The 64^3, p = 4 manufactured solution P = u = v = w = sin x sin y sin z."""
+    import torch
+    p, n = 4, (64, 64, 64)
+    say("manufactured 64^3 p=4")
+    U = inputs.sines(p, n)
+    sel = sample(n, 16, seed=44)
+    Ro = {B.FR_F64: oracle.residual_elems(p, n, U, sel, ZETA, NU, TRELAX),
+          B.FR_F32: oracle.residual_elems(p, n, U.astype(np.float32).astype(np.float64), sel,
+                                          ZETA, NU, TRELAX)}
+    Ud = torch.from_numpy(U).to("cuda")
+    for prec in (B.FR_F64, B.FR_F32):
+        plan = B.Plan(p, n, ZETA, NU, TRELAX, precision=prec)
+        Ui = Ud if prec == B.FR_F64 else Ud.float()
+        R = torch.empty_like(Ui)
+        B.fr_residual(plan.handle, Ui, R)
+        torch.cuda.synchronize()
+        Rs = R[torch.from_numpy(sel).to("cuda")].double().cpu().numpy()
+        plan.close()
+        del R
+        say("  prec=%d rel %.2e" % (prec, rel(Rs, Ro[prec])))
+        assert rel(Rs, Ro[prec]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_gpu_design_order(p):
+    """The GPU residual of the interpolated exact state converges to the exact
+    operator at the design rate (at least p - 0.2) in the max norm."""
+    errs = []
+    ns = [4, 8, 16] if p < 3 else [4, 8, 12]
+    for nn in ns:
+        n = (nn, nn, nn)
+        R = gpu_residual(p, n, inputs.sines(p, n), ZETA, NU, TRELAX)
+        errs.append(np.max(np.abs(R[:, :4] - sines_exact_residual(p, n)[:, :4])))
+    rates = [math.log(errs[i] / errs[i + 1]) / math.log(ns[i + 1] / ns[i]) for i in range(2)]
+    say("design order p=%d errors %s rates %s" % (p, errs, rates))
+    assert rates[-1] > p - 0.2, (errs, rates)
