@@ -489,6 +489,18 @@ __global__ void __launch_bounds__((TraceShape<P, T>::NT))
 // ---------------------------------------------------------------------------
 template <int D> struct Dir { static constexpr int value = D; };
 
+// Divergence as line tasks (diagonal Jacobian, p = 6, where it measured faster
+// than the point-wise form; slower from p = 4 down): one thread per
+// (element, field, line) reads the line once, applies the whole operator
+// (uniform entries, scalar registers) and writes the line's corrected
+// derivatives, instead of every point reading its whole line.
+#ifndef FR_LDIV_PMIN
+#define FR_LDIV_PMIN 6
+#endif
+template <int P, bool DIAG> struct LineDiv {
+    static constexpr bool value = DIAG && P >= FR_LDIV_PMIN;
+};
+
 template <int P, typename T, bool DIAG>
 __global__ void __launch_bounds__((Shape<P, T>::NT))
     k_fused(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
@@ -593,67 +605,169 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
         }
         __syncthreads();
 
-        // ---- stages 3, 5, 6: partially corrected divergence along the three
-        //      line families (compile-time strides), correction with the common
-        //      fluxes, negate, source.
-        for (unsigned t = tid; t < (unsigned)nel * NS; t += NT) {
-            const unsigned el = t / NS, q = t - el * NS;
-            const unsigned qi = q % M, qj = (q / M) % M, qk = q / (M * M);
-            const T *Ue = sU + el * NV * NS;
-            const T *Fe = sF + el * 9 * NS;
-            // g[3a+k] = sum_d n_d,k (corrected d u_a / d xi_d) = det J d u_a / d x_k
-            T g[9], mom[3] = {T(0), T(0), T(0)}, dissP = T(0);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) g[k] = T(0);
+        // ---- stages 3, 5, 6 as line tasks (diagonal Jacobian).  Per direction:
+        //      task (element, field, line) with field u_a or Fhat_{d,a}; the
+        //      corrected derivative along the line, in the same fma order as the
+        //      point-wise form.  Velocity derivatives give the auxiliary residual
+        //      at once (stored over S, which is no longer needed) and the
+        //      divergence (accumulated over P); flux derivatives are stored over
+        //      the consumed flux values.  A final pass writes R.
+        if constexpr (LineDiv<P, DIAG>::value) {
+            constexpr int NTASK = EMAX * 6 * NF;
+            constexpr int TPT = (NTASK + NT - 1) / NT;
+            const int ntask = nel * 6 * NF;
+            const T *gD = ops + OL::Dt;   // uniform operator entries
+            const T *gL = ops + OL::gl;
+            const T *gR = ops + OL::gr;
             auto direction = [&](auto dc) {
                 constexpr int d = decltype(dc)::value;
                 constexpr int str = d == 0 ? 1 : (d == 1 ? M : M * M);
-                const unsigned id = d == 0 ? qi : (d == 1 ? qj : qk);
-                const unsigned base = q - id * str;
-                const unsigned fp = d == 0 ? qj + M * qk : (d == 1 ? qi + M * qk : qi + M * qj);
-                const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + fp;
-                const T *FIp = FIm + EMAX * CHP;
-                const T gld = gl[id], grd = gr[id];
-                const T *Fd = Fe + 3 * d * NS;
-                const T *Drow = Dt + id * M;
-                T du[3] = {T(0), T(0), T(0)}, df[3] = {T(0), T(0), T(0)};
+                T outv[TPT][M];
 #pragma unroll
-                for (int l = 0; l < M; ++l) {
-                    const unsigned ql = base + l * str;
-                    const T w = Drow[l];
+                for (int u = 0; u < TPT; ++u) {
+                    const unsigned t = tid + u * NT;
+                    if ((int)t < ntask) {
+                        const unsigned el = t / (6 * NF), r = t - el * (6 * NF);
+                        const unsigned f = r / NF, L = r - f * NF;
+                        const unsigned a = L % M, bb = L / M;
+                        const unsigned base = d == 0 ? M * L : (d == 1 ? a + M * M * bb : L);
+                        const T *fld = f < 3 ? sU + (el * NV + 1 + f) * NS
+                                             : sF + (el * 9 + 3 * d + f - 3) * NS;
+                        const unsigned comp = f < 3 ? 4 + f : f - 2;
+                        const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + comp * NF + L;
+                        const T fm = FIm[0], fpl = FIm[EMAX * CHP];
+                        T in[M];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        du[a] = fma(w, Ue[(1 + a) * NS + ql], du[a]);
-                        df[a] = fma(w, Fd[a * NS + ql], df[a]);
+                        for (int l = 0; l < M; ++l) in[l] = fld[base + l * str];
+#pragma unroll
+                        for (int i = 0; i < M; ++i) {
+                            T v = T(0);
+#pragma unroll
+                            for (int l = 0; l < M; ++l) v = fma(gD[i * M + l], in[l], v);
+                            outv[u][i] = fma(gL[i], fm, fma(gR[i], fpl, v));
+                        }
                     }
                 }
-                const T n0 = geo[3 * d], n1 = geo[3 * d + 1], n2 = geo[3 * d + 2];
+                __syncthreads();  // every read of this direction's flux values is done
+                const T ndd = c.nvec[d][d];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const T cd = fma(gld, FIm[(4 + a) * NF], fma(grd, FIp[(4 + a) * NF], du[a]));
-                    mom[a] += fma(gld, FIm[(1 + a) * NF], fma(grd, FIp[(1 + a) * NF], df[a]));
-                    g[3 * a] = fma(cd, n0, g[3 * a]);
-                    g[3 * a + 1] = fma(cd, n1, g[3 * a + 1]);
-                    g[3 * a + 2] = fma(cd, n2, g[3 * a + 2]);
+                for (int u = 0; u < TPT; ++u) {
+                    const unsigned t = tid + u * NT;
+                    if ((int)t < ntask) {
+                        const unsigned el = t / (6 * NF), r = t - el * (6 * NF);
+                        const unsigned f = r / NF, L = r - f * NF;
+                        const unsigned a = L % M, bb = L / M;
+                        const unsigned base = d == 0 ? M * L : (d == 1 ? a + M * M * bb : L);
+                        T *Ue = sU + el * NV * NS;
+                        if (f < 3) {
+                            // g[3f+d] = n_dd (corrected d u_f / d xi_d); aux residual (f, d)
+#pragma unroll
+                            for (int i = 0; i < M; ++i) {
+                                const unsigned q = base + i * str;
+                                const T gv = outv[u][i] * ndd;
+                                T *sq = Ue + (4 + 3 * f + d) * NS + q;
+                                *sq = c.invT * fma(c.inv_det, gv, -*sq);
+                                if ((int)f == d) Ue[q] = d == 0 ? gv : Ue[q] + gv;
+                            }
+                        } else {
+                            T *Fq = sF + (el * 9 + 3 * d + f - 3) * NS + base;
+#pragma unroll
+                            for (int i = 0; i < M; ++i) Fq[i * str] = outv[u][i];
+                        }
+                    }
                 }
-                dissP = fma(gld, FIm[0], fma(grd, FIp[0], dissP));
             };
             direction(Dir<0>{});
-            __builtin_amdgcn_sched_barrier(0);
             direction(Dir<1>{});
-            __builtin_amdgcn_sched_barrier(0);
             direction(Dir<2>{});
-            T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
-            // P: -(1/detJ) [ zeta (det J div V) + dissipation ]
-            const T divV = g[0] + g[4] + g[8];
-            __builtin_nontemporal_store(-c.inv_det * fma(c.zeta, divV, dissP), Re);
+            __syncthreads();
+            for (unsigned t = tid; t < (unsigned)nel * NS; t += NT) {
+                const unsigned el = t / NS, q = t - el * NS;
+                const unsigned qi = q % M, qj = (q / M) % M, qk = q / (M * M);
+                const T *Ue = sU + el * NV * NS;
+                const T *Fe = sF + el * 9 * NS;
+                T dissP = T(0);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) __builtin_nontemporal_store(-c.inv_det * mom[a], Re + (1 + a) * NS);
-            // aux (a, k): (1/T) [ d u_a / d x_k - S_ak ]
+                for (int d = 0; d < 3; ++d) {
+                    const unsigned id = d == 0 ? qi : (d == 1 ? qj : qk);
+                    const unsigned fp = d == 0 ? qj + M * qk : (d == 1 ? qi + M * qk : qi + M * qj);
+                    const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + fp;
+                    dissP = fma(gl[id], FIm[0], fma(gr[id], FIm[EMAX * CHP], dissP));
+                }
+                T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
+                __builtin_nontemporal_store(-c.inv_det * fma(c.zeta, Ue[q], dissP), Re);
 #pragma unroll
-            for (int k = 0; k < 9; ++k)
-                __builtin_nontemporal_store(c.invT * fma(c.inv_det, g[k], -Ue[(4 + k) * NS + q]),
-                                            Re + (4 + k) * NS);
+                for (int a = 0; a < 3; ++a)
+                    __builtin_nontemporal_store(
+                        -c.inv_det * ((Fe[a * NS + q] + Fe[(3 + a) * NS + q]) + Fe[(6 + a) * NS + q]),
+                        Re + (1 + a) * NS);
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    __builtin_nontemporal_store(Ue[(4 + k) * NS + q], Re + (4 + k) * NS);
+            }
+        } else {
+            // ---- stages 3, 5, 6: partially corrected divergence along the three
+            //      line families (compile-time strides), correction with the common
+            //      fluxes, negate, source.
+            for (unsigned t = tid; t < (unsigned)nel * NS; t += NT) {
+                const unsigned el = t / NS, q = t - el * NS;
+                const unsigned qi = q % M, qj = (q / M) % M, qk = q / (M * M);
+                const T *Ue = sU + el * NV * NS;
+                const T *Fe = sF + el * 9 * NS;
+                // g[3a+k] = sum_d n_d,k (corrected d u_a / d xi_d) = det J d u_a / d x_k
+                T g[9], mom[3] = {T(0), T(0), T(0)}, dissP = T(0);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) g[k] = T(0);
+                auto direction = [&](auto dc) {
+                    constexpr int d = decltype(dc)::value;
+                    constexpr int str = d == 0 ? 1 : (d == 1 ? M : M * M);
+                    const unsigned id = d == 0 ? qi : (d == 1 ? qj : qk);
+                    const unsigned base = q - id * str;
+                    const unsigned fp = d == 0 ? qj + M * qk : (d == 1 ? qi + M * qk : qi + M * qj);
+                    const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + fp;
+                    const T *FIp = FIm + EMAX * CHP;
+                    const T gld = gl[id], grd = gr[id];
+                    const T *Fd = Fe + 3 * d * NS;
+                    const T *Drow = Dt + id * M;
+                    T du[3] = {T(0), T(0), T(0)}, df[3] = {T(0), T(0), T(0)};
+#pragma unroll
+                    for (int l = 0; l < M; ++l) {
+                        const unsigned ql = base + l * str;
+                        const T w = Drow[l];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            du[a] = fma(w, Ue[(1 + a) * NS + ql], du[a]);
+                            df[a] = fma(w, Fd[a * NS + ql], df[a]);
+                        }
+                    }
+                    const T n0 = geo[3 * d], n1 = geo[3 * d + 1], n2 = geo[3 * d + 2];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const T cd = fma(gld, FIm[(4 + a) * NF], fma(grd, FIp[(4 + a) * NF], du[a]));
+                        mom[a] += fma(gld, FIm[(1 + a) * NF], fma(grd, FIp[(1 + a) * NF], df[a]));
+                        g[3 * a] = fma(cd, n0, g[3 * a]);
+                        g[3 * a + 1] = fma(cd, n1, g[3 * a + 1]);
+                        g[3 * a + 2] = fma(cd, n2, g[3 * a + 2]);
+                    }
+                    dissP = fma(gld, FIm[0], fma(grd, FIp[0], dissP));
+                };
+                direction(Dir<0>{});
+                __builtin_amdgcn_sched_barrier(0);
+                direction(Dir<1>{});
+                __builtin_amdgcn_sched_barrier(0);
+                direction(Dir<2>{});
+                T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
+                // P: -(1/detJ) [ zeta (det J div V) + dissipation ]
+                const T divV = g[0] + g[4] + g[8];
+                __builtin_nontemporal_store(-c.inv_det * fma(c.zeta, divV, dissP), Re);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) __builtin_nontemporal_store(-c.inv_det * mom[a], Re + (1 + a) * NS);
+                // aux (a, k): (1/T) [ d u_a / d x_k - S_ak ]
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    __builtin_nontemporal_store(c.invT * fma(c.inv_det, g[k], -Ue[(4 + k) * NS + q]),
+                                                Re + (4 + k) * NS);
+            }
         }
     }
 }
