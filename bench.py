@@ -108,31 +108,31 @@ def time_residual(B, torch, plan, U, R, reps, warm=1):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(orders, host_states, budget_s):
+def cpu_baseline(orders, lattices, host_states, budget_s):
     """Serial C oracle on a sample of elements of each order's lattice."""
     import numpy as np
     import oracle
     tot_dof, tot_t, sample = 0, 0.0, []
     per = budget_s / len(orders)
     for p in orders:
-        N = LATTICE[p]
-        n = (N, N, N)
+        n = lattices[p]
+        ne = n[0] * n[1] * n[2]
         U = host_states[p]
         m = p + 1
         # calibrate on a few elements, then size the sample to the time budget
         rng = np.random.default_rng(p)
-        probe = rng.choice(N ** 3, size=64, replace=False)
+        probe = rng.choice(ne, size=min(64, ne), replace=False)
         t0 = time.perf_counter()
         oracle.residual_elems(p, n, U, probe, ZETA, NU, TRELAX)
-        dt = (time.perf_counter() - t0) / 64
-        ns = int(max(64, min(N ** 3, per / max(dt, 1e-7))))
-        sel = rng.choice(N ** 3, size=ns, replace=False)
+        dt = (time.perf_counter() - t0) / len(probe)
+        ns = int(max(min(64, ne), min(ne, per / max(dt, 1e-7))))
+        sel = rng.choice(ne, size=ns, replace=False)
         t0 = time.perf_counter()
         oracle.residual_elems(p, n, U, sel, ZETA, NU, TRELAX)
         t = time.perf_counter() - t0
         tot_dof += ns * NV * m ** 3
         tot_t += t
-        sample.append("p=%d: %d of %d elements" % (p, ns, N ** 3))
+        sample.append("p=%d: %d of %d elements" % (p, ns, ne))
         log("cpu oracle p=%d: %d elements in %.2f s" % (p, ns, t))
     return tot_dof / tot_t / 1e9, "; ".join(sample)
 
@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-hbm-ref", action="store_true", help="skip the copy/fill/read reference")
+    ap.add_argument("--lattice", default=None,
+                    help="NX,NY,NZ: one lattice for every order given (default: the sweep lattices)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-guess study (pseudo-iterations per physical step)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -179,17 +181,20 @@ def main():
         log("reference bandwidth: %s" % hbm_ref)
 
     work = []
+    lattices = {}
+    lat = tuple(int(x) for x in args.lattice.split(",")) if args.lattice else None
     for p in orders:
         N = LATTICE[p]
-        n = (N, N, N)
+        n = lat or (N, N, N)
+        lattices[p] = n
         t0 = time.perf_counter()
         U = inputs.fourier(p, n, seed=1000 + p, device=dev)
         R = torch.empty_like(U)
         plan = B.Plan(p, n, ZETA, NU, TRELAX, precision=B.FR_F64, variant=B.FR_FUSED)
         torch.cuda.synchronize()
         work.append((p, n, plan, U, R))
-        log("order %d: %d^3 hexes, %.1f M points, inputs in %.1f s" %
-            (p, N, N ** 3 * (p + 1) ** 3 / 1e6, time.perf_counter() - t0))
+        log("order %d: %s hexes, %.1f M points, inputs in %.1f s" %
+            (p, "x".join(map(str, n)), n[0] * n[1] * n[2] * (p + 1) ** 3 / 1e6, time.perf_counter() - t0))
 
     dof_step = sum(n[0] * n[1] * n[2] * NV * (p + 1) ** 3 for p, n, *_ in work)
 
@@ -228,8 +233,8 @@ def main():
                          fused_gbs=fused_bytes(p, ne, 8) / (fu_ms / max(fu_n, 1)) / 1e6,
                          trace_gbs=trace_bytes(p, ne, 8) / (tr_ms / max(tr_n, 1)) / 1e6)
     pdom = max(kstats, key=lambda p: kstats[p]["fused_total"])
-    Ndom = LATTICE[pdom]
-    dom_bytes = fused_bytes(pdom, Ndom ** 3, 8)
+    ndom = lattices[pdom]
+    dom_bytes = fused_bytes(pdom, ndom[0] * ndom[1] * ndom[2], 8)
     achieved = dom_bytes / kstats[pdom]["fused_ms"] / 1e6
     kname = "k_fused_p%d_f64" % pdom
     traffic = read_traffic(kname)
@@ -276,7 +281,7 @@ def main():
         host = {}
         for p, n, plan, U, R in work:
             host[p] = U.cpu().numpy()
-        val, sample = cpu_baseline(orders, host, args.cpu_seconds)
+        val, sample = cpu_baseline(orders, lattices, host, args.cpu_seconds)
         cpu = {"value": round(val, 6), "unit": "GDOF/s", "cores": 1, "kind": "oracle",
                "sample": "serial C oracle residual on randomly chosen elements of the same "
                          "lattices and fields: " + sample}
@@ -325,9 +330,10 @@ def main():
         "config": {"workload": "order sweep p=%s, fused FP64 ACM-HD FR residual, periodic box "
                                "[0,2pi]^3, lattices %s hexes" %
                                (",".join(map(str, orders)),
-                                "/".join("%d^3" % LATTICE[p] for p in orders)),
-                   "orders": orders, "points_per_order": {str(p): LATTICE[p] ** 3 * (p + 1) ** 3
-                                                          for p in orders},
+                                "/".join("x".join(map(str, lattices[p])) for p in orders)),
+                   "orders": orders,
+                   "points_per_order": {str(p): lattices[p][0] * lattices[p][1] * lattices[p][2] *
+                                        (p + 1) ** 3 for p in orders},
                    "dof_per_step": dof_step, "zeta": ZETA, "nu": NU, "T": TRELAX,
                    "parallelism": "single GPU"},
         "roofline": roofline,

@@ -5,6 +5,8 @@ FETCH_SIZE / WRITE_SIZE counters scaled by a plain copy of known size.
     python -m paper_2107_14027_amd.rocprof_summary stats KERNEL_STATS_CSV OUT --command CMD
     python -m paper_2107_14027_amd.rocprof_summary traffic FETCH_CSV WRITE_CSV OUTDIR \
         --calib-bytes NBYTES --command-fetch CMD --command-write CMD
+    python -m paper_2107_14027_amd.rocprof_summary counters OUT --points P=N,... \
+        --command CMD CSV [CSV ...]
 
 Traffic: each counter is read per dispatch (summed over its dimension entries,
 in KiB), averaged over the dispatches of one kernel instantiation, and scaled
@@ -122,6 +124,56 @@ def traffic(args):
             f.write("\n".join(lines) + "\n")
 
 
+def counters(args):
+    """Per-kernel SQ counters of one or more --pmc passes, per solution point
+    (wave-level instruction counts x 64 / points) and as ratios."""
+    pts = {}
+    for kv in args.points.split(","):
+        k, v = kv.split("=")
+        pts[int(k)] = float(v)
+    agg = collections.defaultdict(dict)
+    for path in args.csv:
+        per = collections.defaultdict(lambda: collections.defaultdict(float))
+        for r in csv.DictReader(open(path)):
+            k = short(r["Kernel_Name"])
+            if not k.startswith("k_"):
+                continue
+            per[(k, int(r["Dispatch_Id"]))][r["Counter_Name"]] += float(r["Counter_Value"])
+        n = collections.Counter(k for k, _ in per)
+        for (k, _), cs in per.items():
+            for c, v in cs.items():
+                agg[k][c] = agg[k].get(c, 0.0) + v / n[k]
+    cols = [("SQ_INSTS_VALU", "VALU"), ("SQ_INSTS_VALU_FMA_F64", "FMA64"),
+            ("SQ_INSTS_VALU_FMA_F32", "FMA32"), ("SQ_INSTS_VALU_INT32", "INT32"),
+            ("SQ_INSTS_SALU", "SALU"), ("SQ_INSTS_LDS", "LDS"), ("SQ_INSTS_VMEM_RD", "VMEM rd")]
+    out = ["# rocprofv3 counters per solution point: %s" % args.workload, "",
+           "command (one pass per counter group): `%s`" % args.command, "",
+           "summary: `python3 -m paper_2107_14027_amd.rocprof_summary %s`" % shlex.join(sys.argv[1:]), "",
+           "Instruction counts are per wavefront x 64 / solution points (= per point); "
+           "bank conflict = SQ_LDS_BANK_CONFLICT / SQ_INSTS_LDS (conflict cycles per LDS instruction); "
+           "the last two columns are raw counter ratios SQ_ACTIVE_INST_VALU / SQ_BUSY_CYCLES and "
+           "SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES (counters summed as rocprofv3 reports them).", "",
+           "| kernel | " + " | ".join(c[1] for c in cols) + " | bank conflict | ACTIVE_INST_VALU / BUSY_CYCLES | WAIT_INST_LDS / WAVE_CYCLES |",
+           "|---|" + "---:|" * (len(cols) + 3)]
+    for k in sorted(agg):
+        m = re.match(r"k_\w+<(\d+),", k)
+        if not m or int(m.group(1)) not in pts:
+            continue
+        a = agg[k]
+        w = pts[int(m.group(1))] / 64.0
+
+        def g(c):
+            return a.get(c, float("nan"))
+        cells = ["%.0f" % (g(c) / w) for c, _ in cols]
+        ratio = lambda x, y: "%.2f" % (g(x) / g(y)) if g(y) > 0 else "nan"
+        out.append("| %s | %s | %s | %s | %s |" % (k, " | ".join(cells),
+                                                   ratio("SQ_LDS_BANK_CONFLICT", "SQ_INSTS_LDS"),
+                                                   ratio("SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES"),
+                                                   ratio("SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES")))
+    with open(args.out, "w") as f:
+        f.write("\n".join(out) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -139,8 +191,14 @@ def main():
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
     t.add_argument("--workload", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("out")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--points", required=True, help="order=solution points, comma separated")
+    c.add_argument("--command", required=True)
+    c.add_argument("--workload", default="")
     a = ap.parse_args()
-    {"stats": stats, "traffic": traffic}[a.cmd](a)
+    {"stats": stats, "traffic": traffic, "counters": counters}[a.cmd](a)
 
 
 if __name__ == "__main__":
