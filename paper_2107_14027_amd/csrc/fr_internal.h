@@ -57,6 +57,9 @@ struct fr_plan {
     int variant;    // FR_FUSED / FR_UNFUSED
     int block;      // elements per workgroup override (0 = default)
     int guess_base = 2;  // extrapolation order the learned guess corrects
+    // persistent grid sizes of the fused path on this plan's device, per
+    // (order, precision, diagonal Jacobian): [0] trace kernel, [1] fused kernel
+    int fused_grid[2][fr::PMAX + 1][2][2] = {};
     int device;
     // host copies of the operators (double)
     double x[8], w[8], D[64], lm[8], lp[8], gl[8], gr[8], Dt[64];

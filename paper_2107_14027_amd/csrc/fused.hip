@@ -795,8 +795,9 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
         ((size_t)TEMAX * NV * TracePad<M>::NSP + 2 * M) * sizeof(T) + 6 * TEMAX * sizeof(int);
     const size_t lds_fu =
         ((size_t)EMAX * (NV + 9) * NS + (size_t)6 * EMAX * CHP + OpsLayout<M>::size + 24) * sizeof(T);
-    static int grid_tr = 0, grid_fu = 0;
-    if (!grid_tr) {
+    int &grid_tr = pl->fused_grid[0][P][sizeof(T) == 8][DIAG];
+    int &grid_fu = pl->fused_grid[1][P][sizeof(T) == 8][DIAG];
+    if (!grid_tr || !grid_fu) {
         int dev = 0, ncu = 0, occ_tr = 0, occ_fu = 0;
         if (int rc = check_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
         if (int rc = check_hip(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev),
