@@ -39,22 +39,22 @@ template <> struct V16<float> { using type = f4v; };
 #define FR_NT1_D 64
 #endif
 #ifndef FR_E2_D
-#define FR_E2_D 4
+#define FR_E2_D 9
 #endif
 #ifndef FR_NT2_D
-#define FR_NT2_D 128
+#define FR_NT2_D 256
 #endif
 #ifndef FR_E3_D
-#define FR_E3_D 1
+#define FR_E3_D 2
 #endif
 #ifndef FR_NT3_D
-#define FR_NT3_D 64
+#define FR_NT3_D 128
 #endif
 #ifndef FR_E4_D
 #define FR_E4_D 1
 #endif
 #ifndef FR_NT4_D
-#define FR_NT4_D 128
+#define FR_NT4_D 192
 #endif
 #ifndef FR_E5_D
 #define FR_E5_D 1

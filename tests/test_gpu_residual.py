@@ -12,6 +12,14 @@ from gpu_util import NU, T_CFG, TOL, ZETA, gpu_residual, rel, say
 
 pytestmark = pytest.mark.gpu
 
+def fused_emax(p, prec):
+    """Elements per batch of the fused kernel's launch shape for order p."""
+    import os
+    import re
+    src = os.path.join(os.path.dirname(__file__), "..", "paper_2107_14027_amd", "csrc", "fused.hip")
+    return int(re.search(r"#define FR_E%d_%s (\d+)" % (p, prec), open(src).read()).group(1))
+
+
 SKEW = np.array([[0.30, 0.05, -0.02], [0.01, 0.25, 0.04], [-0.03, 0.02, 0.35]])
 PREC = [B.FR_F64, B.FR_F32]
 VAR = [B.FR_FUSED, B.FR_UNFUSED]
@@ -89,7 +97,7 @@ def test_block_size_invariance_and_determinism(p):
     ref = gpu_residual(p, n, U)
     again = gpu_residual(p, n, U)
     assert np.array_equal(ref, again)
-    emax = {1: 8, 2: 4, 3: 1, 4: 1, 5: 1, 6: 1}[p]   # largest batch the fused kernel accepts
+    emax = fused_emax(p, "D")   # largest batch the fused kernel accepts
     for E in (1, 2, 3):
         if E <= emax:
             assert np.array_equal(gpu_residual(p, n, U, block=E), ref), E
