@@ -59,8 +59,20 @@ typedef enum fr_option {
     FR_OPT_VARIANT = 2,   /* FR_FUSED (default) or FR_UNFUSED                              */
     FR_OPT_BLOCK = 3,     /* elements per workgroup of the fused kernel; 0 = tuned default  */
     FR_OPT_PROFILE = 4,   /* 1: record HIP events around every kernel launch (see below)   */
-    FR_OPT_GUESS_BASE = 5 /* extrapolation the learned guess corrects: 2 quadratic (default),
+    FR_OPT_GUESS_BASE = 5,/* extrapolation the learned guess corrects: 2 quadratic (default),
                              1 linear                                                      */
+    FR_OPT_GRAPH = 6,     /* 1: fr_rk_step and fr_dual_step replay one captured HIP graph per
+                             (pseudo-)step instead of launching every kernel; 0 (default):
+                             plain launches.  Results are identical either way; the graphs
+                             are captured on a stream the plan owns and re-captured when a
+                             pointer or scalar baked into them changes.                     */
+    FR_OPT_FUSE_STAGE = 7 /* 1 (default): with FR_FUSED, fr_rk_step and fr_dual_step apply each
+                             RK4 stage update (and the BDF source and the pseudo-residual
+                             norm) in the fused kernel's epilogue, so the residual never goes
+                             to memory (not available at p = 6 with a non-diagonal Jacobian,
+                             which keeps the separate kernel); 0: residual kernel + separate
+                             stage kernel.  The states are bitwise identical either way; the
+                             norm's summation order (per workgroup) differs.                 */
 } fr_option;
 
 /* Kernel identifiers for fr_plan_kernel_stats. */

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FR_LIBRARY", os.path.join(HERE, "libfr.so"))
 
 FR_OK, FR_EINVAL, FR_ENOMEM, FR_EHIP, FR_ENONFINITE, FR_ENOCONV, FR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-FR_OPT_PRECISION, FR_OPT_VARIANT, FR_OPT_BLOCK, FR_OPT_PROFILE, FR_OPT_GUESS_BASE = 1, 2, 3, 4, 5
+(FR_OPT_PRECISION, FR_OPT_VARIANT, FR_OPT_BLOCK, FR_OPT_PROFILE, FR_OPT_GUESS_BASE,
+ FR_OPT_GRAPH, FR_OPT_FUSE_STAGE) = 1, 2, 3, 4, 5, 6, 7
 KERNELS = ("trace", "fused", "u_project", "u_flux", "u_div", "u_common", "u_correct",
            "u_negsrc", "stage")
 FR_F64, FR_F32 = 0, 1

@@ -1,6 +1,7 @@
 // C ABI entry points that run work on the GPU: residual, RK4 steps, dual time
 // steps and the extrapolated initial guess.  Argument checking happens here;
 // the kernels assume validated, in-bounds launches.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -50,6 +51,66 @@ int rk_buffers(fr_plan *pl, RkBufs &b)
     return FR_OK;
 }
 
+bool stage_in_epilogue(const fr_plan *pl)
+{
+    return pl->variant == FR_FUSED && pl->fuse_stage && fused_stage_available(pl);
+}
+
+// every plan setting that changes the launches of a step
+uint64_t config_word(const fr_plan *pl)
+{
+    return (uint64_t)pl->precision | (uint64_t)pl->variant << 8 | (uint64_t)pl->fuse_stage << 16 |
+           (uint64_t)(uint32_t)pl->block << 32;
+}
+
+uint64_t bits(double x)
+{
+    uint64_t u;
+    std::memcpy(&u, &x, sizeof u);
+    return u;
+}
+
+// Launch the work that `enqueue(stream)` issues as one HIP graph on stream s.
+// The graph is captured on the plan's own stream the first time and again
+// whenever `key` (every pointer and scalar baked into the launches) changes;
+// all scratch must already be allocated (the callers run one step without a
+// graph first).
+template <class F>
+int graph_run(fr_plan *pl, GraphCache &gc, const uint64_t (&key)[16], hipStream_t s, F &&enqueue)
+{
+    if (!gc.exec || std::memcmp(gc.key, key, sizeof key) != 0) {
+        for (auto &g : pl->graphs)
+            if (&g == &gc) {
+                if (g.exec) hipGraphExecDestroy(g.exec);
+                if (g.graph) hipGraphDestroy(g.graph);
+                g = GraphCache{};
+            }
+        if (!pl->cap_stream)
+            if (int rc = check_hip(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking),
+                                   "hipStreamCreateWithFlags"))
+                return rc;
+        if (int rc = check_hip(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal),
+                               "hipStreamBeginCapture"))
+            return rc;
+        int rc = enqueue(pl->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(pl->cap_stream, &g);
+        if (rc || e != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return rc ? rc : check_hip(e, "hipStreamEndCapture");
+        }
+        if (int rc2 = check_hip(hipGraphInstantiate(&gc.exec, g, nullptr, nullptr, 0),
+                                "hipGraphInstantiate")) {
+            hipGraphDestroy(g);
+            gc.exec = nullptr;
+            return rc2;
+        }
+        gc.graph = g;
+        std::memcpy(gc.key, key, sizeof key);
+    }
+    return check_hip(hipGraphLaunch(gc.exec, s), "hipGraphLaunch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -81,15 +142,45 @@ int fr_rk_step(fr_plan *pl, double *U, double dt, int nsteps, fr_stream_t sv)
     if (!f64) rc = launch_to_precision(pl, U, b.stT, n, s);
     const double c[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
     const double w[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
-    for (int step = 0; step < nsteps && !rc; ++step) {
-        for (int st = 0; st < 4 && !rc; ++st) {
-            const void *in = (st == 0 && f64) ? (const void *)U : b.stT;
-            rc = residual(pl, in, b.k, s);
-            if (rc) break;
-            const bool last = st == 3;
-            rc = launch_stage(pl, false, false, U, b.acc, st64, last && f64 ? nullptr : b.stT, b.k,
-                              nullptr, 0.0, w[st], last ? 0.0 : c[st + 1], st == 0, last, nullptr,
-                              s);
+    // stage updates in the fused kernel's epilogue: the stage states alternate
+    // between the two stage buffers (no residual array); the last stage leaves
+    // the working-precision copy of U in the first one, as the separate path does
+    const bool epi = stage_in_epilogue(pl);
+    void *const bufs[2] = {b.stT, b.k};
+    const int o = f64 ? 0 : 1;
+    auto step = [&](hipStream_t st) -> int {
+        if (epi) {
+            const void *in = f64 ? (const void *)U : bufs[0];
+            for (int k = 0; k < 4; ++k) {
+                const bool last = k == 3;
+                void *out = last ? (f64 ? nullptr : bufs[0]) : bufs[(k + o) % 2];
+                const StageSpec sp{U, b.acc, nullptr, nullptr, out, nullptr, nullptr,
+                                   0.0, w[k], last ? 0.0 : c[k + 1], k == 0, last};
+                if (int r = launch_residual_stage(pl, in, sp, nullptr, st)) return r;
+                in = out;
+            }
+            return FR_OK;
+        }
+        for (int k = 0; k < 4; ++k) {
+            const void *in = (k == 0 && f64) ? (const void *)U : b.stT;
+            if (int r = residual(pl, in, b.k, st)) return r;
+            const bool last = k == 3;
+            if (int r = launch_stage(pl, false, false, U, b.acc, st64, last && f64 ? nullptr : b.stT,
+                                     b.k, nullptr, 0.0, w[k], last ? 0.0 : c[k + 1], k == 0, last,
+                                     nullptr, st))
+                return r;
+        }
+        return FR_OK;
+    };
+    const bool graphs = pl->use_graphs && !pl->profile;
+    for (int it = 0; it < nsteps && !rc; ++it) {
+        if (graphs && it > 0) {
+            const uint64_t key[16] = {2, (uint64_t)U, bits(dt), (uint64_t)pl->rk.ptr,
+                                      (uint64_t)pl->traces.ptr, (uint64_t)pl->unfused.ptr,
+                                      config_word(pl)};
+            rc = graph_run(pl, pl->graphs[2], key, s, step);
+        } else {
+            rc = step(s);
         }
     }
     return rc;
@@ -115,8 +206,8 @@ int fr_dual_step(fr_plan *pl, double *U, const double *Un, const double *Unm1, d
     if (int rc = rk_buffers(pl, b)) return rc;
     const size_t nB = (size_t)pl->ne * 3 * ns;
     if (int rc = ensure_scratch(pl->dual, (nB + (f64 ? 0 : (size_t)n)) * sizeof(double))) return rc;
-    const int nblk = stage_blocks(n);
-    if (int rc = ensure_scratch(pl->norm, (size_t)(nblk + 1) * sizeof(double))) return rc;
+    const int cap = std::max(stage_blocks(n), MAX_PARTIALS);
+    if (int rc = ensure_scratch(pl->norm, (size_t)(cap + 1) * sizeof(double))) return rc;
     if (!pl->norm_host &&
         check_hip(hipHostMalloc((void **)&pl->norm_host, sizeof(double), hipHostMallocDefault),
                   "hipHostMalloc"))
@@ -124,7 +215,8 @@ int fr_dual_step(fr_plan *pl, double *U, const double *Un, const double *Unm1, d
     double *B = (double *)pl->dual.ptr;
     double *st64 = f64 ? (double *)b.stT : B + nB;
     double *partial = (double *)pl->norm.ptr;
-    double *sum = partial + nblk;
+    double *sum = partial + cap;
+    int nparts = stage_blocks(n);  // partial sums the first stage writes
 
     int rc = launch_bdf_const(pl, Un, Unm1, dt, B, s);
     const double a = Unm1 ? 1.5 / dt : 1.0 / dt;
@@ -132,40 +224,94 @@ int fr_dual_step(fr_plan *pl, double *U, const double *Un, const double *Unm1, d
     const double c[4] = {0.0, 0.5 * dtau, 0.5 * dtau, dtau};
     const double w[4] = {dtau / 6.0, dtau / 3.0, dtau / 3.0, dtau / 6.0};
     const double count = 3.0 * (double)pl->ne * ns;
+    // first stage of a pseudo-step (residual of the current iterate, with the
+    // per-block partial sums of its velocity norm), the other three stages,
+    // and the reduction + read-back of the norm into pinned host memory
+    // with the stage updates in the fused kernel's epilogue the stage states
+    // alternate between the two stage buffers, and the double copy of the stage
+    // state that the BDF term needs (FP32) is updated in place
+    const bool epi = stage_in_epilogue(pl);
+    void *const bufs[2] = {b.stT, b.k};
+    const int o = f64 ? 0 : 1;
+    auto stage0 = [&](hipStream_t st) -> int {
+        if (epi) {
+            const StageSpec sp{U, b.acc, nullptr, f64 ? nullptr : st64, bufs[o], B, partial,
+                               a, w[0], c[1], 1, 0};
+            return launch_residual_stage(pl, f64 ? (const void *)U : bufs[0], sp, &nparts, st);
+        }
+        if (int r = residual(pl, f64 ? (const void *)U : b.stT, b.k, st)) return r;
+        return launch_stage(pl, true, true, U, b.acc, st64, b.stT, b.k, B, a, w[0], c[1], 1, 0,
+                            partial, st);
+    };
+    auto stages123 = [&](hipStream_t st) -> int {
+        if (epi) {
+            for (int k = 1; k < 4; ++k) {
+                const bool last = k == 3;
+                void *in = bufs[(k - 1 + o) % 2];
+                void *out = last ? (f64 ? nullptr : bufs[0]) : bufs[(k + o) % 2];
+                const StageSpec sp{U, b.acc, f64 ? (const double *)in : st64,
+                                   (f64 || last) ? nullptr : st64, out, B, nullptr,
+                                   a, w[k], last ? 0.0 : c[k + 1], 0, last};
+                if (int r = launch_residual_stage(pl, in, sp, nullptr, st)) return r;
+            }
+            return FR_OK;
+        }
+        for (int k = 1; k < 4; ++k) {
+            if (int r = residual(pl, b.stT, b.k, st)) return r;
+            const bool last = k == 3;
+            if (int r = launch_stage(pl, true, false, U, b.acc, st64, (last && f64) ? nullptr : b.stT,
+                                     b.k, B, a, w[k], last ? 0.0 : c[k + 1], 0, last, nullptr, st))
+                return r;
+        }
+        return FR_OK;
+    };
+    auto readback = [&](hipStream_t st) -> int {
+        if (int r = launch_final_sum(partial, nparts, sum, st)) return r;
+        return check_hip(hipMemcpyAsync(pl->norm_host, sum, sizeof(double), hipMemcpyDeviceToHost, st),
+                         "hipMemcpyAsync(norm)");
+    };
     int it = 0;
     double res = NAN;
+    auto wait_norm = [&]() -> int {
+        if (int r = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize")) return r;
+        res = std::sqrt(*pl->norm_host / count);
+        if (!std::isfinite(res))
+            return set_error(FR_ENONFINITE, "pseudo-residual norm is %g after %d steps", res, it);
+        return FR_OK;
+    };
+    // iterate `it` has had its first stage; its norm is known when `have`
+    if (!rc) rc = stage0(s);
+    if (!rc) rc = readback(s);
+    if (!rc) rc = wait_norm();
+    bool have = true;
+    const bool graphs = pl->use_graphs && !pl->profile;
     while (!rc) {
-        rc = residual(pl, f64 ? (const void *)U : b.stT, b.k, s);
-        if (rc) break;
-        rc = launch_stage(pl, true, true, U, b.acc, st64, b.stT, b.k, B, a, w[0], c[1], 1, 0,
-                          partial, s);
-        if (rc) break;
-        if (it % check_every == 0 || it >= max_iters) {
-            rc = launch_final_sum(partial, nblk, sum, s);
-            if (!rc) rc = check_hip(hipMemcpyAsync(pl->norm_host, sum, sizeof(double),
-                                                   hipMemcpyDeviceToHost, s),
-                                    "hipMemcpyAsync(norm)");
-            if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-            if (rc) break;
-            res = std::sqrt(*pl->norm_host / count);
-            if (!std::isfinite(res)) {
-                rc = set_error(FR_ENONFINITE, "pseudo-residual norm is %g after %d steps", res, it);
-                break;
-            }
-            if (res < tol) break;
-        }
+        if (have && res < tol) break;
         if (it >= max_iters) {
             rc = set_error(FR_ENOCONV, "no convergence in %d pseudo-steps (residual %g)", it, res);
             break;
         }
-        for (int st = 1; st < 4 && !rc; ++st) {
-            rc = residual(pl, b.stT, b.k, s);
-            if (rc) break;
-            const bool last = st == 3;
-            rc = launch_stage(pl, true, false, U, b.acc, st64, (last && f64) ? nullptr : b.stT,
-                              b.k, B, a, w[st], last ? 0.0 : c[st + 1], 0, last, nullptr, s);
+        const bool check = (it + 1) % check_every == 0 || it + 1 >= max_iters;
+        auto body = [&](hipStream_t st) -> int {
+            if (int r = stages123(st)) return r;
+            if (int r = stage0(st)) return r;
+            return check ? readback(st) : FR_OK;
+        };
+        if (graphs) {
+            const uint64_t key[16] = {1, (uint64_t)U, (uint64_t)Un, (uint64_t)Unm1, bits(dt),
+                                      bits(dtau), (uint64_t)check, (uint64_t)pl->rk.ptr,
+                                      (uint64_t)pl->dual.ptr, (uint64_t)pl->norm.ptr,
+                                      (uint64_t)pl->traces.ptr, (uint64_t)pl->unfused.ptr,
+                                      config_word(pl), (uint64_t)pl->norm_host,
+                                      (uint64_t)nparts};
+            rc = graph_run(pl, pl->graphs[check ? 0 : 1], key, s, body);
+        } else {
+            rc = body(s);
         }
-        if (!rc) ++it;
+        if (rc) break;
+        ++it;
+        have = check;
+        if (check) rc = wait_norm();
     }
     *iters = it;
     *resid = res;

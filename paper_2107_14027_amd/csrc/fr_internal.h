@@ -41,6 +41,39 @@ struct Scratch {
     size_t bytes = 0;
 };
 
+// One captured HIP graph and the launch parameters it was captured with.
+struct GraphCache {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t key[16] = {};
+};
+
+// One classical RK4 stage of dU/dtau = k* applied to a residual k as it is
+// produced (the fused kernel's epilogue), with k* = k - [v in V] (a s + B)
+// when B is set (dual time stepping, velocity only), s the state that produced
+// k in double:
+//   first stage: acc = U + b k*,  else acc += b k*;  s' = U + cnext k*
+//   last stage:  U = acc + b k*
+// s' goes to s_out (plan precision) and, when set, s_out64 (double); on the
+// last stage s_out (when set) receives (T) U.  partial (when set) receives one
+// sum of (k*_V)^2 per workgroup.  Every index is read and written by one
+// thread only, so s_in may equal s_out64; s_out must not be the residual
+// kernel's input.
+struct StageSpec {
+    double *U;
+    double *acc;
+    const double *s_in;   // state that produced k (null: U)
+    double *s_out64;
+    void *s_out;
+    const double *B;      // BDF constant [ne][3][m^3], or null
+    double *partial;
+    double a, b, cnext;
+    int first, last;
+};
+
+// capacity of the per-workgroup partial sums of a fused stage launch
+constexpr int MAX_PARTIALS = 8192;
+
 struct ProfRec {
     int kid;
     hipEvent_t a, b;
@@ -57,9 +90,17 @@ struct fr_plan {
     int variant;    // FR_FUSED / FR_UNFUSED
     int block;      // elements per workgroup override (0 = default)
     int guess_base = 2;  // extrapolation order the learned guess corrects
+    // captured time-integration graphs ([0] pseudo-step with norm read-back,
+    // [1] pseudo-step without, [2] RK4 step) and their capture stream
+    int use_graphs = 0;
+    // fused path: apply the RK stage updates in the fused kernel's epilogue
+    int fuse_stage = 1;
+    hipStream_t cap_stream = nullptr;
+    fr::GraphCache graphs[3];
     // persistent grid sizes of the fused path on this plan's device, per
-    // (order, precision, diagonal Jacobian): [0] trace kernel, [1] fused kernel
-    int fused_grid[2][fr::PMAX + 1][2][2] = {};
+    // (order, precision, diagonal Jacobian): [0] trace kernel, [1] fused kernel,
+    // [2] fused kernel with the stage epilogue
+    int fused_grid[3][fr::PMAX + 1][2][2] = {};
     int device;
     // host copies of the operators (double)
     double x[8], w[8], D[64], lm[8], lp[8], gl[8], gr[8], Dt[64];
@@ -100,10 +141,16 @@ struct ProfScope {
     ~ProfScope();
 };
 void prof_harvest(fr_plan *pl);
+void graphs_reset(fr_plan *pl);
 
 // launchers (return FR_OK or an error code)
 int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s);
 int launch_residual_unfused(fr_plan *pl, const void *U, void *R, hipStream_t s);
+// fused residual of U followed by the stage update sp (no residual array);
+// *nparts receives the number of partial sums written when sp.partial is set
+int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *nparts,
+                          hipStream_t s);
+bool fused_stage_available(const fr_plan *pl);
 
 // time integration kernels (timeint.hip)
 int stage_blocks(int64_t n);

@@ -501,10 +501,34 @@ template <int P, bool DIAG> struct LineDiv {
     static constexpr bool value = DIAG && P >= FR_LDIV_PMIN;
 };
 
-template <int P, typename T, bool DIAG>
+// Values per thread whose global operands the stage epilogue requests at once,
+// per order and precision (a larger chunk overlaps more loads but can cost a
+// wave of occupancy; measured).  FR_STG_CHUNK overrides the table.
+template <int P, typename T>
+constexpr int stage_chunk()
+{
+#ifdef FR_STG_CHUNK
+    return FR_STG_CHUNK;
+#else
+    constexpr int d[PMAX + 1] = {0, 1, 1, 8, 1, 8, 4};
+    constexpr int f[PMAX + 1] = {0, 8, 4, 4, 1, 8, 1};
+    return sizeof(T) == 8 ? d[P] : f[P];
+#endif
+}
+
+// The stage epilogue needs the residual of a whole batch in the state tile:
+// the line-task path leaves it there; the point-wise path holds it in
+// registers, which is only done where a thread has a single point.
+template <int P, typename T, bool DIAG> struct StageEpilogue {
+    static constexpr int NS = (P + 1) * (P + 1) * (P + 1);
+    static constexpr bool value =
+        LineDiv<P, DIAG>::value || Shape<P, T>::EMAX * NS <= Shape<P, T>::NT;
+};
+
+template <int P, typename T, bool DIAG, bool STG>
 __global__ void __launch_bounds__((Shape<P, T>::NT))
     k_fused(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
-            const T *__restrict__ ops, Consts<T> c, int ne, int E, int nbatch)
+            const T *__restrict__ ops, Consts<T> c, int ne, int E, int nbatch, StageSpec sp)
 {
     constexpr int M = P + 1, NS = M * M * M, NF = M * M;
     using TL = TraceLayout<M, T>;
@@ -535,6 +559,8 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
     const T *Dt = sop + OL::Dt;
     const T *gl = sop + OL::gl;
     const T *gr = sop + OL::gr;
+    // STG: sum of (k*_V)^2 over this workgroup's stage updates
+    double ss = 0.0;
     for (; b < nbatch; b += gridDim.x) {
         const int tid = opaque_tid();
         const int e0 = b * E;
@@ -694,22 +720,39 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
                     const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + fp;
                     dissP = fma(gl[id], FIm[0], fma(gr[id], FIm[EMAX * CHP], dissP));
                 }
-                T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
-                __builtin_nontemporal_store(-c.inv_det * fma(c.zeta, Ue[q], dissP), Re);
+                const T rP = -c.inv_det * fma(c.zeta, Ue[q], dissP);
+                T rm[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
-                    __builtin_nontemporal_store(
-                        -c.inv_det * ((Fe[a * NS + q] + Fe[(3 + a) * NS + q]) + Fe[(6 + a) * NS + q]),
-                        Re + (1 + a) * NS);
+                    rm[a] = -c.inv_det * ((Fe[a * NS + q] + Fe[(3 + a) * NS + q]) + Fe[(6 + a) * NS + q]);
+                if constexpr (STG) {
+                    // only this thread touches point q's slots in this pass
+                    T *Uw = sU + el * NV * NS + q;
+                    Uw[0] = rP;
 #pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    __builtin_nontemporal_store(Ue[(4 + k) * NS + q], Re + (4 + k) * NS);
+                    for (int a = 0; a < 3; ++a) Uw[(1 + a) * NS] = rm[a];
+                } else {
+                    T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
+                    __builtin_nontemporal_store(rP, Re);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) __builtin_nontemporal_store(rm[a], Re + (1 + a) * NS);
+#pragma unroll
+                    for (int k = 0; k < 9; ++k)
+                        __builtin_nontemporal_store(Ue[(4 + k) * NS + q], Re + (4 + k) * NS);
+                }
             }
         } else {
             // ---- stages 3, 5, 6: partially corrected divergence along the three
             //      line families (compile-time strides), correction with the common
-            //      fluxes, negate, source.
-            for (unsigned t = tid; t < (unsigned)nel * NS; t += NT) {
+            //      fluxes, negate, source.  A thread handles at most KP points.
+            //      With STG the residual of each point is held in registers until
+            //      every thread has read the tile, then written over the state tile.
+            constexpr int KP = (EMAX * NS + NT - 1) / NT;
+            T rhold[STG ? KP : 1][NV];
+#pragma unroll
+            for (int u = 0; u < KP; ++u) {
+                const unsigned t = tid + u * NT;
+                if (t >= (unsigned)nel * NS) break;
                 const unsigned el = t / NS, q = t - el * NS;
                 const unsigned qi = q % M, qj = (q / M) % M, qk = q / (M * M);
                 const T *Ue = sU + el * NV * NS;
@@ -756,17 +799,108 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
                 direction(Dir<1>{});
                 __builtin_amdgcn_sched_barrier(0);
                 direction(Dir<2>{});
-                T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
+                T r[NV];
                 // P: -(1/detJ) [ zeta (det J div V) + dissipation ]
                 const T divV = g[0] + g[4] + g[8];
-                __builtin_nontemporal_store(-c.inv_det * fma(c.zeta, divV, dissP), Re);
+                r[0] = -c.inv_det * fma(c.zeta, divV, dissP);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) __builtin_nontemporal_store(-c.inv_det * mom[a], Re + (1 + a) * NS);
+                for (int a = 0; a < 3; ++a) r[1 + a] = -c.inv_det * mom[a];
                 // aux (a, k): (1/T) [ d u_a / d x_k - S_ak ]
 #pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    __builtin_nontemporal_store(c.invT * fma(c.inv_det, g[k], -Ue[(4 + k) * NS + q]),
-                                                Re + (4 + k) * NS);
+                for (int k = 0; k < 9; ++k) r[4 + k] = c.invT * fma(c.inv_det, g[k], -Ue[(4 + k) * NS + q]);
+                if constexpr (STG) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) rhold[u][v] = r[v];
+                } else {
+                    T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) __builtin_nontemporal_store(r[v], Re + v * NS);
+                }
+            }
+            if constexpr (STG) {
+                __syncthreads();  // every read of the state tile is done
+#pragma unroll
+                for (int u = 0; u < KP; ++u) {
+                    const unsigned t = tid + u * NT;
+                    if (t < (unsigned)nel * NS) {
+                        const unsigned el = t / NS, q = t - el * NS;
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) sU[(el * NV + v) * NS + q] = rhold[u][v];
+                    }
+                }
+            }
+        }
+        if constexpr (STG) {
+            // ---- RK stage update over the batch's contiguous [element][variable]
+            //      [point] range, the same double arithmetic as the stand-alone
+            //      stage kernel (the residual went through LDS, so nothing is
+            //      contracted into its last operation).  A thread has at most J
+            //      values, taken in chunks of C: the global operands of a chunk
+            //      are requested before the first is used, so that the loads of a
+            //      wave overlap, with a bounded register cost.
+            constexpr int J = (EMAX * NV * NS + NT - 1) / NT;
+            constexpr int C = stage_chunk<P, T>() < J ? stage_chunk<P, T>() : J;
+            __syncthreads();
+            const unsigned cnt = (unsigned)nel * NV * NS;
+            const int64_t g0 = (int64_t)e0 * NV * NS;
+#pragma unroll 1
+            for (int j0 = 0; j0 < J; j0 += C) {
+                double ou[C], oa[C], os[C], ob[C];
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    const unsigned t = tid + (j0 + j) * NT;
+                    if (t < cnt) {
+                        const int64_t gi = g0 + t;
+                        if (!sp.last) ou[j] = sp.U[gi];
+                        if (!sp.first || sp.last) oa[j] = sp.acc[gi];
+                        if (sp.B) {
+                            const unsigned r = t / NS, q = t - r * NS;
+                            const unsigned el = r / NV, v = r - el * NV;
+                            if (v >= 1 && v <= 3) {
+                                os[j] = sp.s_in ? sp.s_in[gi] : sp.U[gi];
+                                ob[j] = sp.B[((int64_t)(e0 + el) * 3 + (v - 1)) * NS + q];
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < C; ++j) {
+                    const unsigned t = tid + (j0 + j) * NT;
+                    if (t < cnt) {
+                        const int64_t gi = g0 + t;
+                        const unsigned v = (t / NS) % NV;
+                        double kv = (double)sU[t];
+                        if (v >= 1 && v <= 3) {
+                            if (sp.B) kv -= fma(sp.a, os[j], ob[j]);
+                            if (sp.partial) ss = fma(kv, kv, ss);
+                        }
+                        if (sp.last) {
+                            const double un = fma(sp.b, kv, oa[j]);
+                            sp.U[gi] = un;
+                            if (sp.s_out) static_cast<T *>(sp.s_out)[gi] = (T)un;
+                        } else {
+                            sp.acc[gi] = fma(sp.b, kv, sp.first ? ou[j] : oa[j]);
+                            const double sn = fma(sp.cnext, kv, ou[j]);
+                            if (sp.s_out64) sp.s_out64[gi] = sn;
+                            static_cast<T *>(sp.s_out)[gi] = (T)sn;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (STG) {
+        if (sp.partial) {
+            // fixed-order workgroup sum: wave butterfly, then the waves in order
+            __shared__ double red[NT / 64];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int w = 0; w < NT / 64; ++w) t += red[w];
+                sp.partial[blockIdx.x] = t;
             }
         }
     }
@@ -776,8 +910,8 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 // launch
 // ---------------------------------------------------------------------------
 template <int P, typename T, bool DIAG>
-int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<T> &c,
-               hipStream_t s)
+int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, T *TR,
+               const T *ops, const Consts<T> &c, hipStream_t s)
 {
     constexpr int M = P + 1, NS = M * M * M;
     constexpr int CHP = TraceLayout<M, T>::CHP;
@@ -795,37 +929,38 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
         ((size_t)TEMAX * NV * TracePad<M>::NSP + 2 * M) * sizeof(T) + 6 * TEMAX * sizeof(int);
     const size_t lds_fu =
         ((size_t)EMAX * (NV + 9) * NS + (size_t)6 * EMAX * CHP + OpsLayout<M>::size + 24) * sizeof(T);
-    int &grid_tr = pl->fused_grid[0][P][sizeof(T) == 8][DIAG];
-    int &grid_fu = pl->fused_grid[1][P][sizeof(T) == 8][DIAG];
-    if (!grid_tr || !grid_fu) {
-        int dev = 0, ncu = 0, occ_tr = 0, occ_fu = 0;
+    const void *ktr = (const void *)k_trace<P, T, DIAG>;
+    constexpr bool STG_OK = StageEpilogue<P, T, DIAG>::value;
+    if (sp && !STG_OK)
+        return set_error(FR_EUNSUPPORTED, "stage epilogue not available at p=%d", P);
+    const void *kfu = (const void *)k_fused<P, T, DIAG, false>;
+    if constexpr (STG_OK)
+        if (sp) kfu = (const void *)k_fused<P, T, DIAG, true>;
+    // persistent grid: every workgroup that fits on the device at once
+    auto persistent_grid = [&](const void *fn, int nt, size_t lds, int &grid) -> int {
+        if (grid) return FR_OK;
+        int dev = 0, ncu = 0, occ = 0;
         if (int rc = check_hip(hipGetDevice(&dev), "hipGetDevice")) return rc;
         if (int rc = check_hip(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev),
                                "hipDeviceGetAttribute"))
             return rc;
-        if (int rc = check_hip(hipFuncSetAttribute((const void *)k_trace<P, T, DIAG>,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)lds_tr), "hipFuncSetAttribute(k_trace)"))
+        if (int rc = check_hip(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)lds),
+                               "hipFuncSetAttribute"))
             return rc;
-        if (int rc = check_hip(hipFuncSetAttribute((const void *)k_fused<P, T, DIAG>,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   (int)lds_fu), "hipFuncSetAttribute(k_fused)"))
+        if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, nt, lds),
+                               "hipOccupancyMaxActiveBlocksPerMultiprocessor"))
             return rc;
-        if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                   &occ_tr, (const void *)k_trace<P, T, DIAG>, TNT, lds_tr),
-                               "occupancy(k_trace)"))
-            return rc;
-        if (int rc = check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                   &occ_fu, (const void *)k_fused<P, T, DIAG>, NT, lds_fu),
-                               "occupancy(k_fused)"))
-            return rc;
-        if (occ_tr < 1 || occ_fu < 1)
-            return set_error(FR_EUNSUPPORTED, "fused kernels do not fit on a CU at p=%d", P);
-        grid_tr = ncu * occ_tr;
-        grid_fu = ncu * occ_fu;
-    }
+        if (occ < 1) return set_error(FR_EUNSUPPORTED, "fused kernels do not fit on a CU at p=%d", P);
+        grid = ncu * occ;
+        return FR_OK;
+    };
+    int &grid_tr = pl->fused_grid[0][P][sizeof(T) == 8][DIAG];
+    int &grid_fu = pl->fused_grid[sp ? 2 : 1][P][sizeof(T) == 8][DIAG];
+    if (int rc = persistent_grid(ktr, TNT, lds_tr, grid_tr)) return rc;
+    if (int rc = persistent_grid(kfu, NT, lds_fu, grid_fu)) return rc;
     const unsigned gtr = (unsigned)min(nbatch_tr, grid_tr);
-    const unsigned gfu = (unsigned)min(nbatch, grid_fu);
+    const unsigned gfu = (unsigned)min(min(nbatch, grid_fu), sp ? MAX_PARTIALS : grid_fu);
     {
         ProfScope ps(pl, FR_K_TRACE, s);
         hipLaunchKernelGGL((k_trace<P, T, DIAG>), dim3(gtr), dim3(TNT), lds_tr, s, U, TR, ops, c,
@@ -833,31 +968,43 @@ int fused_impl(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<
     }
     {
         ProfScope ps(pl, FR_K_FUSED, s);
-        hipLaunchKernelGGL((k_fused<P, T, DIAG>), dim3(gfu), dim3(NT), lds_fu, s, U, TR, R, ops, c,
-                           ne, E, nbatch);
+        if (sp) {
+            if constexpr (STG_OK) {
+                if (nparts) *nparts = (int)gfu;
+                hipLaunchKernelGGL((k_fused<P, T, DIAG, true>), dim3(gfu), dim3(NT), lds_fu, s, U,
+                                   TR, (T *)nullptr, ops, c, ne, E, nbatch, *sp);
+            }
+        } else {
+            hipLaunchKernelGGL((k_fused<P, T, DIAG, false>), dim3(gfu), dim3(NT), lds_fu, s, U, TR,
+                               R, ops, c, ne, E, nbatch, StageSpec{});
+        }
     }
     return check_hip(hipGetLastError(), "fused residual launch");
 }
 
 template <typename T>
-int dispatch_fused(fr_plan *pl, const T *U, T *R, T *TR, const T *ops, const Consts<T> &c,
-                   hipStream_t s)
+int dispatch_fused(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, T *TR,
+                   const T *ops, const Consts<T> &c, hipStream_t s)
 {
     const bool dg = c.diag != 0;
+#define FR_CASE(PP)                                                                        \
+    case PP:                                                                               \
+        return dg ? fused_impl<PP, T, true>(pl, U, R, sp, nparts, TR, ops, c, s)           \
+                  : fused_impl<PP, T, false>(pl, U, R, sp, nparts, TR, ops, c, s);
     switch (pl->p) {
-        case 1: return dg ? fused_impl<1, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<1, T, false>(pl, U, R, TR, ops, c, s);
-        case 2: return dg ? fused_impl<2, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<2, T, false>(pl, U, R, TR, ops, c, s);
-        case 3: return dg ? fused_impl<3, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<3, T, false>(pl, U, R, TR, ops, c, s);
-        case 4: return dg ? fused_impl<4, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<4, T, false>(pl, U, R, TR, ops, c, s);
-        case 5: return dg ? fused_impl<5, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<5, T, false>(pl, U, R, TR, ops, c, s);
-        case 6: return dg ? fused_impl<6, T, true>(pl, U, R, TR, ops, c, s) : fused_impl<6, T, false>(pl, U, R, TR, ops, c, s);
+        FR_CASE(1)
+        FR_CASE(2)
+        FR_CASE(3)
+        FR_CASE(4)
+        FR_CASE(5)
+        FR_CASE(6)
     }
+#undef FR_CASE
     return set_error(FR_EINVAL, "order %d", pl->p);
 }
 
-}  // namespace
-
-int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s)
+int fused_any(fr_plan *pl, const void *U, void *R, const StageSpec *sp, int *nparts,
+              hipStream_t s)
 {
     const int m = pl->m;
     const size_t esz = pl->precision == FR_F64 ? 8 : 4;
@@ -866,10 +1013,43 @@ int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s)
     const size_t tr_bytes = (size_t)6 * pl->ne * chp * esz;
     if (int rc = ensure_scratch(pl->traces, tr_bytes)) return rc;
     if (pl->precision == FR_F64)
-        return dispatch_fused<double>(pl, (const double *)U, (double *)R, (double *)pl->traces.ptr,
-                                      (const double *)pl->ops64, pl->c64, s);
-    return dispatch_fused<float>(pl, (const float *)U, (float *)R, (float *)pl->traces.ptr,
-                                 (const float *)pl->ops32, pl->c32, s);
+        return dispatch_fused<double>(pl, (const double *)U, (double *)R, sp, nparts,
+                                      (double *)pl->traces.ptr, (const double *)pl->ops64,
+                                      pl->c64, s);
+    return dispatch_fused<float>(pl, (const float *)U, (float *)R, sp, nparts,
+                                 (float *)pl->traces.ptr, (const float *)pl->ops32, pl->c32, s);
+}
+
+}  // namespace
+
+int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s)
+{
+    return fused_any(pl, U, R, nullptr, nullptr, s);
+}
+
+bool fused_stage_available(const fr_plan *pl)
+{
+    const bool dg = pl->c64.diag != 0, f64 = pl->precision == FR_F64;
+    auto pick = [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        return f64 ? (dg ? StageEpilogue<P, double, true>::value : StageEpilogue<P, double, false>::value)
+                   : (dg ? StageEpilogue<P, float, true>::value : StageEpilogue<P, float, false>::value);
+    };
+    switch (pl->p) {
+        case 1: return pick(Dir<1>{});
+        case 2: return pick(Dir<2>{});
+        case 3: return pick(Dir<3>{});
+        case 4: return pick(Dir<4>{});
+        case 5: return pick(Dir<5>{});
+        case 6: return pick(Dir<6>{});
+    }
+    return false;
+}
+
+int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *nparts,
+                          hipStream_t s)
+{
+    return fused_any(pl, U, nullptr, &sp, nparts, s);
 }
 
 }  // namespace fr

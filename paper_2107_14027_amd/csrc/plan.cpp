@@ -189,6 +189,15 @@ ProfScope::~ProfScope()
     if (pl->prof.size() > 8192) prof_harvest(pl);
 }
 
+void graphs_reset(fr_plan *pl)
+{
+    for (auto &g : pl->graphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        if (g.graph) hipGraphDestroy(g.graph);
+        g = fr::GraphCache{};
+    }
+}
+
 void prof_harvest(fr_plan *pl)
 {
     for (auto &r : pl->prof) {
@@ -373,6 +382,14 @@ int fr_plan_set_int(fr_plan *pl, int key, int value)
             if (value != 1 && value != 2) return set_error(FR_EINVAL, "guess base %d", value);
             pl->guess_base = value;
             return FR_OK;
+        case FR_OPT_GRAPH:
+            if (value != 0 && value != 1) return set_error(FR_EINVAL, "graph %d", value);
+            pl->use_graphs = value;
+            return FR_OK;
+        case FR_OPT_FUSE_STAGE:
+            if (value != 0 && value != 1) return set_error(FR_EINVAL, "fuse stage %d", value);
+            pl->fuse_stage = value;
+            return FR_OK;
         default:
             return set_error(FR_EINVAL, "unknown option %d", key);
     }
@@ -387,6 +404,8 @@ int fr_plan_get_int(const fr_plan *pl, int key, int *value)
         case FR_OPT_BLOCK: *value = pl->block; return FR_OK;
         case FR_OPT_PROFILE: *value = pl->profile; return FR_OK;
         case FR_OPT_GUESS_BASE: *value = pl->guess_base; return FR_OK;
+        case FR_OPT_GRAPH: *value = pl->use_graphs; return FR_OK;
+        case FR_OPT_FUSE_STAGE: *value = pl->fuse_stage; return FR_OK;
         default: return set_error(FR_EINVAL, "unknown option %d", key);
     }
 }
@@ -411,6 +430,8 @@ void fr_plan_destroy(fr_plan *pl)
     if (!pl) return;
     hipDeviceSynchronize();
     prof_harvest(pl);
+    graphs_reset(pl);
+    if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
     free_scratch(pl->traces);
     free_scratch(pl->unfused);
     free_scratch(pl->rk);

@@ -1,0 +1,91 @@
+"""The RK4 stage update applied in the fused kernel's epilogue (no residual
+array) against the residual kernel followed by the separate stage kernel: the
+states must carry the same bits, for RK4 and for dual time stepping (BDF
+source on the velocity, pseudo-residual norm), every order, both precisions,
+diagonal and general Jacobians, and ragged lattices whose last workgroup batch
+is partial.  The dual step's norm is summed per workgroup in the epilogue, so
+only its rounding may differ."""
+import numpy as np
+import pytest
+
+from paper_2107_14027_amd import binding as B
+from paper_2107_14027_amd import inputs
+from gpu_util import NU, T_CFG, ZETA, say
+
+pytestmark = pytest.mark.gpu
+SKEW = np.array([[0.30, 0.05, -0.02], [0.01, 0.25, 0.04], [-0.03, 0.02, 0.35]])
+
+
+def dev(U):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(U)).to("cuda")
+
+
+def pair(p, n, prec, jac):
+    out = []
+    for fuse in (1, 0):
+        pl = B.Plan(p, n, ZETA, NU, T_CFG, jac, prec, B.FR_FUSED)
+        pl.set(B.FR_OPT_FUSE_STAGE, fuse)
+        out.append(pl)
+    return out
+
+
+@pytest.mark.parametrize("prec", [B.FR_F64, B.FR_F32])
+@pytest.mark.parametrize("p,n,jac", [(1, (5, 3, 4), None), (2, (3, 4, 5), None), (3, (5, 3, 3), None),
+                                     (4, (3, 2, 3), None), (5, (2, 3, 2), None), (6, (2, 2, 3), None),
+                                     (3, (3, 4, 2), "skew"), (6, (2, 1, 2), "skew")])
+def test_rk_epilogue_bitwise(prec, p, n, jac):
+    import torch
+    J = SKEW if jac else None
+    U0 = inputs.tgv(p, n, noise=1e-3, seed=p)
+    g, e = pair(p, n, prec, J)
+    say("rk epilogue p=%d n=%s prec=%d jac=%s" % (p, n, prec, jac))
+    Ug, Ue = dev(U0), dev(U0)
+    for dt, steps in ((1e-3, 3), (2e-3, 2)):
+        B.fr_rk_step(g.handle, Ug, dt, steps)
+        B.fr_rk_step(e.handle, Ue, dt, steps)
+        torch.cuda.synchronize()
+        assert torch.equal(Ug, Ue), (dt, steps)
+    assert not torch.equal(Ug, dev(U0))
+    g.close()
+    e.close()
+
+
+@pytest.mark.parametrize("prec", [B.FR_F64, B.FR_F32])
+@pytest.mark.parametrize("p,n,every,tol", [(2, (3, 2, 4), 1, 1e-3), (3, (2, 3, 3), 3, 1e-3),
+                                           (6, (2, 1, 2), 2, 3e-3), (1, (6, 5, 4), 1, 1e-3)])
+def test_dual_epilogue_bitwise(prec, p, n, every, tol):
+    import torch
+    g, e = pair(p, n, prec, None)
+    say("dual epilogue p=%d n=%s prec=%d every=%d" % (p, n, prec, every))
+    Unm1 = inputs.tgv(p, n, noise=1e-4, seed=7)
+    dUm = dev(Unm1)
+    dUn = dUm.clone()
+    B.fr_rk_step(e.handle, dUn, 2.5e-3, 4)
+    torch.cuda.synchronize()
+    G0 = (2 * dUn - dUm).cpu().numpy()
+    for Um, tol, maxit in ((dUm, tol, 500), (None, tol, 500), (dUm, 1e-12, 9)):
+        outs = []
+        for pl in (g, e):
+            U = dev(G0)
+            rc, it, res = B.fr_dual_step(pl.handle, U, dUn, Um, 1e-2, 1e-3, tol, maxit,
+                                         check_every=every, raise_on_error=False)
+            torch.cuda.synchronize()
+            outs.append((rc, it, res, U))
+        (rg, ig, sg, Ug), (re, ie, se, Ue) = outs
+        assert (rg, ig) == (re, ie), (Um is None, tol)
+        assert abs(sg - se) <= 1e-12 * abs(se)
+        assert torch.equal(Ug, Ue)
+        assert rg == (B.FR_ENOCONV if maxit == 9 else B.FR_OK)
+    g.close()
+    e.close()
+
+
+def test_fuse_stage_option():
+    pl = B.Plan(1, (2, 2, 2), ZETA, NU, T_CFG)
+    assert B.fr_plan_get_int(pl.handle, B.FR_OPT_FUSE_STAGE) == 1
+    pl.set(B.FR_OPT_FUSE_STAGE, 0)
+    assert B.fr_plan_get_int(pl.handle, B.FR_OPT_FUSE_STAGE) == 0
+    with pytest.raises(Exception):
+        pl.set(B.FR_OPT_FUSE_STAGE, 3)
+    pl.close()
