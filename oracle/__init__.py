@@ -17,6 +17,9 @@ Pin status (tests/test_oracle_*.py):
   rk4                                            pinned (closed-form linear mode)
   dual_step                                      pinned (closed-form BDF recurrence)
   extrap                                         pinned (exact on quadratics)
+  pmg.* (P-multigrid dual stepping, pmg.py)      pinned (projection/interpolation
+                                                 exactness, closed-form cycle factors,
+                                                 FAS fixed point, reduction to dual_step)
   mlp_*                                          pinned (finite differences, autograd)
 """
 import ctypes
