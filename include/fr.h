@@ -164,6 +164,51 @@ int fr_dual_step(fr_plan *plan, double *U, const double *Un, const double *Unm1,
                  double *resid, fr_stream_t s);
 
 /*
+ * P-multigrid dual time stepping (Sec. 5: the pseudo-iterations are accelerated
+ * by a P-multigrid cycle of (order, pseudo-steps), the pseudo-step growing by a
+ * constant factor per level below the finest; the paper's cycle for order 4 is
+ * [(4,1), (3,1), (2,1), (1,4), (2,1), (3,1), (4,7)] with a factor of 1.75).
+ * Full-approximation scheme: level l solves dU/dtau = R*_l(U) + d_l, with R*_l
+ * the pseudo-residual of fr_dual_step on order l whose BDF constant is the
+ * restriction of the finest level's, and d_l = 0 on the finest level;
+ *   going down from order h to l = h - 1:  r_h = R*_h(U_h) + d_h,
+ *     U_l = I U_h (kept as U_l^0),  d_l = I r_h - R*_l(U_l);
+ *   going up from l to h:  U_h += P (U_l - U_l^0);
+ * I is the L2 projection onto degree l per direction, P the interpolation of
+ * the coarse polynomial at the fine points (tensor products per element).
+ * Every level takes classical RK4 pseudo-steps of dtau * factor^(P - l).
+ *
+ * fr_pmg_create -- a cycle for the plan `fine` (borrowed: it must outlive the
+ * returned object).  orders/steps hold nlevels entries; the cycle starts and
+ * ends on the fine plan's order and consecutive orders differ by one.  With
+ * nlevels = 0 and both arrays NULL the paper's cycle shape is used for the
+ * fine plan's order P: one pseudo-step per order going down, four on order 1,
+ * one per order going up, seven on order P.  factor > 0.  Creates one plan per
+ * coarser order and allocates their state arrays on the current device.
+ * Returns NULL on error (fr_last_error() says why).
+ */
+typedef struct fr_pmg fr_pmg;
+fr_pmg *fr_pmg_create(fr_plan *fine, int nlevels, const int *orders, const int *steps,
+                      double factor);
+
+/*
+ * fr_pmg_dual_step -- one physical time step (BDF2, or BDF1 when Unm1 is NULL)
+ * by P-multigrid cycles.  Convergence (RMS over all points of the velocity
+ * part of the finest level's R* below tol) is tested before the first cycle
+ * and after each cycle.  The coarse plans take the fine plan's precision,
+ * variant and stage-fusion settings.  Arguments as fr_dual_step; cycles: out,
+ * completed cycles.  Synchronises the stream once per cycle.  Returns FR_OK,
+ * FR_ENOCONV (max_cycles completed, U holds the last iterate) or
+ * FR_ENONFINITE.
+ */
+int fr_pmg_dual_step(fr_pmg *mg, double *U, const double *Un, const double *Unm1, double dt,
+                     double dtau, double tol, int max_cycles, int *cycles, double *resid,
+                     fr_stream_t s);
+
+/* Release the coarse plans and arrays (waits for the device). */
+void fr_pmg_destroy(fr_pmg *mg);
+
+/*
  * fr_guess_extrap -- initial guess for the next physical step by polynomial
  * extrapolation in time of the past states (double state arrays):
  *   order 1: G = 2 Un - Unm1;   order 2: G = 3 Un - 3 Unm1 + Unm2.

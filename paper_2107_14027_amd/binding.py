@@ -23,7 +23,8 @@ EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_des
             "fr_state_len", "fr_residual", "fr_rk_step", "fr_dual_step", "fr_guess_extrap",
             "fr_strerror", "fr_last_error", "fr_plan_operators", "fr_plan_kernel_stats",
             "fr_mlp_state_floats", "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm",
-            "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess")
+            "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess",
+            "fr_pmg_create", "fr_pmg_dual_step", "fr_pmg_destroy")
 
 
 class FrError(RuntimeError):
@@ -73,7 +74,12 @@ def lib():
         L.fr_mlp_grad.argtypes = [_vp, _vp, _vp, _vp, I64, _vp, _vp, _vp]
         L.fr_mlp_train_step.argtypes = [_vp, _vp, _vp, _vp, I64, F, I, _vp, _vp]
         L.fr_mlp_guess.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
-        for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step",
+        L.fr_pmg_create.argtypes = [_vp, I, ctypes.POINTER(I), ctypes.POINTER(I), D]
+        L.fr_pmg_create.restype = _vp
+        L.fr_pmg_dual_step.argtypes = [_vp, _vp, _vp, _vp, D, D, D, I, ctypes.POINTER(I), _dp, _vp]
+        L.fr_pmg_destroy.argtypes = [_vp]
+        L.fr_pmg_destroy.restype = None
+        for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step", "fr_pmg_dual_step",
                   "fr_dual_step", "fr_guess_extrap", "fr_plan_operators", "fr_plan_kernel_stats",
                   "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm", "fr_mlp_forward",
                   "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess"):
@@ -172,6 +178,38 @@ def fr_dual_step(plan, U, Un, Unm1, dt, dtau, tol, max_iters, check_every=1, str
     if raise_on_error and rc not in (FR_OK, FR_ENOCONV):
         _check(rc)
     return rc, it.value, res.value
+
+
+def fr_pmg_create(plan, cycle=None, factor=1.75):
+    """cycle: list of (order, pseudo-steps), or None for the paper's cycle shape."""
+    if cycle is None:
+        ptr = lib().fr_pmg_create(plan, 0, None, None, float(factor))
+    else:
+        o = (ctypes.c_int * len(cycle))(*[int(c[0]) for c in cycle])
+        k = (ctypes.c_int * len(cycle))(*[int(c[1]) for c in cycle])
+        ptr = lib().fr_pmg_create(plan, len(cycle), o, k, float(factor))
+    if not ptr:
+        raise FrError(FR_EINVAL, lib().fr_last_error().decode())
+    return ptr
+
+
+def fr_pmg_dual_step(mg, U, Un, Unm1, dt, dtau, tol, max_cycles, n, stream=None,
+                     raise_on_error=True):
+    """Returns (status, cycles, resid); n is the fine plan's state length."""
+    import torch
+    cyc = ctypes.c_int()
+    res = ctypes.c_double()
+    rc = lib().fr_pmg_dual_step(mg, _dev(U, torch.float64, n, "U"), _dev(Un, torch.float64, n, "Un"),
+                                None if Unm1 is None else _dev(Unm1, torch.float64, n, "Unm1"),
+                                float(dt), float(dtau), float(tol), int(max_cycles),
+                                ctypes.byref(cyc), ctypes.byref(res), _stream(stream))
+    if raise_on_error and rc not in (FR_OK, FR_ENOCONV):
+        _check(rc)
+    return rc, cyc.value, res.value
+
+
+def fr_pmg_destroy(mg):
+    lib().fr_pmg_destroy(mg)
 
 
 def fr_guess_extrap(plan, Un, Unm1, Unm2, order, G, stream=None):
@@ -289,6 +327,29 @@ def fr_plan_operators(p):
         r[name] = out[o:o + size].reshape(shape)
         o += size
     return r
+
+
+class Pmg:
+    """Owning wrapper around an fr_pmg handle (the plan must stay open)."""
+
+    def __init__(self, plan, cycle=None, factor=1.75):
+        self.plan = plan
+        self.handle = fr_pmg_create(plan.handle, cycle, factor)
+
+    def dual_step(self, U, Un, Unm1, dt, dtau, tol, max_cycles, stream=None, raise_on_error=True):
+        return fr_pmg_dual_step(self.handle, U, Un, Unm1, dt, dtau, tol, max_cycles,
+                                self.plan.state_len, stream, raise_on_error)
+
+    def close(self):
+        if self.handle:
+            fr_pmg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:

@@ -113,6 +113,144 @@ int graph_run(fr_plan *pl, GraphCache &gc, const uint64_t (&key)[16], hipStream_
 
 }  // namespace
 
+namespace fr {
+
+int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const double *D,
+                   double dtau, double tol, int max_iters, int check_every, bool norm_last,
+                   int *iters, double *resid, int *converged, hipStream_t s)
+{
+    const bool f64 = pl->precision == FR_F64;
+    const int64_t n = (int64_t)fr_state_len(pl);
+    const int ns = pl->m * pl->m * pl->m;
+    RkBufs b;
+    if (int rc = rk_buffers(pl, b)) return rc;
+    const size_t nB = (size_t)pl->ne * 3 * ns;
+    // the double copy of the stage state the BDF term needs (FP32) follows the
+    // BDF constant's slot in the plan's dual scratch
+    if (!f64)
+        if (int rc = ensure_scratch(pl->dual, (nB + (size_t)n) * sizeof(double))) return rc;
+    const int cap = std::max(stage_blocks(n), MAX_PARTIALS);
+    if (int rc = ensure_scratch(pl->norm, (size_t)(cap + 1) * sizeof(double))) return rc;
+    if (!pl->norm_host &&
+        check_hip(hipHostMalloc((void **)&pl->norm_host, sizeof(double), hipHostMallocDefault),
+                  "hipHostMalloc"))
+        return FR_ENOMEM;
+    double *st64 = f64 ? (double *)b.stT : (double *)pl->dual.ptr + nB;
+    double *partial = (double *)pl->norm.ptr;
+    double *sum = partial + cap;
+    int nparts = stage_blocks(n);  // partial sums the first stage writes
+
+    int rc = FR_OK;
+    if (!f64) rc = launch_to_precision(pl, U, b.stT, n, s);
+    const double c[4] = {0.0, 0.5 * dtau, 0.5 * dtau, dtau};
+    const double w[4] = {dtau / 6.0, dtau / 3.0, dtau / 3.0, dtau / 6.0};
+    const double count = 3.0 * (double)pl->ne * ns;
+    // first stage of a pseudo-step (residual of the current iterate, with the
+    // per-block partial sums of its velocity norm), the other three stages,
+    // and the reduction + read-back of the norm into pinned host memory.
+    // With the stage updates in the fused kernel's epilogue the stage states
+    // alternate between the two stage buffers, and the double copy of the stage
+    // state that the BDF term needs (FP32) is updated in place.  A fixed source
+    // D runs on the separate stage kernel.
+    const bool epi = stage_in_epilogue(pl) && !D;
+    void *const bufs[2] = {b.stT, b.k};
+    const int o = f64 ? 0 : 1;
+    auto stage0 = [&](hipStream_t st) -> int {
+        if (epi) {
+            const StageSpec sp{U, b.acc, nullptr, f64 ? nullptr : st64, bufs[o], B, partial,
+                               a, w[0], c[1], 1, 0};
+            return launch_residual_stage(pl, f64 ? (const void *)U : bufs[0], sp, &nparts, st);
+        }
+        if (int r = residual(pl, f64 ? (const void *)U : b.stT, b.k, st)) return r;
+        return launch_stage(pl, true, true, U, b.acc, st64, b.stT, b.k, B, a, w[0], c[1], 1, 0,
+                            partial, st, D);
+    };
+    auto stages123 = [&](hipStream_t st) -> int {
+        if (epi) {
+            for (int k = 1; k < 4; ++k) {
+                const bool last = k == 3;
+                void *in = bufs[(k - 1 + o) % 2];
+                void *out = last ? (f64 ? nullptr : bufs[0]) : bufs[(k + o) % 2];
+                const StageSpec sp{U, b.acc, f64 ? (const double *)in : st64,
+                                   (f64 || last) ? nullptr : st64, out, B, nullptr,
+                                   a, w[k], last ? 0.0 : c[k + 1], 0, last};
+                if (int r = launch_residual_stage(pl, in, sp, nullptr, st)) return r;
+            }
+            return FR_OK;
+        }
+        for (int k = 1; k < 4; ++k) {
+            if (int r = residual(pl, b.stT, b.k, st)) return r;
+            const bool last = k == 3;
+            if (int r = launch_stage(pl, true, false, U, b.acc, st64, (last && f64) ? nullptr : b.stT,
+                                     b.k, B, a, w[k], last ? 0.0 : c[k + 1], 0, last, nullptr, st, D))
+                return r;
+        }
+        return FR_OK;
+    };
+    auto readback = [&](hipStream_t st) -> int {
+        if (int r = launch_final_sum(partial, nparts, sum, st)) return r;
+        return check_hip(hipMemcpyAsync(pl->norm_host, sum, sizeof(double), hipMemcpyDeviceToHost, st),
+                         "hipMemcpyAsync(norm)");
+    };
+    int it = 0;
+    double res = NAN;
+    auto wait_norm = [&]() -> int {
+        if (int r = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize")) return r;
+        res = std::sqrt(*pl->norm_host / count);
+        if (!std::isfinite(res))
+            return set_error(FR_ENONFINITE, "pseudo-residual norm is %g after %d steps", res, it);
+        return FR_OK;
+    };
+    // is the norm of iterate j read back?
+    auto checked = [&](int j) {
+        return check_every > 0 ? (j % check_every == 0 || j >= max_iters)
+                               : (norm_last && j >= max_iters);
+    };
+    // iterate `it` has had its first stage (unless it is the last and its norm
+    // is not wanted); its norm is known when `have`
+    bool have = checked(0);
+    if (!rc && (max_iters > 0 || have)) rc = stage0(s);
+    if (!rc && have) rc = readback(s);
+    if (!rc && have) rc = wait_norm();
+    *converged = 0;
+    const bool graphs = pl->use_graphs && !pl->profile;
+    while (!rc) {
+        if (have && res < tol) {
+            *converged = 1;
+            break;
+        }
+        if (it >= max_iters) break;
+        const bool check = checked(it + 1);
+        const bool next0 = it + 1 < max_iters || check;
+        auto body = [&](hipStream_t st) -> int {
+            if (int r = stages123(st)) return r;
+            if (!next0) return FR_OK;
+            if (int r = stage0(st)) return r;
+            return check ? readback(st) : FR_OK;
+        };
+        if (graphs) {
+            const uint64_t key[16] = {1, (uint64_t)U, (uint64_t)B, (uint64_t)D, bits(a), bits(dtau),
+                                      (uint64_t)check | (uint64_t)next0 << 1, (uint64_t)pl->rk.ptr,
+                                      (uint64_t)pl->dual.ptr, (uint64_t)pl->norm.ptr,
+                                      (uint64_t)pl->traces.ptr, (uint64_t)pl->unfused.ptr,
+                                      config_word(pl), (uint64_t)pl->norm_host,
+                                      (uint64_t)nparts};
+            rc = graph_run(pl, pl->graphs[check ? 0 : 1], key, s, body);
+        } else {
+            rc = body(s);
+        }
+        if (rc) break;
+        ++it;
+        have = check;
+        if (check) rc = wait_norm();
+    }
+    *iters = it;
+    *resid = res;
+    return rc;
+}
+
+}  // namespace fr
+
 extern "C" {
 
 int fr_residual(fr_plan *pl, const void *U, void *R, fr_stream_t s)
@@ -200,122 +338,19 @@ int fr_dual_step(fr_plan *pl, double *U, const double *Un, const double *Unm1, d
                          dtau, tol, max_iters, check_every);
     hipStream_t s = (hipStream_t)sv;
     const bool f64 = pl->precision == FR_F64;
-    const int64_t n = (int64_t)fr_state_len(pl);
-    const int ns = pl->m * pl->m * pl->m;
-    RkBufs b;
-    if (int rc = rk_buffers(pl, b)) return rc;
-    const size_t nB = (size_t)pl->ne * 3 * ns;
-    if (int rc = ensure_scratch(pl->dual, (nB + (f64 ? 0 : (size_t)n)) * sizeof(double))) return rc;
-    const int cap = std::max(stage_blocks(n), MAX_PARTIALS);
-    if (int rc = ensure_scratch(pl->norm, (size_t)(cap + 1) * sizeof(double))) return rc;
-    if (!pl->norm_host &&
-        check_hip(hipHostMalloc((void **)&pl->norm_host, sizeof(double), hipHostMallocDefault),
-                  "hipHostMalloc"))
-        return FR_ENOMEM;
+    const size_t n = fr_state_len(pl);
+    const size_t nB = (size_t)pl->ne * 3 * pl->m * pl->m * pl->m;
+    if (int rc = ensure_scratch(pl->dual, (nB + (f64 ? 0 : n)) * sizeof(double))) return rc;
     double *B = (double *)pl->dual.ptr;
-    double *st64 = f64 ? (double *)b.stT : B + nB;
-    double *partial = (double *)pl->norm.ptr;
-    double *sum = partial + cap;
-    int nparts = stage_blocks(n);  // partial sums the first stage writes
-
-    int rc = launch_bdf_const(pl, Un, Unm1, dt, B, s);
-    const double a = Unm1 ? 1.5 / dt : 1.0 / dt;
-    if (!rc && !f64) rc = launch_to_precision(pl, U, b.stT, n, s);
-    const double c[4] = {0.0, 0.5 * dtau, 0.5 * dtau, dtau};
-    const double w[4] = {dtau / 6.0, dtau / 3.0, dtau / 3.0, dtau / 6.0};
-    const double count = 3.0 * (double)pl->ne * ns;
-    // first stage of a pseudo-step (residual of the current iterate, with the
-    // per-block partial sums of its velocity norm), the other three stages,
-    // and the reduction + read-back of the norm into pinned host memory
-    // with the stage updates in the fused kernel's epilogue the stage states
-    // alternate between the two stage buffers, and the double copy of the stage
-    // state that the BDF term needs (FP32) is updated in place
-    const bool epi = stage_in_epilogue(pl);
-    void *const bufs[2] = {b.stT, b.k};
-    const int o = f64 ? 0 : 1;
-    auto stage0 = [&](hipStream_t st) -> int {
-        if (epi) {
-            const StageSpec sp{U, b.acc, nullptr, f64 ? nullptr : st64, bufs[o], B, partial,
-                               a, w[0], c[1], 1, 0};
-            return launch_residual_stage(pl, f64 ? (const void *)U : bufs[0], sp, &nparts, st);
-        }
-        if (int r = residual(pl, f64 ? (const void *)U : b.stT, b.k, st)) return r;
-        return launch_stage(pl, true, true, U, b.acc, st64, b.stT, b.k, B, a, w[0], c[1], 1, 0,
-                            partial, st);
-    };
-    auto stages123 = [&](hipStream_t st) -> int {
-        if (epi) {
-            for (int k = 1; k < 4; ++k) {
-                const bool last = k == 3;
-                void *in = bufs[(k - 1 + o) % 2];
-                void *out = last ? (f64 ? nullptr : bufs[0]) : bufs[(k + o) % 2];
-                const StageSpec sp{U, b.acc, f64 ? (const double *)in : st64,
-                                   (f64 || last) ? nullptr : st64, out, B, nullptr,
-                                   a, w[k], last ? 0.0 : c[k + 1], 0, last};
-                if (int r = launch_residual_stage(pl, in, sp, nullptr, st)) return r;
-            }
-            return FR_OK;
-        }
-        for (int k = 1; k < 4; ++k) {
-            if (int r = residual(pl, b.stT, b.k, st)) return r;
-            const bool last = k == 3;
-            if (int r = launch_stage(pl, true, false, U, b.acc, st64, (last && f64) ? nullptr : b.stT,
-                                     b.k, B, a, w[k], last ? 0.0 : c[k + 1], 0, last, nullptr, st))
-                return r;
-        }
-        return FR_OK;
-    };
-    auto readback = [&](hipStream_t st) -> int {
-        if (int r = launch_final_sum(partial, nparts, sum, st)) return r;
-        return check_hip(hipMemcpyAsync(pl->norm_host, sum, sizeof(double), hipMemcpyDeviceToHost, st),
-                         "hipMemcpyAsync(norm)");
-    };
-    int it = 0;
-    double res = NAN;
-    auto wait_norm = [&]() -> int {
-        if (int r = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize")) return r;
-        res = std::sqrt(*pl->norm_host / count);
-        if (!std::isfinite(res))
-            return set_error(FR_ENONFINITE, "pseudo-residual norm is %g after %d steps", res, it);
-        return FR_OK;
-    };
-    // iterate `it` has had its first stage; its norm is known when `have`
-    if (!rc) rc = stage0(s);
-    if (!rc) rc = readback(s);
-    if (!rc) rc = wait_norm();
-    bool have = true;
-    const bool graphs = pl->use_graphs && !pl->profile;
-    while (!rc) {
-        if (have && res < tol) break;
-        if (it >= max_iters) {
-            rc = set_error(FR_ENOCONV, "no convergence in %d pseudo-steps (residual %g)", it, res);
-            break;
-        }
-        const bool check = (it + 1) % check_every == 0 || it + 1 >= max_iters;
-        auto body = [&](hipStream_t st) -> int {
-            if (int r = stages123(st)) return r;
-            if (int r = stage0(st)) return r;
-            return check ? readback(st) : FR_OK;
-        };
-        if (graphs) {
-            const uint64_t key[16] = {1, (uint64_t)U, (uint64_t)Un, (uint64_t)Unm1, bits(dt),
-                                      bits(dtau), (uint64_t)check, (uint64_t)pl->rk.ptr,
-                                      (uint64_t)pl->dual.ptr, (uint64_t)pl->norm.ptr,
-                                      (uint64_t)pl->traces.ptr, (uint64_t)pl->unfused.ptr,
-                                      config_word(pl), (uint64_t)pl->norm_host,
-                                      (uint64_t)nparts};
-            rc = graph_run(pl, pl->graphs[check ? 0 : 1], key, s, body);
-        } else {
-            rc = body(s);
-        }
-        if (rc) break;
-        ++it;
-        have = check;
-        if (check) rc = wait_norm();
-    }
-    *iters = it;
-    *resid = res;
-    return rc;
+    if (int rc = launch_bdf_const(pl, Un, Unm1, dt, B, s)) return rc;
+    int conv = 0;
+    const int rc = pseudo_iterate(pl, U, B, Unm1 ? 1.5 / dt : 1.0 / dt, nullptr, dtau, tol,
+                                  max_iters, check_every, true, iters, resid, &conv, s);
+    if (rc) return rc;
+    if (!conv)
+        return set_error(FR_ENOCONV, "no convergence in %d pseudo-steps (residual %g)", *iters,
+                         *resid);
+    return FR_OK;
 }
 
 int fr_guess_extrap(fr_plan *pl, const double *Un, const double *Unm1, const double *Unm2,

@@ -152,11 +152,22 @@ int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *
                           hipStream_t s);
 bool fused_stage_available(const fr_plan *pl);
 
+// Up to max_iters classical RK4 pseudo-steps of dU/dtau = R(U) - M_V (a U + B)
+// + D (D may be null) on plan pl, from U (double, in place).  The RMS of the
+// velocity part of the first-stage residual is read back (one host wait) for
+// iterates 0, check_every, 2 check_every, ... and max_iters (check_every > 0),
+// or only for iterate max_iters when check_every == 0 and norm_last; the loop
+// stops early once a read norm is below tol (*converged = 1).  *iters counts
+// completed pseudo-steps, *resid is the last norm read (NaN if none).
+int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const double *D,
+                   double dtau, double tol, int max_iters, int check_every, bool norm_last,
+                   int *iters, double *resid, int *converged, hipStream_t s);
+
 // time integration kernels (timeint.hip)
 int stage_blocks(int64_t n);
 int launch_stage(fr_plan *pl, bool bdf, bool norm, double *U, double *acc, double *st64,
                  void *stT, const void *k, const double *B, double a, double b, double cnext,
-                 int first, int last, double *partial, hipStream_t s);
+                 int first, int last, double *partial, hipStream_t s, const double *D = nullptr);
 int launch_to_precision(fr_plan *pl, const double *U, void *out, int64_t n, hipStream_t s);
 int launch_bdf_const(fr_plan *pl, const double *Un, const double *Unm1, double dt, double *B,
                      hipStream_t s);

@@ -32,7 +32,8 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return s;
 }
 
-// One RK4 stage of dU/dtau = k*, with k* = k - [v in V] (a s + B) when bdf:
+// One RK4 stage of dU/dtau = k*, with k* = k - [v in V] (a s + B) when bdf,
+// plus D (a fixed source, when given):
 //   first stage: acc = U + b k*,  else acc += b k*
 //   then the next stage state  s' = U + cnext k*  -> st64 (double) and stT (T)
 //   last stage:  U = acc + b k*, stT = (T) U
@@ -41,7 +42,8 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 template <typename T, bool BDF, bool NORM>
 __global__ void __launch_bounds__(TB) k_stage(double *__restrict__ U, double *__restrict__ acc,
                                               double *st64, T *stT, const T *__restrict__ k,
-                                              const double *__restrict__ B, double a, double b,
+                                              const double *__restrict__ B,
+                                              const double *__restrict__ D, double a, double b,
                                               double cnext, int first, int last, int64_t n, int ns,
                                               double *__restrict__ partial)
 {
@@ -49,18 +51,19 @@ __global__ void __launch_bounds__(TB) k_stage(double *__restrict__ U, double *__
     double ss = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
         double kv = (double)k[i];
+        bool vel = false;
         if (BDF || NORM) {
             const int64_t r = i / ns;
             const int v = (int)(r % NV);
-            if (v >= 1 && v <= 3) {
-                if (BDF) {
-                    const double sv = first ? U[i] : st64[i];
-                    const int64_t e = r / NV;
-                    kv -= fma(a, sv, B[(e * 3 + (v - 1)) * ns + (i - r * ns)]);
-                }
-                if (NORM) ss = fma(kv, kv, ss);
+            vel = v >= 1 && v <= 3;
+            if (BDF && vel) {
+                const double sv = first ? U[i] : st64[i];
+                const int64_t e = r / NV;
+                kv -= fma(a, sv, B[(e * 3 + (v - 1)) * ns + (i - r * ns)]);
             }
         }
+        if (D) kv += D[i];
+        if (NORM && vel) ss = fma(kv, kv, ss);
         if (last) {
             const double un = fma(b, kv, acc[i]);
             U[i] = un;
@@ -125,24 +128,25 @@ __global__ void __launch_bounds__(TB) k_extrap(const double *__restrict__ Un,
 
 template <typename T>
 int stage_dispatch(bool bdf, bool norm, double *U, double *acc, double *st64, void *stT,
-                   const void *k, const double *B, double a, double b, double cnext, int first,
-                   int last, int64_t n, int ns, double *partial, hipStream_t s)
+                   const void *k, const double *B, const double *D, double a, double b,
+                   double cnext, int first, int last, int64_t n, int ns, double *partial,
+                   hipStream_t s)
 {
     const unsigned g = grid_for(n);
     T *st = (T *)stT;
     const T *kk = (const T *)k;
     if (bdf && norm)
         hipLaunchKernelGGL((k_stage<T, true, true>), dim3(g), dim3(TB), 0, s, U, acc, st64, st, kk,
-                           B, a, b, cnext, first, last, n, ns, partial);
+                           B, D, a, b, cnext, first, last, n, ns, partial);
     else if (bdf)
         hipLaunchKernelGGL((k_stage<T, true, false>), dim3(g), dim3(TB), 0, s, U, acc, st64, st,
-                           kk, B, a, b, cnext, first, last, n, ns, partial);
+                           kk, B, D, a, b, cnext, first, last, n, ns, partial);
     else if (norm)
         hipLaunchKernelGGL((k_stage<T, false, true>), dim3(g), dim3(TB), 0, s, U, acc, st64, st,
-                           kk, B, a, b, cnext, first, last, n, ns, partial);
+                           kk, B, D, a, b, cnext, first, last, n, ns, partial);
     else
         hipLaunchKernelGGL((k_stage<T, false, false>), dim3(g), dim3(TB), 0, s, U, acc, st64, st,
-                           kk, B, a, b, cnext, first, last, n, ns, partial);
+                           kk, B, D, a, b, cnext, first, last, n, ns, partial);
     return check_hip(hipGetLastError(), "k_stage launch");
 }
 
@@ -152,16 +156,16 @@ int stage_blocks(int64_t n) { return (int)grid_for(n); }
 
 int launch_stage(fr_plan *pl, bool bdf, bool norm, double *U, double *acc, double *st64,
                  void *stT, const void *k, const double *B, double a, double b, double cnext,
-                 int first, int last, double *partial, hipStream_t s)
+                 int first, int last, double *partial, hipStream_t s, const double *D)
 {
     const int64_t n = (int64_t)fr_state_len(pl);
     const int ns = pl->m * pl->m * pl->m;
     ProfScope ps(pl, FR_K_STAGE, s);
     if (pl->precision == FR_F64)
-        return stage_dispatch<double>(bdf, norm, U, acc, st64, stT, k, B, a, b, cnext, first, last,
-                                      n, ns, partial, s);
-    return stage_dispatch<float>(bdf, norm, U, acc, st64, stT, k, B, a, b, cnext, first, last, n,
-                                 ns, partial, s);
+        return stage_dispatch<double>(bdf, norm, U, acc, st64, stT, k, B, D, a, b, cnext, first,
+                                      last, n, ns, partial, s);
+    return stage_dispatch<float>(bdf, norm, U, acc, st64, stT, k, B, D, a, b, cnext, first, last,
+                                 n, ns, partial, s);
 }
 
 int launch_to_precision(fr_plan *pl, const double *U, void *out, int64_t n, hipStream_t s)

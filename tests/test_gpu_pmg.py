@@ -1,0 +1,129 @@
+"""GPU parity of P-multigrid dual time stepping (fr_pmg_*) against the oracle's
+FAS cycle (oracle/pmg.py): fixed numbers of cycles compared element by element,
+the closed form on uniform states, converged steps, custom cycles, both
+precisions and both residual variants."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import pmg as opmg
+from paper_2107_14027_amd import binding as B
+from paper_2107_14027_amd import inputs
+from gpu_util import NU, T_CFG, ZETA, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(U):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(U)).to("cuda")
+
+
+def case(P, n, seed=1):
+    Unm1 = inputs.tgv(P, n, noise=1e-4, seed=seed)
+    Un = oracle.rk4(P, n, Unm1, ZETA, NU, T_CFG, 2.5e-3, 4)
+    return 2 * Un - Unm1, Un, Unm1
+
+
+def gpu_pmg(P, n, G, Un, Unm1, dt, dtau, tol, maxc, prec=B.FR_F64, var=B.FR_FUSED, cycle=None,
+            factor=1.75, T=T_CFG):
+    import torch
+    plan = B.Plan(P, n, ZETA, NU, T, None, prec, var)
+    mg = B.Pmg(plan, cycle, factor)
+    U = dev(G)
+    rc, cyc, res = mg.dual_step(U, dev(Un), None if Unm1 is None else dev(Unm1), dt, dtau, tol, maxc,
+                                raise_on_error=False)
+    torch.cuda.synchronize()
+    out = U.cpu().numpy()
+    mg.close()
+    plan.close()
+    return out, rc, cyc, res
+
+
+@pytest.mark.parametrize("P,n,bdf2", [(2, (3, 2, 2), True), (3, (2, 3, 2), True),
+                                      (3, (2, 2, 3), False), (4, (2, 2, 2), True)])
+def test_fixed_cycles_match_oracle(P, n, bdf2):
+    G, Un, Unm1 = case(P, n)
+    Um = Unm1 if bdf2 else None
+    say("pmg fixed cycles P=%d n=%s bdf2=%s" % (P, n, bdf2))
+    Ug, rc, cyc, res = gpu_pmg(P, n, G, Un, Um, 1e-2, 1e-3, 1e-30, 2)
+    Uo, cyco, reso, rco = opmg.pmg_dual_step(P, n, G, Un, Um, ZETA, NU, T_CFG, 1e-2, 1e-3, 1e-30, 2)
+    assert rc == B.FR_ENOCONV and rco == -5 and cyc == cyco == 2
+    assert rel(Ug.reshape(-1), Uo) <= 1e-11
+    assert rel(Ug.reshape(-1) - G.reshape(-1), Uo - G.reshape(-1)) <= 1e-9
+    assert abs(res - reso) <= 1e-9 * reso
+
+
+@pytest.mark.parametrize("var", [B.FR_FUSED, B.FR_UNFUSED])
+def test_fp32_and_unfused(var):
+    P, n = 3, (3, 2, 2)
+    G, Un, Unm1 = case(P, n, seed=3)
+    say("pmg fp32 var=%d" % var)
+    Uo, _, reso, _ = opmg.pmg_dual_step(P, n, G, Un, Unm1, ZETA, NU, T_CFG, 1e-2, 1e-3, 1e-30, 2)
+    U32, rc, cyc, res = gpu_pmg(P, n, G, Un, Unm1, 1e-2, 1e-3, 1e-30, 2, prec=B.FR_F32, var=var)
+    assert rc == B.FR_ENOCONV and cyc == 2
+    assert rel(U32.reshape(-1), Uo) <= 1e-5
+    assert abs(res - reso) <= 1e-3 * reso
+    U64, rc, cyc, res = gpu_pmg(P, n, G, Un, Unm1, 1e-2, 1e-3, 1e-30, 2, var=var)
+    assert rel(U64.reshape(-1), Uo) <= 1e-11
+
+
+def test_custom_cycle_and_factor():
+    P, n = 3, (2, 2, 2)
+    G, Un, Unm1 = case(P, n, seed=4)
+    cyc = [(3, 2), (2, 3), (1, 2), (2, 0), (3, 1)]
+    say("pmg custom cycle")
+    Ug, rc, c, res = gpu_pmg(P, n, G, Un, Unm1, 1e-2, 1e-3, 1e-30, 3, cycle=cyc, factor=1.5)
+    Uo, co, reso, rco = opmg.pmg_dual_step(P, n, G, Un, Unm1, ZETA, NU, T_CFG, 1e-2, 1e-3, 1e-30, 3,
+                                           cycle=cyc, factor=1.5)
+    assert c == co == 3
+    assert rel(Ug.reshape(-1), Uo) <= 1e-11
+
+
+def test_closed_form_uniform():
+    P, n, T = 3, (2, 1, 2), 40.528
+    dt, dtau, fac = 1e-2, 1e-3, 1.75
+    Vn, Vm1 = np.array([0.3, -0.2, 0.1]), np.array([0.28, -0.25, 0.12])
+    q0 = np.linspace(0.01, 0.09, 9)
+    mk = lambda V: inputs.uniform(P, n, np.concatenate([[0.9], V, q0]))
+    say("pmg closed form")
+    U, rc, cyc, res = gpu_pmg(P, n, mk(2 * Vn - Vm1), mk(Vn), mk(Vm1), dt, dtau, 1e-30, 2, T=T)
+    Vs, a = (4 * Vn - Vm1) / 3, 1.5 / dt
+    t4 = lambda z: 1 - z + z * z / 2 - z ** 3 / 6 + z ** 4 / 24
+    cy = opmg.default_cycle(P)
+    fv = np.prod([t4(a * dtau * fac ** (P - p)) ** k for p, k in cy]) ** 2
+    fq = np.prod([t4(dtau * fac ** (P - p) / T) ** k for p, k in cy]) ** 2
+    U = U.reshape(-1, 13, 64)
+    assert np.allclose(U[:, 1:4], (Vs + ((2 * Vn - Vm1) - Vs) * fv)[None, :, None], rtol=0, atol=1e-13)
+    assert np.allclose(U[:, 4:], (q0 * fq)[None, :, None], rtol=1e-12, atol=0)
+
+
+def test_converges_like_oracle():
+    P, n = 3, (2, 2, 2)
+    G, Un, Unm1 = case(P, n, seed=2)
+    tol = 1.2e-3
+    say("pmg converged")
+    Ug, rc, cyc, res = gpu_pmg(P, n, G, Un, Unm1, 1e-2, 1e-3, tol, 100)
+    Uo, cyco, reso, rco = opmg.pmg_dual_step(P, n, G, Un, Unm1, ZETA, NU, T_CFG, 1e-2, 1e-3, tol, 100)
+    assert rc == B.FR_OK and rco == 0 and res < tol
+    assert abs(cyc - cyco) <= 1
+    if cyc == cyco:
+        assert rel(Ug.reshape(-1), Uo) <= 1e-11
+
+
+def test_errors():
+    plan = B.Plan(3, (2, 2, 2), ZETA, NU, T_CFG)
+    for cyc in ([(3, 1), (1, 1), (3, 1)], [(2, 1), (3, 1)], [(3, 1), (2, -1), (3, 1)]):
+        with pytest.raises(B.FrError):
+            B.Pmg(plan, cyc)
+    with pytest.raises(B.FrError):
+        B.Pmg(plan, None, factor=0.0)
+    G, Un, Unm1 = case(3, (2, 2, 2))
+    bad = G.copy()
+    bad.reshape(-1)[5] = np.nan
+    mg = B.Pmg(plan)
+    rc, cyc, res = mg.dual_step(dev(bad), dev(Un), dev(Unm1), 1e-2, 1e-3, 1e-6, 3,
+                                raise_on_error=False)
+    assert rc == B.FR_ENONFINITE
+    mg.close()
+    plan.close()
