@@ -292,6 +292,9 @@ def main():
         from paper_2107_14027_amd import learned as L
         t0 = time.perf_counter()
         r = L.run(guess_base=1)
+        t1 = time.perf_counter()
+        rp = L.run(guess_base=1, solver="pmg")
+        mp = rp["modes"]
         m = r["modes"]
         learned = {
             "unit": "pseudo-iterations per physical step (mean over the evaluation steps)",
@@ -310,7 +313,26 @@ def main():
             "learned_vs_quadratic": round(r["mlp_vs_quadratic_iters"], 4),
             "learned_vs_linear": round(r["mlp_vs_linear_iters"], 4),
             "training_loss": r["loss_curve"][-1][1],
-            "seconds": round(time.perf_counter() - t0, 1)}
+            "seconds": round(t1 - t0, 1),
+            "pmg_solver": {
+                "unit": "P-multigrid cycles per physical step (cycle [(p,1),...,(1,4),...,(p,7)], "
+                        "pseudo-step x1.75 per level), same protocol",
+                "learned": round(mp["mlp"]["iters_mean"], 2),
+                "quadratic_extrap": round(mp["extrap"]["iters_mean"], 2),
+                "linear_extrap": round(mp["extrap1"]["iters_mean"], 2),
+                "learned_with_residual_fallback": round(mp["mlp_fallback"]["iters_mean"], 2),
+                "capped": {k: mp[v]["capped"] for k, v in (("learned", "mlp"),
+                                                           ("quadratic_extrap", "extrap"),
+                                                           ("linear_extrap", "extrap1"))},
+                "ms_per_step": {k: round(mp[v]["ms_per_step"], 1) for k, v in
+                                (("learned", "mlp"), ("quadratic_extrap", "extrap"),
+                                 ("linear_extrap", "extrap1"))},
+                "rk4_ms_per_step": {k: round(m[v]["ms_per_step"], 1) for k, v in
+                                    (("learned", "mlp"), ("quadratic_extrap", "extrap"),
+                                     ("linear_extrap", "extrap1"))},
+                "learned_vs_quadratic": round(rp["mlp_vs_quadratic_iters"], 4),
+                "learned_vs_linear": round(rp["mlp_vs_linear_iters"], 4),
+                "seconds": round(time.perf_counter() - t1, 1)}}
         log("learned guess: %s" % learned)
 
     out = {

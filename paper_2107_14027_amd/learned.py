@@ -11,6 +11,9 @@ Protocol (dual time stepping, BDF2, RK4 pseudo-steps, Taylor-Green field):
   network kept only where its initial pseudo-residual is not larger than the
   quadratic extrapolation's, recording the completed pseudo-steps of every
   physical step.  The network corrects the extrapolation chosen by guess_base.
+  With solver="pmg" every physical step runs P-multigrid cycles instead (the
+  paper's cycle shape for order p, pseudo-step x1.75 per level), and the counts
+  are completed cycles.
 Defaults: p = 3 on 16^3 hexes, dt = 5e-2 with dtau = dt/10 (the paper's ratio),
 tolerance 1e-6; the iteration counts are set by the slowest (k = 1) pressure
 mode, whose rate does not depend on the lattice.
@@ -37,12 +40,17 @@ def log(*a):
 
 def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
         eval_steps=20, samples_per_step=1 << 14, epochs=2000, lr=2e-3, batch=1 << 16,
-        zeta=4.0, Re=1600.0, Lr=1.0 / (2.0 * math.pi), seed=5, precision=B.FR_F64, guess_base=2):
+        zeta=4.0, Re=1600.0, Lr=1.0 / (2.0 * math.pi), seed=5, precision=B.FR_F64, guess_base=2,
+        solver="rk4", max_cycles=400):
     import torch
     nu, T = inputs.nu_T_from_length(Re, Lr)
     n = (N, N, N)
     plan = B.Plan(p, n, zeta, nu, T, precision=precision)
     plan.set(B.FR_OPT_GUESS_BASE, guess_base)
+    if solver not in ("rk4", "pmg"):
+        raise ValueError("solver %r" % solver)
+    mg = B.Pmg(plan) if solver == "pmg" else None
+    unit = "cycles" if mg is not None else "pseudo-steps"
     ns = plan.state_len
     npts = ns // 13
     U0 = inputs.tgv(p, n)
@@ -51,8 +59,11 @@ def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
 
     def step(guess, Un, Unm1):
         U = guess.clone()
-        rc, it, res = B.fr_dual_step(plan.handle, U, Un, Unm1, dt, dtau, tol, max_iters,
-                                     raise_on_error=False)
+        if mg is None:
+            rc, it, res = B.fr_dual_step(plan.handle, U, Un, Unm1, dt, dtau, tol, max_iters,
+                                         raise_on_error=False)
+        else:
+            rc, it, res = mg.dual_step(U, Un, Unm1, dt, dtau, tol, max_cycles, raise_on_error=False)
         if rc not in (B.FR_OK, B.FR_ENOCONV):
             raise Diverged("pseudo-iteration failed (status %d, residual %g after %d steps)"
                            % (rc, res, it))
@@ -89,8 +100,8 @@ def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
         hist.append(U)
         hist = hist[-3:]
         if s % 10 == 0 or s <= 3:
-            log("train step %d: %d pseudo-steps, residual %.3e, rc %d (%.0f s)" %
-                (s, it, res, rc, time.time() - t0))
+            log("train step %d: %d %s, residual %.3e, rc %d (%.0f s)" %
+                (s, it, unit, res, rc, time.time() - t0))
     # fit the network
     state = B.mlp_new_state(seed)
     Xr, Yr = X[:nrows], Y[:nrows]
@@ -133,15 +144,18 @@ def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
             hs.append(U)
             hs = hs[-3:]
             if s % 5 == 0:
-                log("%s step %d: %d pseudo-steps, initial residual %.3e, rc %d" % (mode, s, it, r0, rc))
+                log("%s step %d: %d %s, initial residual %.3e, rc %d" % (mode, s, it, unit, r0, rc))
         res_by[mode] = {"iters": its, "initial_residual": r0s, "rc": rcs, "fallback": fallback,
                         "seconds": time.time() - t1}
-        log("%s: mean %.2f pseudo-steps/step, median initial residual %.3e, %d capped, %d fallbacks" %
-            (mode, np.mean(its), np.median(r0s), sum(1 for r in rcs if r != 0), fallback))
+        log("%s: mean %.2f %s/step, median initial residual %.3e, %d capped, %d fallbacks" %
+            (mode, np.mean(its), unit, np.median(r0s), sum(1 for r in rcs if r != 0), fallback))
+    if mg is not None:
+        mg.close()
     plan.close()
     summary = {}
     for mode, r in res_by.items():
         summary[mode] = {"iters_mean": float(np.mean(r["iters"])),
+                         "ms_per_step": 1e3 * r["seconds"] / max(1, len(r["iters"])),
                          "capped": int(sum(1 for c in r["rc"] if c != 0)),
                          "initial_residual_median": float(np.median(r["initial_residual"])),
                          "fallbacks": r["fallback"], "iters": r["iters"],
@@ -150,7 +164,8 @@ def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
         "config": {"p": p, "lattice": N, "dt": dt, "dtau": dtau, "tol": tol,
                    "max_iters": max_iters, "train_steps": train_steps, "eval_steps": eval_steps,
                    "samples": nrows, "epochs": epochs, "lr": lr, "zeta": zeta, "nu": nu, "T": T,
-                   "guess_base": guess_base},
+                   "guess_base": guess_base, "solver": solver,
+                   "max_cycles": max_cycles if solver == "pmg" else None},
         "train_iters_mean": float(np.mean([t[0] for t in train_log])),
         "train_capped": int(sum(1 for t in train_log if t[2] != 0)),
         "loss_curve": losses,
