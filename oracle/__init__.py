@@ -20,6 +20,8 @@ Pin status (tests/test_oracle_*.py):
   pmg.* (P-multigrid dual stepping, pmg.py)      pinned (projection/interpolation
                                                  exactness, closed-form cycle factors,
                                                  FAS fixed point, reduction to dual_step)
+  diagnostics.diagnostics (diagnostics.py)       pinned (Taylor-Green closed forms, single
+                                                 modes per curl entry, irrotational field)
   mlp_*                                          pinned (finite differences, autograd)
 """
 import ctypes
