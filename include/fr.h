@@ -209,6 +209,18 @@ int fr_pmg_dual_step(fr_pmg *mg, double *U, const double *Un, const double *Unm1
 void fr_pmg_destroy(fr_pmg *mg);
 
 /*
+ * fr_diagnostics -- flow diagnostics of a double state U (Sec. 5 follows the
+ * Taylor-Green run through them):
+ *   out[0] = kinetic energy  (1/|Omega|) int |V|^2 / 2 dx
+ *   out[1] = enstrophy       (nu/|Omega|) int omega . omega dx,  omega = curl V
+ * with the Gauss quadrature of the solution points (exact for the nodal
+ * polynomials' squares) and omega formed from the auxiliary variables,
+ * omega = (s_y - r_z, q_z - s_x, r_x - q_y).  out is host memory (2 doubles);
+ * synchronises the stream.  Allocates a small scratch on first use.
+ */
+int fr_diagnostics(fr_plan *plan, const double *U, double *out, fr_stream_t s);
+
+/*
  * fr_guess_extrap -- initial guess for the next physical step by polynomial
  * extrapolation in time of the past states (double state arrays):
  *   order 1: G = 2 Un - Unm1;   order 2: G = 3 Un - 3 Unm1 + Unm2.

@@ -24,7 +24,7 @@ EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_des
             "fr_strerror", "fr_last_error", "fr_plan_operators", "fr_plan_kernel_stats",
             "fr_mlp_state_floats", "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm",
             "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess",
-            "fr_pmg_create", "fr_pmg_dual_step", "fr_pmg_destroy")
+            "fr_pmg_create", "fr_pmg_dual_step", "fr_pmg_destroy", "fr_diagnostics")
 
 
 class FrError(RuntimeError):
@@ -77,9 +77,10 @@ def lib():
         L.fr_pmg_create.argtypes = [_vp, I, ctypes.POINTER(I), ctypes.POINTER(I), D]
         L.fr_pmg_create.restype = _vp
         L.fr_pmg_dual_step.argtypes = [_vp, _vp, _vp, _vp, D, D, D, I, ctypes.POINTER(I), _dp, _vp]
+        L.fr_diagnostics.argtypes = [_vp, _vp, _dp, _vp]
         L.fr_pmg_destroy.argtypes = [_vp]
         L.fr_pmg_destroy.restype = None
-        for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step", "fr_pmg_dual_step",
+        for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step", "fr_pmg_dual_step", "fr_diagnostics",
                   "fr_dual_step", "fr_guess_extrap", "fr_plan_operators", "fr_plan_kernel_stats",
                   "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm", "fr_mlp_forward",
                   "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess"):
@@ -206,6 +207,15 @@ def fr_pmg_dual_step(mg, U, Un, Unm1, dt, dtau, tol, max_cycles, n, stream=None,
     if raise_on_error and rc not in (FR_OK, FR_ENOCONV):
         _check(rc)
     return rc, cyc.value, res.value
+
+
+def fr_diagnostics(plan, U, stream=None):
+    """(kinetic energy, enstrophy) of a double state U."""
+    import torch
+    out = np.zeros(2)
+    _check(lib().fr_diagnostics(plan, _dev(U, torch.float64, fr_state_len(plan), "U"),
+                                out.ctypes.data_as(_dp), _stream(stream)))
+    return float(out[0]), float(out[1])
 
 
 def fr_pmg_destroy(mg):

@@ -115,6 +115,7 @@ struct fr_plan {
     fr::Scratch dual;       // BDF constant part (double, velocity only)
     fr::Scratch norm;       // partial sums (double)
     fr::Scratch mlp;        // MLP gradient partials / moments
+    fr::Scratch diag;       // partial sums of the flow diagnostics
     double *norm_host = nullptr;  // pinned host word for the norm read-back
     // optional per-kernel event timing
     int profile = 0;

@@ -438,6 +438,7 @@ void fr_plan_destroy(fr_plan *pl)
     free_scratch(pl->dual);
     free_scratch(pl->norm);
     free_scratch(pl->mlp);
+    free_scratch(pl->diag);
     if (pl->norm_host) hipHostFree(pl->norm_host);
     if (pl->ops64) hipFree(pl->ops64);
     if (pl->ops32) hipFree(pl->ops32);
