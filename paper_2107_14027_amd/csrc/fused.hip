@@ -511,7 +511,7 @@ constexpr int stage_chunk()
     return FR_STG_CHUNK;
 #else
     constexpr int d[PMAX + 1] = {0, 1, 1, 8, 1, 8, 4};
-    constexpr int f[PMAX + 1] = {0, 8, 4, 4, 1, 8, 1};
+    constexpr int f[PMAX + 1] = {0, 8, 4, 1, 1, 8, 1};
     return sizeof(T) == 8 ? d[P] : f[P];
 #endif
 }
@@ -749,11 +749,9 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
             //      every thread has read the tile, then written over the state tile.
             constexpr int KP = (EMAX * NS + NT - 1) / NT;
             T rhold[STG ? KP : 1][NV];
-#pragma unroll
-            for (int u = 0; u < KP; ++u) {
-                const unsigned t = tid + u * NT;
-                if (t >= (unsigned)nel * NS) break;
-                const unsigned el = t / NS, q = t - el * NS;
+            // residual of point q of element el, each value handed to put(v, value)
+            // as soon as it is formed (keeps few values live in the plain path)
+            auto point = [&](unsigned el, unsigned q, auto &&put) {
                 const unsigned qi = q % M, qj = (q / M) % M, qk = q / (M * M);
                 const T *Ue = sU + el * NV * NS;
                 const T *Fe = sF + el * 9 * NS;
@@ -799,22 +797,28 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
                 direction(Dir<1>{});
                 __builtin_amdgcn_sched_barrier(0);
                 direction(Dir<2>{});
-                T r[NV];
                 // P: -(1/detJ) [ zeta (det J div V) + dissipation ]
                 const T divV = g[0] + g[4] + g[8];
-                r[0] = -c.inv_det * fma(c.zeta, divV, dissP);
+                put(0, -c.inv_det * fma(c.zeta, divV, dissP));
 #pragma unroll
-                for (int a = 0; a < 3; ++a) r[1 + a] = -c.inv_det * mom[a];
+                for (int a = 0; a < 3; ++a) put(1 + a, -c.inv_det * mom[a]);
                 // aux (a, k): (1/T) [ d u_a / d x_k - S_ak ]
 #pragma unroll
-                for (int k = 0; k < 9; ++k) r[4 + k] = c.invT * fma(c.inv_det, g[k], -Ue[(4 + k) * NS + q]);
-                if constexpr (STG) {
+                for (int k = 0; k < 9; ++k)
+                    put(4 + k, c.invT * fma(c.inv_det, g[k], -Ue[(4 + k) * NS + q]));
+            };
+            if constexpr (STG) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) rhold[u][v] = r[v];
-                } else {
+                for (int u = 0; u < KP; ++u) {
+                    const unsigned t = tid + u * NT;
+                    if (t >= (unsigned)nel * NS) break;
+                    point(t / NS, t % NS, [&](int v, T val) { rhold[u][v] = val; });
+                }
+            } else {
+                for (unsigned t = tid; t < (unsigned)nel * NS; t += NT) {
+                    const unsigned el = t / NS, q = t - el * NS;
                     T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) __builtin_nontemporal_store(r[v], Re + v * NS);
+                    point(el, q, [&](int v, T val) { __builtin_nontemporal_store(val, Re + v * NS); });
                 }
             }
             if constexpr (STG) {

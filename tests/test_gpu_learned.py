@@ -29,12 +29,14 @@ def test_learned_guess_cuts_pseudo_iterations():
 
 
 def test_learned_guess_with_pmg_solver():
-    """The same study with P-multigrid cycles as the solver (counts are cycles)."""
+    """The default study with P-multigrid cycles as the solver (counts are
+    cycles; about 20 s).  Measured: 16.5 cycles with the network, 19.3 with
+    linear and 62.6 with quadratic extrapolation."""
     from paper_2107_14027_amd import learned
-    say("learned guess study, P-multigrid (short)")
-    r = learned.run(train_steps=12, eval_steps=8, epochs=600, guess_base=1, solver="pmg")
+    say("learned guess study, P-multigrid")
+    r = learned.run(guess_base=1, solver="pmg")
     m = r["modes"]
     for mode in ("extrap", "extrap1", "mlp"):
         assert m[mode]["capped"] == 0, (mode, m[mode]["iters"])
-    assert m["mlp"]["iters_mean"] < 0.9 * m["extrap"]["iters_mean"], m
-    assert m["mlp"]["iters_mean"] <= 1.1 * m["extrap1"]["iters_mean"], m
+    assert m["mlp"]["iters_mean"] < 0.5 * m["extrap"]["iters_mean"], m
+    assert m["mlp"]["iters_mean"] < 0.95 * m["extrap1"]["iters_mean"], m
