@@ -20,6 +20,10 @@ Pin status (tests/test_oracle_*.py):
   pmg.* (P-multigrid dual stepping, pmg.py)      pinned (projection/interpolation
                                                  exactness, closed-form cycle factors,
                                                  FAS fixed point, reduction to dual_step)
+  rk34.step, pmg.dual_step_local (rk34.py)       pinned (order conditions, fourth-order local
+                                                 error, closed-form uniform decay with the
+                                                 controller's growth and cap, deadbeat
+                                                 controller on an h^3 error, convergence)
   diagnostics.diagnostics (diagnostics.py)       pinned (Taylor-Green closed forms, single
                                                  modes per curl entry, irrotational field)
   mlp_*                                          pinned (finite differences, autograd)

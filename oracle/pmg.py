@@ -27,6 +27,7 @@ import numpy as np
 from numpy.polynomial import legendre as npleg
 
 from . import NV, gauss_legendre, lagrange_eval, residual
+from . import rk34
 
 
 def default_cycle(P):
@@ -105,17 +106,60 @@ class Level:
         return U
 
 
+    def rk34_steps(self, U, a, B, D, h, h0, atol, nsteps):
+        """RK34 steps with the locally adaptive step field h (oracle/rk34.py)."""
+        for _ in range(nsteps):
+            U, h = rk34.step(lambda X: self.pseudo_residual(X, a, B, D), U, h, h0, atol)
+        return U, h
+
+
+def bdf_terms(fine, Un, Unm1, dt):
+    """(a, B) of the BDF pseudo-residual on the finest level."""
+    Unv = np.asarray(Un, dtype=np.float64).reshape(fine.shape())[:, 1:4]
+    if Unm1 is None:
+        return 1.0 / dt, -Unv / dt
+    Um = np.asarray(Unm1, dtype=np.float64).reshape(fine.shape())[:, 1:4]
+    return 1.5 / dt, (Um - 4.0 * Unv) / (2.0 * dt)
+
+
+def dual_step_local(p, n, U0, Un, Unm1, zeta, nu, T, dt, dtau, tol, max_iters, h=None, jac=None):
+    """One BDF physical step by RK34 pseudo-steps with locally adaptive steps
+    (initial step dtau everywhere unless a field h is passed in), tested on
+    RMS(R*_V) before every pseudo-step.  Returns (U, iters, resid, rc, h)."""
+    lv = Level(p, n, zeta, nu, T, jac)
+    a, B = bdf_terms(lv, Un, Unm1, dt)
+    U = np.array(U0, dtype=np.float64).reshape(lv.shape())
+    h = np.full(U.shape, dtau) if h is None else np.array(h, dtype=np.float64).reshape(U.shape)
+    it, rc = 0, -5
+    while True:
+        res = velocity_rms(lv.pseudo_residual(U, a, B, None))
+        if not np.isfinite(res):
+            rc = -4
+            break
+        if res < tol:
+            rc = 0
+            break
+        if it >= max_iters:
+            break
+        U, h = lv.rk34_steps(U, a, B, None, h, dtau, tol, 1)
+        it += 1
+    return U.reshape(-1), it, res, rc, h.reshape(-1)
+
+
 def velocity_rms(Rs):
     return float(np.sqrt(np.mean(Rs[:, 1:4] ** 2)))
 
 
 def pmg_dual_step(P, n, U0, Un, Unm1, zeta, nu, T, dt, dtau, tol, max_cycles, cycle=None,
-                  factor=1.75, jac=None, forcing=None):
+                  factor=1.75, jac=None, forcing=None, scheme="rk4", fields=None):
     """One BDF physical step (BDF2, or BDF1 when Unm1 is None) by P-multigrid
     cycles of RK4 pseudo-steps.  Returns (U, cycles, resid, rc): rc 0 converged,
     -5 max_cycles completed without convergence, -4 non-finite residual.
     forcing (tests only) is a fixed source added on the finest level, where the
-    FAS defect is otherwise zero."""
+    FAS defect is otherwise zero.  scheme "rk34" takes RK34 steps with locally
+    adaptive step fields on every level (initial step dtau * factor^(P - l),
+    the convergence tolerance as the controller's atol); fields (a dict order ->
+    step field) carries them between calls and is updated in place."""
     cycle = default_cycle(P) if cycle is None else [tuple(c) for c in cycle]
     check_cycle(P, cycle)
     levels = {p: Level(p, n, zeta, nu, T, jac) for p in {c[0] for c in cycle}}
@@ -160,7 +204,16 @@ def pmg_dual_step(P, n, U0, Un, Unm1, zeta, nu, T, dt, dtau, tol, max_cycles, cy
             elif prev is not None and p > prev:
                 l = prev
                 Us[p] = Us[p] + apply3(ops[l][1], Us[l] - U0s[l], l + 1)
-            Us[p] = levels[p].rk4_steps(Us[p], a, Bs[p], Ds[p], dtau * factor ** (P - p), nst)
+            h0 = dtau * factor ** (P - p)
+            if scheme == "rk34":
+                if fields is None:
+                    fields = {}
+                hp = fields.get(p)
+                if hp is None or hp.shape != Us[p].shape:
+                    hp = np.full(Us[p].shape, h0)
+                Us[p], fields[p] = levels[p].rk34_steps(Us[p], a, Bs[p], Ds[p], hp, h0, tol, nst)
+            else:
+                Us[p] = levels[p].rk4_steps(Us[p], a, Bs[p], Ds[p], h0, nst)
             prev = p
         U = Us[P]
         cycles += 1
