@@ -66,13 +66,21 @@ typedef enum fr_option {
                              plain launches.  Results are identical either way; the graphs
                              are captured on a stream the plan owns and re-captured when a
                              pointer or scalar baked into them changes.                     */
-    FR_OPT_FUSE_STAGE = 7 /* 1 (default): with FR_FUSED, fr_rk_step and fr_dual_step apply each
+    FR_OPT_FUSE_STAGE = 7,/* 1 (default): with FR_FUSED, fr_rk_step and fr_dual_step apply each
                              RK4 stage update (and the BDF source and the pseudo-residual
                              norm) in the fused kernel's epilogue, so the residual never goes
                              to memory (not available at p = 6 with a non-diagonal Jacobian,
                              which keeps the separate kernel); 0: residual kernel + separate
                              stage kernel.  The states are bitwise identical either way; the
                              norm's summation order (per workgroup) differs.                 */
+    FR_OPT_PSEUDO = 8     /* pseudo-time scheme of fr_dual_step and of every fr_pmg level:
+                             0 (default) classical RK4 with the fixed step dtau; 1 the RK34
+                             embedded pair (Sec. 5; coefficients of Kennedy, Carpenter and
+                             Lewis's RK3(2)4[2R+]C) with one pseudo-step per state value,
+                             scaled after each step by clamp(0.8 (|e|/tol)^(-1/3), 0.98, 1.01)
+                             (e the embedded error estimate, tol the call's tolerance) and
+                             kept within [dtau/3, 3 dtau].  The step field persists in the
+                             plan between calls with the same dtau.                           */
 } fr_option;
 
 /* Kernel identifiers for fr_plan_kernel_stats. */

@@ -60,7 +60,7 @@ bool stage_in_epilogue(const fr_plan *pl)
 uint64_t config_word(const fr_plan *pl)
 {
     return (uint64_t)pl->precision | (uint64_t)pl->variant << 8 | (uint64_t)pl->fuse_stage << 16 |
-           (uint64_t)(uint32_t)pl->block << 32;
+           (uint64_t)pl->pseudo << 24 | (uint64_t)(uint32_t)pl->block << 32;
 }
 
 uint64_t bits(double x)
@@ -76,7 +76,7 @@ uint64_t bits(double x)
 // all scratch must already be allocated (the callers run one step without a
 // graph first).
 template <class F>
-int graph_run(fr_plan *pl, GraphCache &gc, const uint64_t (&key)[16], hipStream_t s, F &&enqueue)
+int graph_run(fr_plan *pl, GraphCache &gc, const uint64_t (&key)[20], hipStream_t s, F &&enqueue)
 {
     if (!gc.exec || std::memcmp(gc.key, key, sizeof key) != 0) {
         for (auto &g : pl->graphs)
@@ -152,10 +152,29 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
     // alternate between the two stage buffers, and the double copy of the stage
     // state that the BDF term needs (FP32) is updated in place.  A fixed source
     // D runs on the separate stage kernel.
-    const bool epi = stage_in_epilogue(pl) && !D;
+    // RK34 with locally adaptive steps: the step field persists in the plan
+    // while the initial step is unchanged
+    const bool rk34 = pl->pseudo == 1;
+    double *h34 = nullptr, *err34 = nullptr;
+    if (rk34) {
+        const void *before = pl->rk34.ptr;
+        if (int r = ensure_scratch(pl->rk34, 2 * (size_t)n * sizeof(double))) return r;
+        h34 = (double *)pl->rk34.ptr;
+        err34 = h34 + n;
+        if (pl->rk34.ptr != before || pl->rk34_h0 != dtau) {
+            if (int r = launch_fill(h34, dtau, n, s)) return r;
+            pl->rk34_h0 = dtau;
+        }
+    }
+    const bool epi = stage_in_epilogue(pl) && !D && !rk34;
     void *const bufs[2] = {b.stT, b.k};
     const int o = f64 ? 0 : 1;
     auto stage0 = [&](hipStream_t st) -> int {
+        if (rk34) {
+            if (int r = residual(pl, f64 ? (const void *)U : b.stT, b.k, st)) return r;
+            return launch_stage34(pl, 0, U, b.acc, err34, h34, st64, b.stT, b.k, B, D, a, tol, dtau,
+                                  partial, st);
+        }
         if (epi) {
             const StageSpec sp{U, b.acc, nullptr, f64 ? nullptr : st64, bufs[o], B, partial,
                                a, w[0], c[1], 1, 0};
@@ -166,6 +185,16 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
                             partial, st, D);
     };
     auto stages123 = [&](hipStream_t st) -> int {
+        if (rk34) {
+            for (int k = 1; k < 4; ++k) {
+                if (int r = residual(pl, b.stT, b.k, st)) return r;
+                if (int r = launch_stage34(pl, k, U, b.acc, err34, h34, st64,
+                                           (k == 3 && f64) ? nullptr : b.stT, b.k, B, D, a, tol,
+                                           dtau, nullptr, st))
+                    return r;
+            }
+            return FR_OK;
+        }
         if (epi) {
             for (int k = 1; k < 4; ++k) {
                 const bool last = k == 3;
@@ -229,12 +258,12 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
             return check ? readback(st) : FR_OK;
         };
         if (graphs) {
-            const uint64_t key[16] = {1, (uint64_t)U, (uint64_t)B, (uint64_t)D, bits(a), bits(dtau),
+            const uint64_t key[20] = {1, (uint64_t)U, (uint64_t)B, (uint64_t)D, bits(a), bits(dtau),
                                       (uint64_t)check | (uint64_t)next0 << 1, (uint64_t)pl->rk.ptr,
                                       (uint64_t)pl->dual.ptr, (uint64_t)pl->norm.ptr,
                                       (uint64_t)pl->traces.ptr, (uint64_t)pl->unfused.ptr,
                                       config_word(pl), (uint64_t)pl->norm_host,
-                                      (uint64_t)nparts};
+                                      (uint64_t)nparts, (uint64_t)pl->rk34.ptr, bits(tol)};
             rc = graph_run(pl, pl->graphs[check ? 0 : 1], key, s, body);
         } else {
             rc = body(s);
@@ -313,7 +342,7 @@ int fr_rk_step(fr_plan *pl, double *U, double dt, int nsteps, fr_stream_t sv)
     const bool graphs = pl->use_graphs && !pl->profile;
     for (int it = 0; it < nsteps && !rc; ++it) {
         if (graphs && it > 0) {
-            const uint64_t key[16] = {2, (uint64_t)U, bits(dt), (uint64_t)pl->rk.ptr,
+            const uint64_t key[20] = {2, (uint64_t)U, bits(dt), (uint64_t)pl->rk.ptr,
                                       (uint64_t)pl->traces.ptr, (uint64_t)pl->unfused.ptr,
                                       config_word(pl)};
             rc = graph_run(pl, pl->graphs[2], key, s, step);

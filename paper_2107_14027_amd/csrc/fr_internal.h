@@ -45,7 +45,7 @@ struct Scratch {
 struct GraphCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint64_t key[16] = {};
+    uint64_t key[20] = {};
 };
 
 // One classical RK4 stage of dU/dtau = k* applied to a residual k as it is
@@ -95,6 +95,12 @@ struct fr_plan {
     int use_graphs = 0;
     // fused path: apply the RK stage updates in the fused kernel's epilogue
     int fuse_stage = 1;
+    // pseudo-time scheme of the dual step: 0 RK4 with a fixed step, 1 RK34 with
+    // locally adaptive steps (field and error estimate in rk34, initial step
+    // rk34_h0 of the field held there)
+    int pseudo = 0;
+    double rk34_h0 = 0.0;
+    fr::Scratch rk34;
     hipStream_t cap_stream = nullptr;
     fr::GraphCache graphs[3];
     // persistent grid sizes of the fused path on this plan's device, per
@@ -169,6 +175,10 @@ int stage_blocks(int64_t n);
 int launch_stage(fr_plan *pl, bool bdf, bool norm, double *U, double *acc, double *st64,
                  void *stT, const void *k, const double *B, double a, double b, double cnext,
                  int first, int last, double *partial, hipStream_t s, const double *D = nullptr);
+int launch_stage34(fr_plan *pl, int stage, double *U, double *acc, double *err, double *h,
+                   double *st64, void *stT, const void *k, const double *B, const double *D,
+                   double a, double atol, double h0, double *partial, hipStream_t s);
+int launch_fill(double *x, double v, int64_t n, hipStream_t s);
 int launch_to_precision(fr_plan *pl, const double *U, void *out, int64_t n, hipStream_t s);
 int launch_bdf_const(fr_plan *pl, const double *Un, const double *Unm1, double dt, double *B,
                      hipStream_t s);

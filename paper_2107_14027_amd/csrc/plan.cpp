@@ -390,6 +390,10 @@ int fr_plan_set_int(fr_plan *pl, int key, int value)
             if (value != 0 && value != 1) return set_error(FR_EINVAL, "fuse stage %d", value);
             pl->fuse_stage = value;
             return FR_OK;
+        case FR_OPT_PSEUDO:
+            if (value != 0 && value != 1) return set_error(FR_EINVAL, "pseudo-time scheme %d", value);
+            pl->pseudo = value;
+            return FR_OK;
         default:
             return set_error(FR_EINVAL, "unknown option %d", key);
     }
@@ -406,6 +410,7 @@ int fr_plan_get_int(const fr_plan *pl, int key, int *value)
         case FR_OPT_GUESS_BASE: *value = pl->guess_base; return FR_OK;
         case FR_OPT_GRAPH: *value = pl->use_graphs; return FR_OK;
         case FR_OPT_FUSE_STAGE: *value = pl->fuse_stage; return FR_OK;
+        case FR_OPT_PSEUDO: *value = pl->pseudo; return FR_OK;
         default: return set_error(FR_EINVAL, "unknown option %d", key);
     }
 }
@@ -439,6 +444,7 @@ void fr_plan_destroy(fr_plan *pl)
     free_scratch(pl->norm);
     free_scratch(pl->mlp);
     free_scratch(pl->diag);
+    free_scratch(pl->rk34);
     if (pl->norm_host) hipHostFree(pl->norm_host);
     if (pl->ops64) hipFree(pl->ops64);
     if (pl->ops32) hipFree(pl->ops32);

@@ -82,6 +82,67 @@ __global__ void __launch_bounds__(TB) k_stage(double *__restrict__ U, double *__
     }
 }
 
+// One stage of the RK3(2)4[2R+]C pair (Kennedy, Carpenter and Lewis: four
+// stages, third order, embedded second order, two registers) with one
+// pseudo-step h per value, on dU/dtau = k* (k* as in k_stage).  With
+// hk = h k*:
+//   stages 0..2:  next = U + acc + anext hk;  acc += b hk;  err += bd hk
+//                 (acc, err start from zero on stage 0)
+//   stage 3:      U = U + acc + b hk;  e = err + bd hk;
+//                 h = clamp(h clamp(0.8 (|e|/atol)^(-1/3), 0.98, 1.01), h0/3, 3 h0)
+// bd = b - bhat; e is the embedded error estimate.
+template <typename T>
+__global__ void __launch_bounds__(TB)
+    k_stage34(double *__restrict__ U, double *__restrict__ acc, double *__restrict__ err,
+              double *__restrict__ h, double *st64, T *stT, const T *__restrict__ k,
+              const double *__restrict__ B, const double *__restrict__ D, double a, int stage,
+              double anext, double bs, double bds, double atol, double h0, int64_t n, int ns,
+              double *__restrict__ partial)
+{
+    __shared__ double sh[TB / 64];
+    double ss = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+        double kv = (double)k[i];
+        const int64_t r = i / ns;
+        const int v = (int)(r % NV);
+        const bool vel = v >= 1 && v <= 3;
+        if (B && vel) {
+            const double sv = stage == 0 ? U[i] : st64[i];
+            kv -= fma(a, sv, B[((r / NV) * 3 + (v - 1)) * ns + (i - r * ns)]);
+        }
+        if (D) kv += D[i];
+        if (partial && vel) ss = fma(kv, kv, ss);
+        const double hv = h[i];
+        const double hk = hv * kv;
+        if (stage == 3) {
+            const double un = U[i] + (acc[i] + bs * hk);
+            const double e = err[i] + bds * hk;
+            const double q = fmax(fabs(e) / atol, 1e-300);
+            const double fac = fmin(fmax(0.8 * pow(q, -1.0 / 3.0), 0.98), 1.01);
+            h[i] = fmin(fmax(hv * fac, h0 / 3.0), h0 * 3.0);
+            U[i] = un;
+            if (stT) stT[i] = (T)un;
+        } else {
+            const double ac = stage == 0 ? 0.0 : acc[i];
+            const double sn = U[i] + (ac + anext * hk);
+            acc[i] = ac + bs * hk;
+            err[i] = (stage == 0 ? 0.0 : err[i]) + bds * hk;
+            if (st64 && (void *)st64 != (void *)stT) st64[i] = sn;
+            stT[i] = (T)sn;
+        }
+    }
+    if (partial) {
+        const double s = block_sum(ss, sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+    }
+}
+
+__global__ void __launch_bounds__(TB) k_fill(double *__restrict__ x, double v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB)
+        x[i] = v;
+}
+
 __global__ void __launch_bounds__(TB) k_final_sum(const double *__restrict__ partial, int nb,
                                                   double *__restrict__ out)
 {
@@ -166,6 +227,43 @@ int launch_stage(fr_plan *pl, bool bdf, bool norm, double *U, double *acc, doubl
                                       last, n, ns, partial, s);
     return stage_dispatch<float>(bdf, norm, U, acc, st64, stT, k, B, D, a, b, cnext, first, last,
                                  n, ns, partial, s);
+}
+
+int launch_stage34(fr_plan *pl, int stage, double *U, double *acc, double *err, double *h,
+                   double *st64, void *stT, const void *k, const double *B, const double *D,
+                   double a, double atol, double h0, double *partial, hipStream_t s)
+{
+    // RK3(2)4[2R+]C: sub-diagonal a_{i+1,i}, weights b, b - bhat
+    static const double anext[3] = {11847461282814.0 / 36547543011857.0,
+                                    3943225443063.0 / 7078155732230.0,
+                                    -346793006927.0 / 4029903576067.0};
+    static const double b[4] = {1017324711453.0 / 9774461848756.0, 8237718856693.0 / 13685301971492.0,
+                                57731312506979.0 / 19404895981398.0,
+                                -101169746363290.0 / 37734290219643.0};
+    static const double bhat[4] = {15763415370699.0 / 46270243929542.0,
+                                   514528521746.0 / 5659431552419.0,
+                                   27030193851939.0 / 9429696342944.0,
+                                   -69544964788955.0 / 30262026368149.0};
+    const int64_t n = (int64_t)fr_state_len(pl);
+    const int ns = pl->m * pl->m * pl->m;
+    const unsigned g = grid_for(n);
+    const double an = stage < 3 ? anext[stage] : 0.0;
+    ProfScope ps(pl, FR_K_STAGE, s);
+    if (pl->precision == FR_F64)
+        hipLaunchKernelGGL(k_stage34<double>, dim3(g), dim3(TB), 0, s, U, acc, err, h, st64,
+                           (double *)stT, (const double *)k, B, D, a, stage, an, b[stage],
+                           b[stage] - bhat[stage], atol, h0, n, ns, partial);
+    else
+        hipLaunchKernelGGL(k_stage34<float>, dim3(g), dim3(TB), 0, s, U, acc, err, h, st64,
+                           (float *)stT, (const float *)k, B, D, a, stage, an, b[stage],
+                           b[stage] - bhat[stage], atol, h0, n, ns, partial);
+    return check_hip(hipGetLastError(), "k_stage34 launch");
+}
+
+int launch_fill(double *x, double v, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(TB), 0, s, x, v, n);
+    return check_hip(hipGetLastError(), "k_fill launch");
 }
 
 int launch_to_precision(fr_plan *pl, const double *U, void *out, int64_t n, hipStream_t s)
