@@ -19,6 +19,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -137,6 +138,43 @@ def cpu_baseline(orders, lattices, host_states, budget_s):
     return tot_dof / tot_t / 1e9, "; ".join(sample)
 
 
+def time_steps(p=3, N=64, steps=5):
+    """Wall time of one RK4 step and one dual pseudo-step (BDF2, norm every 10th)
+    on a p=3, 64^3 FP64 Taylor-Green state, with the stage update in the fused
+    kernel's epilogue and with the separate stage kernel."""
+    import torch
+    from paper_2107_14027_amd import binding as B
+    from paper_2107_14027_amd import inputs
+    nu, T = inputs.nu_T_from_length(1600.0, 1.0 / (2.0 * math.pi))
+    n = (N, N, N)
+    U0 = torch.tensor(inputs.tgv(p, n), device="cuda")
+    out = {"workload": "Taylor-Green, p=%d on %d^3 hexes, FP64; ms per RK4 step (dt 1e-4) and per "
+                       "BDF2 pseudo-step (dtau 5e-3)" % (p, N)}
+    for fuse in (1, 0):
+        plan = B.Plan(p, n, 4.0, nu, T)
+        plan.set(B.FR_OPT_FUSE_STAGE, fuse)
+        V = U0.clone()
+        B.fr_rk_step(plan.handle, V, 1e-4, 1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        B.fr_rk_step(plan.handle, V, 1e-4, steps)
+        torch.cuda.synchronize()
+        rk = 1e3 * (time.perf_counter() - t) / steps
+        W = U0.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, it, res = B.fr_dual_step(plan.handle, W, U0, U0, 5e-2, 5e-3, 1e-30, 2 * steps,
+                                     check_every=10, raise_on_error=False)
+        torch.cuda.synchronize()
+        du = 1e3 * (time.perf_counter() - t) / max(1, it)
+        key = "stage_epilogue" if fuse else "separate_stage_kernel"
+        out[key] = {"rk4_step_ms": round(rk, 3), "pseudo_step_ms": round(du, 3)}
+        plan.close()
+        del V, W
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +187,8 @@ def main():
     ap.add_argument("--no-hbm-ref", action="store_true", help="skip the copy/fill/read reference")
     ap.add_argument("--lattice", default=None,
                     help="NX,NY,NZ: one lattice for every order given (default: the sweep lattices)")
+    ap.add_argument("--no-timestep", action="store_true",
+                    help="skip the RK4 / dual pseudo-step timing (stage epilogue vs separate stage kernel)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-guess study (pseudo-iterations per physical step)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -287,6 +327,11 @@ def main():
                          "lattices and fields: " + sample}
         del host
 
+    timestep = None
+    if not args.no_timestep:
+        timestep = time_steps()
+        log("time steps: %s" % timestep)
+
     learned = None
     if not args.no_learned:
         from paper_2107_14027_amd import learned as L
@@ -360,6 +405,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "time_step": timestep,
         "learned_guess": learned,
         "sweep": sweep,
         "kernel_ms": {str(p): {"trace": round(kstats[p]["trace_ms"], 4),

@@ -33,9 +33,19 @@ def kernel_source_hash():
 
 
 def short(name):
-    m = re.search(r"(k_\w+)<(\d+), (\w+)(?:, [^>]*)?>", name)
+    m = re.search(r"(k_\w+)<(\d+), (\w+)((?:, \w+)*)>", name)
     if m:
-        return "%s<%s,%s>" % m.groups()
+        kern, p, t, extra = m.groups()
+        # the fused kernel's last template argument selects the stage epilogue
+        if kern == "k_fused" and extra.endswith("true") and extra.count(",") == 2:
+            kern = "k_fused_stage"
+        return "%s<%s,%s>" % (kern, p, t)
+    m = re.search(r"(k_\w+)<([^>]*)>", name)
+    if m:
+        return "%s<%s>" % (m.group(1), m.group(2).replace(" ", ""))
+    m = re.search(r"(k_\w+)\(", name)
+    if m:
+        return m.group(1)
     m = re.search(r"([A-Za-z_][\w:]*)[<(]", name)
     return (m.group(1) if m else name)[:56]
 
