@@ -232,8 +232,12 @@ int fr_diagnostics(fr_plan *plan, const double *U, double *out, fr_stream_t s);
  * fr_guess_extrap -- initial guess for the next physical step by polynomial
  * extrapolation in time of the past states (double state arrays):
  *   order 1: G = 2 Un - Unm1;   order 2: G = 3 Un - 3 Unm1 + Unm2.
+ * With FR_GUESS_KEEP_P or-ed into order, the pressure is not extrapolated but
+ * taken from Un (it has no physical time derivative; extrapolating the part of
+ * it a capped pseudo-iteration left unconverged makes that part grow).
  * Unm2 may be NULL for order 1.  G may alias none of the inputs.
  */
+#define FR_GUESS_KEEP_P 0x10
 int fr_guess_extrap(fr_plan *plan, const double *Un, const double *Unm1, const double *Unm2,
                     int order, double *G, fr_stream_t s);
 

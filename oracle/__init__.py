@@ -234,13 +234,17 @@ def dual_step(p, n, U0, Un, Unm1, zeta, nu, T, dt, dtau, tol, max_iters, order=2
     return U, it.value, res.value, rc
 
 
-def extrap(Un, Unm1, Unm2, order):
-    """Polynomial extrapolation of past states to the next physical step."""
+def extrap(Un, Unm1, Unm2, order, keep_p=False, ns=None):
+    """Polynomial extrapolation of past states to the next physical step; with
+    keep_p the pressure (variable 0 of each element's ns points) is taken from
+    Un instead (it has no physical time derivative in Sec. 2.2's system)."""
     Un, Unm1 = _f64(Un), _f64(Unm1)
     Unm2 = _f64(Unm2) if Unm2 is not None else Un
     G = np.zeros_like(Un)
     if lib().orc_extrap(Un.size, _p(Un), _p(Unm1), _p(Unm2), order, _p(G)):
         raise ValueError("bad order")
+    if keep_p:
+        G.reshape(-1, NV, ns)[:, 0] = Un.reshape(-1, NV, ns)[:, 0]
     return G
 
 

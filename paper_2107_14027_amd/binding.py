@@ -222,6 +222,9 @@ def fr_pmg_destroy(mg):
     lib().fr_pmg_destroy(mg)
 
 
+FR_GUESS_KEEP_P = 0x10   # or-ed into the order of fr_guess_extrap: pressure from Un
+
+
 def fr_guess_extrap(plan, Un, Unm1, Unm2, order, G, stream=None):
     import torch
     n = fr_state_len(plan)

@@ -386,6 +386,8 @@ int fr_guess_extrap(fr_plan *pl, const double *Un, const double *Unm1, const dou
                     int order, double *G, fr_stream_t s)
 {
     if (!pl) return set_error(FR_EINVAL, "fr_guess_extrap: NULL plan");
+    const bool keep_p = (order & FR_GUESS_KEEP_P) != 0;
+    order &= ~FR_GUESS_KEEP_P;
     if (order != 1 && order != 2) return set_error(FR_EINVAL, "fr_guess_extrap: order %d", order);
     if (int rc = check_array(Un, "Un")) return rc;
     if (int rc = check_array(Unm1, "Unm1")) return rc;
@@ -396,7 +398,8 @@ int fr_guess_extrap(fr_plan *pl, const double *Un, const double *Unm1, const dou
     if (overlap(G, bytes, Un, bytes) || overlap(G, bytes, Unm1, bytes) ||
         (order == 2 && overlap(G, bytes, Unm2, bytes)))
         return set_error(FR_EINVAL, "fr_guess_extrap: G overlaps an input");
-    return launch_extrap(Un, Unm1, Unm2, order, G, (int64_t)fr_state_len(pl), (hipStream_t)s);
+    return launch_extrap(Un, Unm1, Unm2, order, keep_p ? pl->m * pl->m * pl->m : 0, G,
+                         (int64_t)fr_state_len(pl), (hipStream_t)s);
 }
 
 }  // extern "C"

@@ -184,6 +184,6 @@ int launch_bdf_const(fr_plan *pl, const double *Un, const double *Unm1, double d
                      hipStream_t s);
 int launch_final_sum(const double *partial, int nblocks, double *out, hipStream_t s);
 int launch_extrap(const double *Un, const double *Unm1, const double *Unm2, int order,
-                  double *G, int64_t n, hipStream_t s);
+                  int keep_ns, double *G, int64_t n, hipStream_t s);
 
 }  // namespace fr

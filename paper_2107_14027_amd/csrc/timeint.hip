@@ -176,13 +176,16 @@ __global__ void __launch_bounds__(TB) k_bdf_const(const double *__restrict__ Un,
     }
 }
 
+// keep_ns > 0: the pressure (variable 0 of every element, keep_ns points)
+// is copied from Un instead of extrapolated
 __global__ void __launch_bounds__(TB) k_extrap(const double *__restrict__ Un,
                                                const double *__restrict__ Unm1,
                                                const double *__restrict__ Unm2, int order,
-                                               double *__restrict__ G, int64_t n)
+                                               int keep_ns, double *__restrict__ G, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
-        if (order == 1) G[i] = 2.0 * Un[i] - Unm1[i];
+        if (keep_ns && (i / keep_ns) % NV == 0) G[i] = Un[i];
+        else if (order == 1) G[i] = 2.0 * Un[i] - Unm1[i];
         else G[i] = 3.0 * (Un[i] - Unm1[i]) + Unm2[i];
     }
 }
@@ -291,10 +294,11 @@ int launch_final_sum(const double *partial, int nblocks, double *out, hipStream_
     return check_hip(hipGetLastError(), "k_final_sum launch");
 }
 
-int launch_extrap(const double *Un, const double *Unm1, const double *Unm2, int order, double *G,
-                  int64_t n, hipStream_t s)
+int launch_extrap(const double *Un, const double *Unm1, const double *Unm2, int order, int keep_ns,
+                  double *G, int64_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_extrap, dim3(grid_for(n)), dim3(TB), 0, s, Un, Unm1, Unm2, order, G, n);
+    hipLaunchKernelGGL(k_extrap, dim3(grid_for(n)), dim3(TB), 0, s, Un, Unm1, Unm2, order, keep_ns,
+                       G, n);
     return check_hip(hipGetLastError(), "k_extrap launch");
 }
 

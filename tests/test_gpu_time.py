@@ -192,4 +192,11 @@ def test_extrapolation():
     torch.cuda.synchronize()
     assert np.allclose(G.cpu().numpy().reshape(a.shape), oracle.extrap(f(2.0), f(1.0), None, 1),
                        rtol=0, atol=1e-13)
+    for order in (1, 2):
+        B.fr_guess_extrap(plan.handle, to_dev(f(2.0)), to_dev(f(1.0)), to_dev(f(0.0)),
+                          order | B.FR_GUESS_KEEP_P, G)
+        torch.cuda.synchronize()
+        ref = oracle.extrap(f(2.0), f(1.0), f(0.0), order, keep_p=True, ns=27)
+        assert np.allclose(G.cpu().numpy().reshape(a.shape), ref.reshape(a.shape), rtol=0, atol=1e-13)
+        assert np.array_equal(G.cpu().numpy().reshape(a.shape)[:, 0], f(2.0)[:, 0])
     plan.close()

@@ -96,3 +96,18 @@ def test_extrapolation_exact_on_polynomials_in_time():
     assert np.allclose(oracle.extrap(f(2.0), f(1.0), f(0.0), 2), f(3.0), atol=1e-13)
     assert np.allclose(oracle.extrap(g(2.0), g(1.0), None, 1), g(3.0), atol=1e-13)
     assert not np.allclose(oracle.extrap(f(2.0), f(1.0), None, 1), f(3.0), atol=1e-3)
+
+
+def test_extrapolation_keeping_the_pressure():
+    """keep_p: the pressure of every point is U^n's exactly; every other
+    variable is the plain extrapolation (exact on quadratics in time)."""
+    rng = np.random.default_rng(8)
+    ne, ns = 3, 8
+    a, b, c = (rng.standard_normal((ne, 13, ns)) for _ in range(3))
+    f = lambda t: a + b * t + c * t * t
+    G = oracle.extrap(f(2.0), f(1.0), f(0.0), 2, keep_p=True, ns=ns).reshape(ne, 13, ns)
+    assert np.array_equal(G[:, 0], f(2.0)[:, 0])
+    assert np.allclose(G[:, 1:], f(3.0)[:, 1:], rtol=0, atol=1e-12)
+    G1 = oracle.extrap(f(2.0), f(1.0), None, 1, keep_p=True, ns=ns).reshape(ne, 13, ns)
+    assert np.array_equal(G1[:, 0], f(2.0)[:, 0])
+    assert np.allclose(G1[:, 1:], (2 * f(2.0) - f(1.0))[:, 1:], rtol=0, atol=1e-12)
