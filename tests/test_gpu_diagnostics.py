@@ -58,3 +58,19 @@ def test_short_run_energy_balance():
     assert np.all(np.diff(ke) < 0)
     inner = slice(2, -1)
     assert np.max(np.abs(rate[inner] - ens[inner]) / ens[inner]) < 0.02, (rate, ens)
+
+
+def test_run_with_the_pressure_kept_converges_every_step():
+    """The paper's constants on 8^3 hexes, p = 3, to t = 1 with the pressure of
+    the last step as its guess: no step reaches the cycle cap, the kinetic
+    energy decays, and FP32 tracks FP64 to round-off."""
+    from paper_2107_14027_amd import tgv
+    say("tgv to t=1, pressure kept")
+    out = {}
+    for prec in (B.FR_F64, B.FR_F32):
+        r = tgv.run(p=3, N=8, dt=1e-2, t_end=1.0, tol=2e-4, every=10, max_cycles=60, precision=prec)
+        assert r["capped_steps"] == 0, r["series"]["cycles"]
+        ke = np.array(r["series"]["ke"])
+        assert np.all(np.diff(ke) < 0)
+        out[prec] = np.array(r["series"]["enstrophy"])
+    assert np.max(np.abs(out[B.FR_F32] - out[B.FR_F64]) / out[B.FR_F64]) < 1e-5
