@@ -195,8 +195,8 @@ def main():
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the multi-GPU sharding is a design note, not built)" % args.gpus, file=sys.stderr)
+        print("bench.py: measures one GPU; --gpus %d is not supported "
+              "(sharding across GPUs is not implemented)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     orders = [int(x) for x in args.orders.split(",")]
 
