@@ -204,7 +204,7 @@ fr_pmg *fr_pmg_create(fr_plan *fine, int nlevels, const int *orders, const int *
  * by P-multigrid cycles.  Convergence (RMS over all points of the velocity
  * part of the finest level's R* below tol) is tested before the first cycle
  * and after each cycle.  The coarse plans take the fine plan's precision,
- * variant and stage-fusion settings.  Arguments as fr_dual_step; cycles: out,
+ * variant, stage-fusion, pseudo-time-scheme and graph settings.  Arguments as fr_dual_step; cycles: out,
  * completed cycles.  Synchronises the stream once per cycle.  Returns FR_OK,
  * FR_ENOCONV (max_cycles completed, U holds the last iterate) or
  * FR_ENONFINITE.

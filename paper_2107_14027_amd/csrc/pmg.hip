@@ -314,6 +314,7 @@ int fr_pmg_dual_step(fr_pmg *mg, double *U, const double *Un, const double *Unm1
             if (int rc = fr_plan_set_int(c, FR_OPT_VARIANT, fine->variant)) return rc;
             if (int rc = fr_plan_set_int(c, FR_OPT_FUSE_STAGE, fine->fuse_stage)) return rc;
             if (int rc = fr_plan_set_int(c, FR_OPT_PSEUDO, fine->pseudo)) return rc;
+            if (int rc = fr_plan_set_int(c, FR_OPT_GRAPH, fine->use_graphs)) return rc;
         }
     const double a = Unm1 ? 1.5 / dt : 1.0 / dt;
     if (int rc = launch_bdf_const(fine, Un, Unm1, dt, mg->B[P], s)) return rc;

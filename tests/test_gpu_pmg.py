@@ -40,7 +40,7 @@ def gpu_pmg(P, n, G, Un, Unm1, dt, dtau, tol, maxc, prec=B.FR_F64, var=B.FR_FUSE
     return out, rc, cyc, res
 
 
-@pytest.mark.parametrize("P,n,bdf2", [(2, (3, 2, 2), True), (3, (2, 3, 2), True),
+@pytest.mark.parametrize("P,n,bdf2", [(1, (3, 2, 2), True), (2, (3, 2, 2), True), (3, (2, 3, 2), True),
                                       (3, (2, 2, 3), False), (4, (2, 2, 2), True)])
 def test_fixed_cycles_match_oracle(P, n, bdf2):
     G, Un, Unm1 = case(P, n)
@@ -127,3 +127,27 @@ def test_errors():
     assert rc == B.FR_ENONFINITE
     mg.close()
     plan.close()
+
+
+def test_graph_replay_bitwise():
+    """P-multigrid with every level's pseudo-steps replayed as captured graphs
+    gives the bits of plain launches, over two physical steps."""
+    import torch
+    P, n = 3, (2, 2, 3)
+    G, Un, Unm1 = case(P, n, seed=7)
+    say("pmg graphs")
+    outs = []
+    for graph in (1, 0):
+        plan = B.Plan(P, n, ZETA, NU, T_CFG)
+        plan.set(B.FR_OPT_GRAPH, graph)
+        mg = B.Pmg(plan)
+        U = dev(G)
+        res = []
+        for _ in range(2):
+            res.append(mg.dual_step(U, dev(Un), dev(Unm1), 1e-2, 1e-3, 1e-30, 2, raise_on_error=False))
+        torch.cuda.synchronize()
+        outs.append((U.cpu().numpy(), res))
+        mg.close()
+        plan.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert outs[0][1] == outs[1][1]
