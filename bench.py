@@ -175,6 +175,58 @@ def time_steps(p=3, N=64, steps=5):
     return out
 
 
+def time_mlp(p=3, N=64, rows=1 << 16, reps=10):
+    """The learned guess's kernels on their own: one network guess over every
+    point of a p=3, 64^3 FP64 state (three states read, one written: 416 B per
+    point; 2 x (12*64 + 64*64 + 64*4) flop per point) and one training step
+    (forward, backward, Adam) on a batch of `rows` samples, by HIP events on
+    the launch stream."""
+    import torch
+    from paper_2107_14027_amd import binding as B
+    n = (N, N, N)
+    plan = B.Plan(p, n, ZETA, NU, TRELAX)
+    ns = plan.state_len
+    npts = ns // NV
+    st = B.mlp_new_state(5)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    U = [torch.randn(ns, dtype=torch.float64, device="cuda", generator=g) for _ in range(3)]
+    G = torch.empty_like(U[0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        B.fr_mlp_guess(plan.handle, st, U[0], U[1], U[2], G)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        B.fr_mlp_guess(plan.handle, st, U[0], U[1], U[2], G)
+    e1.record()
+    torch.cuda.synchronize()
+    gms = e0.elapsed_time(e1) / reps
+    flop_pt = 2 * (12 * 64 + 64 * 64 + 64 * 4)
+    bytes_pt = 4 * NV * 8
+    X = torch.randn(rows, 12, dtype=torch.float32, device="cuda", generator=g)
+    Y = torch.randn(rows, 4, dtype=torch.float32, device="cuda", generator=g)
+    B.fr_mlp_fit_norm(plan.handle, st, X, Y)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for i in range(2):
+        B.fr_mlp_train_step(plan.handle, st, X, Y, 1e-3, i + 1, loss)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(2 * reps):
+        B.fr_mlp_train_step(plan.handle, st, X, Y, 1e-3, i + 3, loss)
+    e1.record()
+    torch.cuda.synchronize()
+    tms = e0.elapsed_time(e1) / (2 * reps)
+    plan.close()
+    del U, G
+    torch.cuda.empty_cache()
+    return {"workload": "network guess on p=%d, %d^3 (%d points, FP64 states); training step on %d rows"
+                        % (p, N, npts, rows),
+            "guess_ms": round(gms, 4), "guess_GB_per_s": round(bytes_pt * npts / gms / 1e6, 1),
+            "guess_frac_hbm": round(bytes_pt * npts / gms / 1e6 / HBM_PEAK_GBS, 4),
+            "guess_TFLOP_per_s": round(flop_pt * npts / gms / 1e9, 2),
+            "train_step_ms": round(tms, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +387,8 @@ def main():
     learned = None
     if not args.no_learned:
         from paper_2107_14027_amd import learned as L
+        kern = time_mlp()
+        log("mlp kernels: %s" % kern)
         t0 = time.perf_counter()
         r = L.run(guess_base=1)
         t1 = time.perf_counter()
@@ -377,7 +431,8 @@ def main():
                                      ("linear_extrap", "extrap1"))},
                 "learned_vs_quadratic": round(rp["mlp_vs_quadratic_iters"], 4),
                 "learned_vs_linear": round(rp["mlp_vs_linear_iters"], 4),
-                "seconds": round(time.perf_counter() - t1, 1)}}
+                "seconds": round(time.perf_counter() - t1, 1)},
+            "kernels": kern}
         log("learned guess: %s" % learned)
 
     out = {

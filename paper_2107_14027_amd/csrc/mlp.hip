@@ -37,11 +37,11 @@ constexpr int OADAM_M = NPAR + 28, OADAM_V = OADAM_M + NPAR, NSTATE = OADAM_V + 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// FP32 -> BF16, round to nearest even (the hardware conversion, two values
+// per instruction on gfx950).
 __device__ __forceinline__ short bf16_rne(float x)
 {
-    unsigned u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+    return __builtin_bit_cast(short, (__bf16)x);
 }
 
 __device__ __forceinline__ v4s pack4(float a, float b, float c, float d)
@@ -60,6 +60,23 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Hyperbolic tangent from the exponential identity tanh|x| = (1 - t) / (1 + t),
+// t = e^{-2|x|} = 2^{-2 log2(e) |x|}, on the hardware exp2 and reciprocal (no
+// overflow: the exponent is never positive); below |x| = 1/16, where 1 - t
+// cancels, the odd Taylor series to x^7 (truncation below 4e-13 relative).
+// Relative error about 1e-6, far below the BF16 rounding the activations get
+// next; both branches are straight-line code, so lanes do not diverge.
+__device__ __forceinline__ float tanh_exp(float x)
+{
+    const float a = fabsf(x);
+    const float t = __builtin_amdgcn_exp2f(-2.88539008177792681f * a);
+    const float big = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
+    const float s = a * a;
+    const float small =
+        a + a * s * (-1.0f / 3.0f + s * (2.0f / 15.0f + s * (-17.0f / 315.0f)));
+    return copysignf(a < 0.0625f ? small : big, x);
 }
 
 __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
@@ -121,27 +138,26 @@ __device__ __forceinline__ v4f forward(const Weights &w, v4s xb, Acts &a)
     v4s hb[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        v4f z = {0.f, 0.f, 0.f, 0.f};
+        // the FP32 bias seeds the accumulator
+        v4f z = {w.b1[r][0], w.b1[r][1], w.b1[r][2], w.b1[r][3]};
         z = mfma(w.w1[r], xb, z);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) a.h1[r][t] = tanhf(z[t] + w.b1[r][t]);
+        for (int t = 0; t < 4; ++t) a.h1[r][t] = tanh_exp(z[t]);
         hb[r] = pack4(a.h1[r][0], a.h1[r][1], a.h1[r][2], a.h1[r][3]);
     }
     v4s h2b[4];
 #pragma unroll
     for (int r2 = 0; r2 < 4; ++r2) {
-        v4f z = {0.f, 0.f, 0.f, 0.f};
+        v4f z = {w.b2[r2][0], w.b2[r2][1], w.b2[r2][2], w.b2[r2][3]};
 #pragma unroll
         for (int r = 0; r < 4; ++r) z = mfma(w.w2[r2][r], hb[r], z);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) a.h2[r2][t] = tanhf(z[t] + w.b2[r2][t]);
+        for (int t = 0; t < 4; ++t) a.h2[r2][t] = tanh_exp(z[t]);
         h2b[r2] = pack4(a.h2[r2][0], a.h2[r2][1], a.h2[r2][2], a.h2[r2][3]);
     }
-    v4f y = {0.f, 0.f, 0.f, 0.f};
+    v4f y = {w.b3[0], w.b3[1], w.b3[2], w.b3[3]};
 #pragma unroll
     for (int r = 0; r < 4; ++r) y = mfma(w.w3[r], h2b[r], y);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) y[t] += w.b3[t];
     return y;
 }
 
@@ -541,28 +557,46 @@ __global__ void __launch_bounds__(64 * TW) k_mlp_grad(const float *__restrict__ 
     if (lane == 0) loss_part[wave] = lsum;
 }
 
-// Sum the per-wave partials in a fixed order and apply Adam to the master.
-__global__ void __launch_bounds__(256) k_mlp_adam(const float *__restrict__ part, int nwaves,
+// The per-wave gradient partials part[nwaves][NPAR] are summed in a fixed
+// order in two levels: chunks of RCH consecutive waves (one thread per
+// parameter and chunk, so the loads of many chunks are in flight at once),
+// then the chunks in order.
+constexpr int RCH = 32;
+
+__global__ void __launch_bounds__(256) k_mlp_chunks(const float *__restrict__ part, int nwaves,
+                                                    float *__restrict__ chunks)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NPAR) return;
+    const int c = blockIdx.y;
+    const int w0 = c * RCH, w1 = min(w0 + RCH, nwaves);
+    float s = 0.f;
+    for (int wv = w0; wv < w1; ++wv) s += part[(int64_t)wv * NPAR + k];
+    chunks[(int64_t)c * NPAR + k] = s;
+}
+
+// Sum the chunk partials in order and apply Adam to the master.
+__global__ void __launch_bounds__(256) k_mlp_adam(const float *__restrict__ chunks, int nchunk,
                                                   float *__restrict__ S, float lr, float b1,
                                                   float b2, float eps, int step)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= NPAR) return;
     float gsum = 0.f;
-    for (int wv = 0; wv < nwaves; ++wv) gsum += part[(int64_t)wv * NPAR + k];
+    for (int c = 0; c < nchunk; ++c) gsum += chunks[(int64_t)c * NPAR + k];
     const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
     float m = S[OADAM_M + k] = b1 * S[OADAM_M + k] + (1.0f - b1) * gsum;
     float v = S[OADAM_V + k] = b2 * S[OADAM_V + k] + (1.0f - b2) * gsum * gsum;
     S[k] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
 }
 
-__global__ void __launch_bounds__(256) k_mlp_sum_partials(const float *__restrict__ part,
-                                                           int nwaves, float *__restrict__ grad)
+__global__ void __launch_bounds__(256) k_mlp_sum_partials(const float *__restrict__ chunks,
+                                                           int nchunk, float *__restrict__ grad)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= NPAR) return;
     float gsum = 0.f;
-    for (int wv = 0; wv < nwaves; ++wv) gsum += part[(int64_t)wv * NPAR + k];
+    for (int c = 0; c < nchunk; ++c) gsum += chunks[(int64_t)c * NPAR + k];
     grad[k] = gsum;
 }
 
@@ -601,13 +635,19 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ S
     }
 }
 
-__global__ void k_loss_sum(const double *__restrict__ lp, int nwaves, int64_t n, float *__restrict__ out)
+// Mean squared error from the per-wave sums: one block, fixed order (strided
+// per-thread sums, then a butterfly within each wave, then the waves in order).
+__global__ void __launch_bounds__(256) k_loss_sum(const double *__restrict__ lp, int nwaves,
+                                                  int64_t n, float *__restrict__ out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < nwaves; ++i) s += lp[i];
-        out[0] = (float)(s / (4.0 * (double)n));
-    }
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nwaves; i += 256) s += lp[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = (float)((((sh[0] + sh[1]) + sh[2]) + sh[3]) / (4.0 * (double)n));
 }
 
 }  // namespace mlp
@@ -639,18 +679,28 @@ uint64_t mix(uint64_t &s)
     return z ^ (z >> 31);
 }
 
+constexpr int NWAVES_GRAD = GRAD_BLOCKS * TW;
+constexpr int NCHUNK = (NWAVES_GRAD + RCH - 1) / RCH;
+
+// Gradient partials per wave, then their chunk sums; *chunks_out holds NCHUNK
+// rows of NPAR floats, *loss_out the per-wave squared-error sums.
 int grad_impl(fr_plan *pl, const float *S, const float *X, const float *Y, int64_t n,
-              float **part_out, double **loss_out, hipStream_t s)
+              float **chunks_out, double **loss_out, hipStream_t s)
 {
-    const size_t bytes = (size_t)GRAD_BLOCKS * TW * NPAR * sizeof(float) +
-                         (size_t)GRAD_BLOCKS * TW * sizeof(double) + 64 * sizeof(float);
+    const size_t bytes = (size_t)NWAVES_GRAD * NPAR * sizeof(float) +
+                         (size_t)NWAVES_GRAD * sizeof(double) +
+                         (size_t)NCHUNK * NPAR * sizeof(float) + 64 * sizeof(float);
     if (int rc = ensure_scratch(pl->mlp, bytes)) return rc;
     float *part = (float *)pl->mlp.ptr;
-    double *lp = (double *)(part + (size_t)GRAD_BLOCKS * TW * NPAR);
+    double *lp = (double *)(part + (size_t)NWAVES_GRAD * NPAR);
+    float *chunks = (float *)(lp + NWAVES_GRAD);
     hipLaunchKernelGGL(k_mlp_grad, dim3(GRAD_BLOCKS), dim3(64 * TW), 0, s, S, X, Y, n, part, lp);
-    *part_out = part;
+    if (int rc = check_hip(hipGetLastError(), "k_mlp_grad launch")) return rc;
+    hipLaunchKernelGGL(k_mlp_chunks, dim3((NPAR + 255) / 256, NCHUNK), dim3(256), 0, s, part,
+                       NWAVES_GRAD, chunks);
+    *chunks_out = chunks;
     *loss_out = lp;
-    return check_hip(hipGetLastError(), "k_mlp_grad launch");
+    return check_hip(hipGetLastError(), "k_mlp_chunks launch");
 }
 
 }  // namespace
@@ -748,13 +798,13 @@ int fr_mlp_grad(fr_plan *pl, const float *state, const float *X, const float *Y,
     if (int rc = check_dev(grad, "grad")) return rc;
     if (n < 1) return set_error(FR_EINVAL, "fr_mlp_grad: n = %lld", (long long)n);
     hipStream_t s = (hipStream_t)sv;
-    float *part;
+    float *chunks;
     double *lp;
-    if (int rc = grad_impl(pl, state, X, Y, n, &part, &lp, s)) return rc;
-    // fixed-order sum of the per-wave partials, no update
-    hipLaunchKernelGGL(k_mlp_sum_partials, dim3((NPAR + 255) / 256), dim3(256), 0, s, part,
-                       GRAD_BLOCKS * TW, grad);
-    if (loss) hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, s, lp, GRAD_BLOCKS * TW, n, loss);
+    if (int rc = grad_impl(pl, state, X, Y, n, &chunks, &lp, s)) return rc;
+    // fixed-order sum of the chunk partials, no update
+    hipLaunchKernelGGL(k_mlp_sum_partials, dim3((NPAR + 255) / 256), dim3(256), 0, s, chunks,
+                       NCHUNK, grad);
+    if (loss) hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(256), 0, s, lp, NWAVES_GRAD, n, loss);
     return check_hip(hipGetLastError(), "fr_mlp_grad launch");
 }
 
@@ -769,12 +819,12 @@ int fr_mlp_train_step(fr_plan *pl, float *state, const float *X, const float *Y,
         return set_error(FR_EINVAL, "fr_mlp_train_step: n=%lld step=%d lr=%g", (long long)n, step,
                          (double)lr);
     hipStream_t s = (hipStream_t)sv;
-    float *part;
+    float *chunks;
     double *lp;
-    if (int rc = grad_impl(pl, state, X, Y, n, &part, &lp, s)) return rc;
-    if (loss) hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(64), 0, s, lp, GRAD_BLOCKS * TW, n, loss);
-    hipLaunchKernelGGL(k_mlp_adam, dim3((NPAR + 255) / 256), dim3(256), 0, s, part,
-                       GRAD_BLOCKS * TW, state, lr, 0.9f, 0.999f, 1e-8f, step);
+    if (int rc = grad_impl(pl, state, X, Y, n, &chunks, &lp, s)) return rc;
+    if (loss) hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(256), 0, s, lp, NWAVES_GRAD, n, loss);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((NPAR + 255) / 256), dim3(256), 0, s, chunks, NCHUNK,
+                       state, lr, 0.9f, 0.999f, 1e-8f, step);
     return check_hip(hipGetLastError(), "fr_mlp_train_step launch");
 }
 
