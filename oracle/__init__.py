@@ -27,6 +27,10 @@ Pin status (tests/test_oracle_*.py):
   diagnostics.diagnostics (diagnostics.py)       pinned (Taylor-Green closed forms, single
                                                  modes per curl entry, irrotational field)
   mlp_*                                          pinned (finite differences, autograd)
+  acm_ldg.residual, acm_ldg.gradient             pinned (reduction to the ACM-HD residual at
+  (standard ACM with LDG, acm_ldg.py)            nu = 0, smooth-field convergence, conservation,
+                                                 LDG energy identity for any beta and tau,
+                                                 one-sided gradient at beta = 1/2)
 """
 import ctypes
 import os
