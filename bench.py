@@ -175,6 +175,44 @@ def time_steps(p=3, N=64, steps=5):
     return out
 
 
+def time_acm(p=4, N=51, reps=10):
+    """Standard ACM with LDG viscous fluxes (the paper's comparison system,
+    beta = 0.5, tau = 0.1) against ACM-HD on the same p, N^3 FP64 box: ms per
+    residual by HIP events on the launch stream.  The ACM state is the first
+    four variables (P, V) of the sweep's Fourier state."""
+    import torch
+    from paper_2107_14027_amd import binding as B
+    from paper_2107_14027_amd import inputs
+    n = (N, N, N)
+    plan = B.Plan(p, n, ZETA, NU, TRELAX)
+    U13 = inputs.fourier(p, n, seed=1000 + p, device="cuda")
+    R13 = torch.empty_like(U13)
+    hd = time_residual(B, torch, plan, U13, R13, reps)
+    acm = B.Acm(plan, 0.5, 0.1)
+    U4 = U13.view(-1, NV, (p + 1) ** 3)[:, :4].contiguous().view(-1)
+    del R13
+    R4 = torch.empty_like(U4)
+    acm.residual(U4, R4)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        acm.residual(U4, R4)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    acm.close()
+    plan.close()
+    del U13, U4, R4
+    torch.cuda.empty_cache()
+    npts = N ** 3 * (p + 1) ** 3
+    return {"workload": "one residual, p=%d on %d^3 hexes (%d solution points), FP64" % (p, N, npts),
+            "acm_ldg_residual_ms": round(ms, 3), "acm_hd_fused_residual_ms": round(hd, 3),
+            "acm_ldg_Mpoints_per_s": round(npts / ms / 1e3, 1),
+            "acm_hd_Mpoints_per_s": round(npts / hd / 1e3, 1),
+            "acm_ldg_over_acm_hd_time": round(ms / hd, 3)}
+
+
 def time_mlp(p=3, N=64, rows=1 << 16, reps=10):
     """The learned guess's kernels on their own: one network guess over every
     point of a p=3, 64^3 FP64 state (three states read, one written: 416 B per
@@ -243,6 +281,8 @@ def main():
                     help="skip the RK4 / dual pseudo-step timing (stage epilogue vs separate stage kernel)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-guess study (pseudo-iterations per physical step)")
+    ap.add_argument("--no-acm", action="store_true",
+                    help="skip the standard ACM (LDG) residual timing beside ACM-HD")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -384,6 +424,11 @@ def main():
         timestep = time_steps()
         log("time steps: %s" % timestep)
 
+    acm = None
+    if not args.no_acm:
+        acm = time_acm()
+        log("standard ACM: %s" % acm)
+
     learned = None
     if not args.no_learned:
         from paper_2107_14027_amd import learned as L
@@ -461,6 +506,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "time_step": timestep,
+        "standard_acm_ldg": acm,
         "learned_guess": learned,
         "sweep": sweep,
         "kernel_ms": {str(p): {"trace": round(kstats[p]["trace_ms"], 4),

@@ -217,6 +217,49 @@ int fr_pmg_dual_step(fr_pmg *mg, double *U, const double *Un, const double *Unm1
 void fr_pmg_destroy(fr_pmg *mg);
 
 /*
+ * Standard ACM with LDG viscous fluxes -- the system the paper compares ACM-HD
+ * against (Sec. 2.2, eq. acm_2d in three dimensions; Sec. 5): unknowns
+ * (P, u, v, w), dU/dtau + div F = 0 with
+ *   F_j = [zeta u_j ; u_i u_j + P delta_ij - nu du_i/dx_j].
+ * The viscous term takes the FR route for second-order systems (Sec. 2.1):
+ * a corrected velocity gradient with a common solution at the interfaces,
+ * then the FR divergence.  Interfaces: Rusanov on the inviscid part (the
+ * ACM-HD wave speed), LDG on the viscous part, with L the element on the
+ * minus side of a face, R the plus side and n the unit normal along +xi_d:
+ *   u^I   = (u_L + u_R)/2 + beta (u_L - u_R)
+ *   F_v^I = (F_vL + F_vR).n/2 - beta (F_vL - F_vR).n + tau (u_L - u_R)  (velocity only)
+ * The paper's runs use beta = 0.5, tau = 0.1.  The geometry, order, zeta and
+ * nu come from the plan (its precision, variant and T are not used: this path
+ * is double precision only).  States are U[e][4][m^3] (P, u, v, w), the same
+ * element and point order as the ACM-HD state.
+ *
+ * fr_acm_create -- bind beta and tau (finite, tau >= 0) to the plan (borrowed:
+ * it must outlive the object) and allocate the intermediates on the current
+ * device: face traces (24 m^2 doubles per element), the gradient (9 m^3) and
+ * the common fluxes (12 m^2).  Returns NULL on error (fr_last_error() says why).
+ */
+typedef struct fr_acm fr_acm;
+fr_acm *fr_acm_create(fr_plan *plan, double ldg_beta, double ldg_tau);
+
+/*
+ * fr_acm_residual -- R = -div F of the device state U, both [ne][4][m^3]
+ * double, 8-byte aligned, R not aliasing U.  Asynchronous on stream s; calls
+ * that overlap on one object share its intermediates and race.  Returns
+ * FR_EINVAL on bad arguments, else FR_OK or a launch error.
+ */
+int fr_acm_residual(fr_acm *a, const double *U, double *R, fr_stream_t s);
+
+/*
+ * fr_acm_gradient -- the corrected velocity gradient of U:
+ * Q[e][3 i + j][m^3] = du_i/dx_j (device, double).  Same rules as
+ * fr_acm_residual.
+ */
+int fr_acm_gradient(fr_acm *a, const double *U, double *Q, fr_stream_t s);
+
+/* Release the intermediates (waits for the device). */
+void fr_acm_destroy(fr_acm *a);
+
+/*
  * fr_diagnostics -- flow diagnostics of a double state U (Sec. 5 follows the
  * Taylor-Green run through them):
  *   out[0] = kinetic energy  (1/|Omega|) int |V|^2 / 2 dx

@@ -24,7 +24,8 @@ EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_des
             "fr_strerror", "fr_last_error", "fr_plan_operators", "fr_plan_kernel_stats",
             "fr_mlp_state_floats", "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm",
             "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess",
-            "fr_pmg_create", "fr_pmg_dual_step", "fr_pmg_destroy", "fr_diagnostics")
+            "fr_pmg_create", "fr_pmg_dual_step", "fr_pmg_destroy", "fr_diagnostics",
+            "fr_acm_create", "fr_acm_residual", "fr_acm_gradient", "fr_acm_destroy")
 
 
 class FrError(RuntimeError):
@@ -80,10 +81,17 @@ def lib():
         L.fr_diagnostics.argtypes = [_vp, _vp, _dp, _vp]
         L.fr_pmg_destroy.argtypes = [_vp]
         L.fr_pmg_destroy.restype = None
+        L.fr_acm_create.argtypes = [_vp, D, D]
+        L.fr_acm_create.restype = _vp
+        L.fr_acm_residual.argtypes = [_vp, _vp, _vp, _vp]
+        L.fr_acm_gradient.argtypes = [_vp, _vp, _vp, _vp]
+        L.fr_acm_destroy.argtypes = [_vp]
+        L.fr_acm_destroy.restype = None
         for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step", "fr_pmg_dual_step", "fr_diagnostics",
                   "fr_dual_step", "fr_guess_extrap", "fr_plan_operators", "fr_plan_kernel_stats",
                   "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm", "fr_mlp_forward",
-                  "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess"):
+                  "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess", "fr_acm_residual",
+                  "fr_acm_gradient"):
             getattr(L, n).restype = I
         _lib = L
     return _lib
@@ -222,6 +230,31 @@ def fr_pmg_destroy(mg):
     lib().fr_pmg_destroy(mg)
 
 
+def fr_acm_create(plan, beta=0.5, tau=0.1):
+    ptr = lib().fr_acm_create(plan, float(beta), float(tau))
+    if not ptr:
+        raise FrError(FR_EINVAL, lib().fr_last_error().decode())
+    return ptr
+
+
+def fr_acm_residual(acm, U, R, n, stream=None):
+    """R = -div F of the standard-ACM state U (both [ne][4][m^3] double, n values)."""
+    import torch
+    return _check(lib().fr_acm_residual(acm, _dev(U, torch.float64, n, "U"),
+                                        _dev(R, torch.float64, n, "R"), _stream(stream)))
+
+
+def fr_acm_gradient(acm, U, Q, n, stream=None):
+    """Q[e][3 i + j][m^3] = du_i/dx_j of the standard-ACM state U (n values)."""
+    import torch
+    return _check(lib().fr_acm_gradient(acm, _dev(U, torch.float64, n, "U"),
+                                        _dev(Q, torch.float64, n // 4 * 9, "Q"), _stream(stream)))
+
+
+def fr_acm_destroy(acm):
+    lib().fr_acm_destroy(acm)
+
+
 FR_GUESS_KEEP_P = 0x10   # or-ed into the order of fr_guess_extrap: pressure from Un
 
 
@@ -340,6 +373,33 @@ def fr_plan_operators(p):
         r[name] = out[o:o + size].reshape(shape)
         o += size
     return r
+
+
+class Acm:
+    """Owning wrapper around an fr_acm handle (standard ACM with LDG; the plan
+    must stay open).  state_len: values of a [ne][4][m^3] state."""
+
+    def __init__(self, plan, beta=0.5, tau=0.1):
+        self.plan = plan
+        self.state_len = plan.state_len // NV * 4
+        self.handle = fr_acm_create(plan.handle, beta, tau)
+
+    def residual(self, U, R, stream=None):
+        return fr_acm_residual(self.handle, U, R, self.state_len, stream)
+
+    def gradient(self, U, Q, stream=None):
+        return fr_acm_gradient(self.handle, U, Q, self.state_len, stream)
+
+    def close(self):
+        if self.handle:
+            fr_acm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Pmg:

@@ -1,0 +1,331 @@
+// Standard ACM with LDG viscous fluxes: the comparison system of the paper's
+// Sec. 5 (eq. acm_2d taken to three dimensions), unknowns (P, u, v, w) in
+// double precision,
+//   dU/dtau + div F = 0,  F_j = [zeta u_j ; u_i u_j + P delta_ij - nu du_i/dx_j].
+// The viscous term needs the FR route for second-order systems (Sec. 2.1):
+// a corrected velocity gradient with a common solution at the interfaces,
+// then the FR divergence of the flux built with it.  Interfaces (Sec. 5):
+// Rusanov on the inviscid part (the ACM-HD wave speed), LDG on the viscous
+// part.  Between L (element on the minus side of a face) and R (plus side),
+// unit normal n along +xi_d:
+//   u^I   = (u_L + u_R)/2 + beta (u_L - u_R)
+//   F_v^I = (F_vL + F_vR).n/2 - beta (F_vL - F_vR).n + tau (u_L - u_R)   (velocity)
+//
+// Four plain kernels, one thread per output value, every intermediate through
+// HBM (this is the unfused multi-step pipeline that hyperbolised diffusion
+// removes):
+//   k_acm_trace   U -> face traces of P, V         utr[e][6][4][m^2]
+//   k_acm_grad    U, utr -> corrected gradient     Q[e][9][m^3]   (du_i/dx_j at 3 i + j)
+//   k_acm_common  utr, Q -> common normal flux     FI[e][3][4][m^2] (plus face of e)
+//   k_acm_resid   U, Q, FI -> R = -div F           R[e][4][m^3]
+// Faces are numbered f = 2 d + side (side 0: xi_d = -1); a face point (a, b)
+// holds the two tangential point indices in increasing direction order.
+#include <algorithm>
+#include <cmath>
+
+#include "fr_internal.h"
+
+namespace fr {
+namespace {
+
+constexpr int NA = 4;
+constexpr int TB = 256;
+constexpr int MM = PMAX + 1;
+
+struct AcmArgs {
+    double D[MM * MM], Dt[MM * MM];  // l_k'(x_i); D minus the two boundary corrections
+    double gl[MM], gr[MM];            // correction derivatives h_l'(x_i), h_r'(x_i)
+    double lm[MM], lp[MM];            // l_k(-1), l_k(+1)
+    double Jinv[9];                   // (J^{-1})_{d j} at 3 d + j
+    double nvec[9], nhat[9], nmag[3]; // n_d = det J J^{-T} e_d, n_d / |n_d|, |n_d|
+    double inv_det, zeta, nu, beta, tau;
+    int m, nx, ny, nz;
+};
+
+__device__ __forceinline__ int line_pt(int m, int d, int a, int b, int l)
+{
+    return d == 0 ? l + m * (a + m * b) : (d == 1 ? a + m * (l + m * b) : a + m * (b + m * l));
+}
+
+// neighbour of element e one step along direction d (dir = +-1), periodic
+__device__ __forceinline__ int64_t nbr(const AcmArgs &A, int64_t e, int d, int dir)
+{
+    int64_t ex = e % A.nx, t = e / A.nx;
+    int64_t ey = t % A.ny, ez = t / A.ny;
+    if (d == 0) ex = (ex + dir + A.nx) % A.nx;
+    else if (d == 1) ey = (ey + dir + A.ny) % A.ny;
+    else ez = (ez + dir + A.nz) % A.nz;
+    return ex + (int64_t)A.nx * (ey + (int64_t)A.ny * ez);
+}
+
+// the line through point (i, j, k) along d: its position l0 and face point (a, b)
+__device__ __forceinline__ void line_of(int d, int i, int j, int k, int &l0, int &a, int &b)
+{
+    if (d == 0) l0 = i, a = j, b = k;
+    else if (d == 1) l0 = j, a = i, b = k;
+    else l0 = k, a = i, b = j;
+}
+
+__global__ void __launch_bounds__(TB) k_acm_trace(const double *__restrict__ U,
+                                                  double *__restrict__ utr, AcmArgs A, int64_t ne)
+{
+    const int m = A.m, nfp = m * m, ns = nfp * m;
+    const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (t >= ne * 6 * nfp) return;
+    const int ab = (int)(t % nfp);
+    const int f = (int)((t / nfp) % 6);
+    const int64_t e = t / (6 * nfp);
+    const int d = f >> 1, side = f & 1, a = ab % m, b = ab / m;
+    const double *L = side ? A.lp : A.lm;
+    const double *Ue = U + e * NA * ns;
+    for (int v = 0; v < NA; ++v) {
+        double s = 0.0;
+        for (int l = 0; l < m; ++l) s += L[l] * Ue[v * ns + line_pt(m, d, a, b, l)];
+        utr[((e * 6 + f) * NA + v) * nfp + ab] = s;
+    }
+}
+
+__global__ void __launch_bounds__(TB) k_acm_grad(const double *__restrict__ U,
+                                                 const double *__restrict__ utr,
+                                                 double *__restrict__ Q, AcmArgs A, int64_t ne)
+{
+    const int m = A.m, nfp = m * m, ns = nfp * m;
+    const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (t >= ne * ns) return;
+    const int q = (int)(t % ns);
+    const int64_t e = t / ns;
+    const int i = q % m, j = (q / m) % m, k = q / nfp;
+    const double *Ue = U + e * NA * ns;
+    double g[3][3];  // g[c][d]: d/dxi_d of velocity component c
+    for (int d = 0; d < 3; ++d) {
+        int l0, a, b;
+        line_of(d, i, j, k, l0, a, b);
+        const int ab = a + m * b;
+        const int64_t em = nbr(A, e, d, -1), ep = nbr(A, e, d, +1);
+        for (int c = 0; c < 3; ++c) {
+            const int v = 1 + c;
+            double s = 0.0;
+            for (int l = 0; l < m; ++l) s += A.D[l0 * m + l] * Ue[v * ns + line_pt(m, d, a, b, l)];
+            const double om = utr[((e * 6 + 2 * d) * NA + v) * nfp + ab];
+            const double op = utr[((e * 6 + 2 * d + 1) * NA + v) * nfp + ab];
+            const double nm = utr[((em * 6 + 2 * d + 1) * NA + v) * nfp + ab];  // e-1's plus face
+            const double np = utr[((ep * 6 + 2 * d) * NA + v) * nfp + ab];      // e+1's minus face
+            const double uim = 0.5 * (nm + om) + A.beta * (nm - om);
+            const double uip = 0.5 * (op + np) + A.beta * (op - np);
+            g[c][d] = s + A.gl[l0] * (uim - om) + A.gr[l0] * (uip - op);
+        }
+    }
+    double *Qe = Q + e * 9 * ns + q;
+    for (int c = 0; c < 3; ++c)
+        for (int jx = 0; jx < 3; ++jx)
+            Qe[(3 * c + jx) * ns] =
+                A.Jinv[jx] * g[c][0] + A.Jinv[3 + jx] * g[c][1] + A.Jinv[6 + jx] * g[c][2];
+}
+
+__global__ void __launch_bounds__(TB) k_acm_common(const double *__restrict__ utr,
+                                                   const double *__restrict__ Q,
+                                                   double *__restrict__ FI, AcmArgs A, int64_t ne)
+{
+    const int m = A.m, nfp = m * m, ns = nfp * m;
+    const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (t >= ne * 3 * nfp) return;
+    const int ab = (int)(t % nfp);
+    const int d = (int)((t / nfp) % 3);
+    const int64_t e = t / (3 * nfp);
+    const int a = ab % m, b = ab / m;
+    const int64_t er = nbr(A, e, d, +1);
+    const double *nh = A.nhat + 3 * d;
+    double uL[NA], uR[NA];
+    for (int v = 0; v < NA; ++v) {
+        uL[v] = utr[((e * 6 + 2 * d + 1) * NA + v) * nfp + ab];
+        uR[v] = utr[((er * 6 + 2 * d) * NA + v) * nfp + ab];
+    }
+    // viscous normal flux -nu (grad u_c) . n of both sides, from Q traced to the face
+    double fvL[3], fvR[3];
+    for (int c = 0; c < 3; ++c) {
+        double sl = 0.0, sr = 0.0;
+        for (int jx = 0; jx < 3; ++jx) {
+            double ql = 0.0, qr = 0.0;
+            for (int l = 0; l < m; ++l) {
+                const int pt = line_pt(m, d, a, b, l);
+                ql += A.lp[l] * Q[(e * 9 + 3 * c + jx) * ns + pt];
+                qr += A.lm[l] * Q[(er * 9 + 3 * c + jx) * ns + pt];
+            }
+            sl += ql * nh[jx];
+            sr += qr * nh[jx];
+        }
+        fvL[c] = -A.nu * sl;
+        fvR[c] = -A.nu * sr;
+    }
+    const double vnL = uL[1] * nh[0] + uL[2] * nh[1] + uL[3] * nh[2];
+    const double vnR = uR[1] * nh[0] + uR[2] * nh[1] + uR[3] * nh[2];
+    const double lam = fmax(fabs(vnL) + sqrt(vnL * vnL + A.zeta), fabs(vnR) + sqrt(vnR * vnR + A.zeta));
+    double *out = FI + (e * 3 + d) * NA * nfp + ab;
+    out[0] = 0.5 * A.zeta * (vnL + vnR) - 0.5 * lam * (uR[0] - uL[0]);
+    for (int c = 0; c < 3; ++c) {
+        const double mL = uL[1 + c] * vnL + uL[0] * nh[c];
+        const double mR = uR[1 + c] * vnR + uR[0] * nh[c];
+        out[(1 + c) * nfp] = 0.5 * (mL + mR) - 0.5 * lam * (uR[1 + c] - uL[1 + c]) +
+                             0.5 * (fvL[c] + fvR[c]) - A.beta * (fvL[c] - fvR[c]) +
+                             A.tau * (uL[1 + c] - uR[1 + c]);
+    }
+}
+
+__global__ void __launch_bounds__(TB) k_acm_resid(const double *__restrict__ U,
+                                                  const double *__restrict__ Q,
+                                                  const double *__restrict__ FI,
+                                                  double *__restrict__ R, AcmArgs A, int64_t ne)
+{
+    const int m = A.m, nfp = m * m, ns = nfp * m;
+    const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (t >= ne * ns) return;
+    const int q = (int)(t % ns);
+    const int64_t e = t / ns;
+    const int i = q % m, j = (q / m) % m, k = q / nfp;
+    const double *Ue = U + e * NA * ns;
+    const double *Qe = Q + e * 9 * ns;
+    double div[NA] = {0.0, 0.0, 0.0, 0.0};
+    for (int d = 0; d < 3; ++d) {
+        int l0, a, b;
+        line_of(d, i, j, k, l0, a, b);
+        const double *nv = A.nvec + 3 * d;
+        for (int l = 0; l < m; ++l) {
+            const int pt = line_pt(m, d, a, b, l);
+            const double w = A.Dt[l0 * m + l];
+            const double P = Ue[pt], V[3] = {Ue[ns + pt], Ue[2 * ns + pt], Ue[3 * ns + pt]};
+            const double vn = V[0] * nv[0] + V[1] * nv[1] + V[2] * nv[2];
+            div[0] += w * A.zeta * vn;
+            for (int c = 0; c < 3; ++c) {
+                // (V_c V + P e_c - nu grad u_c) . n_d
+                const double gn = Qe[(3 * c) * ns + pt] * nv[0] + Qe[(3 * c + 1) * ns + pt] * nv[1] +
+                                  Qe[(3 * c + 2) * ns + pt] * nv[2];
+                div[1 + c] += w * (V[c] * vn + P * nv[c] - A.nu * gn);
+            }
+        }
+        const int ab = a + m * b;
+        const int64_t em = nbr(A, e, d, -1);
+        const double *Fp = FI + (e * 3 + d) * NA * nfp + ab;
+        const double *Fm = FI + (em * 3 + d) * NA * nfp + ab;
+        for (int v = 0; v < NA; ++v)
+            div[v] += A.nmag[d] * (A.gl[l0] * Fm[v * nfp] + A.gr[l0] * Fp[v * nfp]);
+    }
+    double *Re = R + e * NA * ns + q;
+    for (int v = 0; v < NA; ++v) Re[v * ns] = -div[v] * A.inv_det;
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + TB - 1) / TB); }
+
+}  // namespace
+}  // namespace fr
+
+struct fr_acm {
+    fr_plan *plan = nullptr;
+    fr::AcmArgs args;
+    double *utr = nullptr, *Q = nullptr, *FI = nullptr;
+};
+
+using namespace fr;
+
+namespace {
+
+int acm_check(fr_acm *a, const void *U, const void *out, const char *what)
+{
+    if (!a || !U || !out) return set_error(FR_EINVAL, "%s: NULL argument", what);
+    if (((uintptr_t)U | (uintptr_t)out) & 7) return set_error(FR_EINVAL, "%s: unaligned state", what);
+    if (U == out) return set_error(FR_EINVAL, "%s: the output may not alias the input", what);
+    return FR_OK;
+}
+
+int launch_front(fr_acm *a, const double *U, hipStream_t s)
+{
+    const int64_t ne = a->plan->ne;
+    const int m = a->args.m, nfp = m * m, ns = nfp * m;
+    hipLaunchKernelGGL(k_acm_trace, dim3(blocks_for(ne * 6 * nfp)), dim3(TB), 0, s, U, a->utr,
+                       a->args, ne);
+    if (int rc = check_hip(hipGetLastError(), "k_acm_trace launch")) return rc;
+    hipLaunchKernelGGL(k_acm_grad, dim3(blocks_for(ne * ns)), dim3(TB), 0, s, U, a->utr, a->Q,
+                       a->args, ne);
+    return check_hip(hipGetLastError(), "k_acm_grad launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+fr_acm *fr_acm_create(fr_plan *plan, double ldg_beta, double ldg_tau)
+{
+    if (!plan) {
+        set_error(FR_EINVAL, "fr_acm_create: NULL plan");
+        return nullptr;
+    }
+    if (!std::isfinite(ldg_beta) || !std::isfinite(ldg_tau) || ldg_tau < 0.0) {
+        set_error(FR_EINVAL, "fr_acm_create: beta=%g tau=%g", ldg_beta, ldg_tau);
+        return nullptr;
+    }
+    fr_acm *a = new fr_acm();
+    a->plan = plan;
+    AcmArgs &A = a->args;
+    const int m = plan->m;
+    A.m = m;
+    A.nx = plan->nx, A.ny = plan->ny, A.nz = plan->nz;
+    for (int i = 0; i < m * m; ++i) A.D[i] = plan->D[i], A.Dt[i] = plan->Dt[i];
+    for (int i = 0; i < m; ++i)
+        A.gl[i] = plan->gl[i], A.gr[i] = plan->gr[i], A.lm[i] = plan->lm[i], A.lp[i] = plan->lp[i];
+    for (int d = 0; d < 3; ++d) {
+        A.nmag[d] = plan->c64.nmag[d];
+        for (int j = 0; j < 3; ++j) {
+            A.Jinv[3 * d + j] = plan->Jinv[3 * d + j];
+            A.nvec[3 * d + j] = plan->c64.nvec[d][j];
+            A.nhat[3 * d + j] = plan->c64.nhat[d][j];
+        }
+    }
+    A.inv_det = 1.0 / plan->detJ;
+    A.zeta = plan->zeta;
+    A.nu = plan->nu;
+    A.beta = ldg_beta;
+    A.tau = ldg_tau;
+    const int64_t ne = plan->ne;
+    const size_t nfp = (size_t)m * m, ns = nfp * m;
+    if (check_hip(hipMalloc((void **)&a->utr, (size_t)ne * 6 * NA * nfp * sizeof(double)), "hipMalloc(acm traces)") ||
+        check_hip(hipMalloc((void **)&a->Q, (size_t)ne * 9 * ns * sizeof(double)), "hipMalloc(acm gradient)") ||
+        check_hip(hipMalloc((void **)&a->FI, (size_t)ne * 3 * NA * nfp * sizeof(double)), "hipMalloc(acm fluxes)")) {
+        fr_acm_destroy(a);
+        return nullptr;
+    }
+    return a;
+}
+
+int fr_acm_gradient(fr_acm *a, const double *U, double *Q, fr_stream_t sv)
+{
+    if (int rc = acm_check(a, U, Q, "fr_acm_gradient")) return rc;
+    hipStream_t s = (hipStream_t)sv;
+    if (int rc = launch_front(a, U, s)) return rc;
+    const size_t bytes = (size_t)a->plan->ne * 9 * a->args.m * a->args.m * a->args.m * sizeof(double);
+    return check_hip(hipMemcpyAsync(Q, a->Q, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(acm gradient)");
+}
+
+int fr_acm_residual(fr_acm *a, const double *U, double *R, fr_stream_t sv)
+{
+    if (int rc = acm_check(a, U, R, "fr_acm_residual")) return rc;
+    hipStream_t s = (hipStream_t)sv;
+    const int64_t ne = a->plan->ne;
+    const int m = a->args.m, nfp = m * m, ns = nfp * m;
+    if (int rc = launch_front(a, U, s)) return rc;
+    hipLaunchKernelGGL(k_acm_common, dim3(blocks_for(ne * 3 * nfp)), dim3(TB), 0, s, a->utr, a->Q,
+                       a->FI, a->args, ne);
+    if (int rc = check_hip(hipGetLastError(), "k_acm_common launch")) return rc;
+    hipLaunchKernelGGL(k_acm_resid, dim3(blocks_for(ne * ns)), dim3(TB), 0, s, U, a->Q, a->FI, R,
+                       a->args, ne);
+    return check_hip(hipGetLastError(), "k_acm_resid launch");
+}
+
+void fr_acm_destroy(fr_acm *a)
+{
+    if (!a) return;
+    if (a->utr) (void)hipFree(a->utr);
+    if (a->Q) (void)hipFree(a->Q);
+    if (a->FI) (void)hipFree(a->FI);
+    delete a;
+}
+
+}  // extern "C"
