@@ -31,6 +31,8 @@ Pin status (tests/test_oracle_*.py):
   (standard ACM with LDG, acm_ldg.py)            nu = 0, smooth-field convergence, conservation,
                                                  LDG energy identity for any beta and tau,
                                                  one-sided gradient at beta = 1/2)
+  acm_ldg.dual_step                              pinned (equals the ACM-HD dual step on P, V
+                                                 at nu = tau = 0: states, norms, iterations)
 """
 import ctypes
 import os

@@ -26,7 +26,8 @@ internally (nz, ny, nx, var, k, j, i).
 
 Pins: tests/test_oracle_acm_ldg.py (reduction to the ACM-HD oracle at nu = 0,
 closed-form smooth residual, conservation, the LDG energy identity for any
-beta and tau, the side the common solution is taken from).
+beta and tau, the side the common solution is taken from; the dual step's
+reduction to the ACM-HD C oracle's dual step at nu = tau = 0).
 """
 import numpy as np
 
@@ -157,3 +158,49 @@ def residual(p, n, U, zeta, nu, beta=0.5, tau=0.1, jac=None):
         div += _spread(nmag[d] * FIp - _face(Fh, ops["lp"], d), ops["hr"], d)
     m = p + 1
     return (-div / det).reshape(-1, NA, m ** 3)
+
+
+def pseudo_residual(p, n, U, Un, Unm1, dt, zeta, nu, beta, tau, jac):
+    """R* = R(U) - M_V dU/dt with the BDF2 derivative (3U - 4Un + Unm1)/(2 dt),
+    or BDF1 (U - Un)/dt when Unm1 is None; velocity only: the pressure has no
+    physical time derivative (Sec. 2.2), as for ACM-HD."""
+    Rs = residual(p, n, U, zeta, nu, beta, tau, jac)
+    V, Vn = U[:, 1:4], Un[:, 1:4]
+    dudt = (3.0 * V - 4.0 * Vn + Unm1[:, 1:4]) / (2.0 * dt) if Unm1 is not None else (V - Vn) / dt
+    Rs[:, 1:4] -= dudt
+    return Rs
+
+
+def velocity_rms(Rs):
+    """Root mean square of the three velocity components of R* over all points."""
+    return float(np.sqrt(np.sum(Rs[:, 1:4] ** 2) / (3.0 * Rs.shape[0] * Rs.shape[2])))
+
+
+def dual_step(p, n, U0, Un, Unm1, zeta, nu, dt, dtau, tol, max_iters, beta=0.5, tau=0.1, jac=None):
+    """One BDF physical step of the standard ACM system by classical RK4
+    pseudo-steps of size dtau on dU/dtau = R*(U) (Sec. 5's dual time stepping),
+    until RMS(R*_V) < tol, tested on the first-stage residual of every
+    pseudo-step.  Returns (U, iters, resid, rc): rc 0 converged, -5 max_iters
+    reached, -4 non-finite norm."""
+    m3 = (p + 1) ** 3
+    U = np.array(U0, dtype=np.float64).reshape(-1, NA, m3)
+    Un = np.asarray(Un, dtype=np.float64).reshape(-1, NA, m3)
+    Unm1 = None if Unm1 is None else np.asarray(Unm1, dtype=np.float64).reshape(-1, NA, m3)
+    c = (0.0, 0.5, 0.5, 1.0)
+    b = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
+    it = 0
+    while True:
+        k = pseudo_residual(p, n, U, Un, Unm1, dt, zeta, nu, beta, tau, jac)
+        res = velocity_rms(k)
+        if not np.isfinite(res):
+            return U, it, res, -4
+        if res < tol:
+            return U, it, res, 0
+        if it >= max_iters:
+            return U, it, res, -5
+        acc = b[0] * k
+        for s in range(1, 4):
+            k = pseudo_residual(p, n, U + c[s] * dtau * k, Un, Unm1, dt, zeta, nu, beta, tau, jac)
+            acc = acc + b[s] * k
+        U = U + dtau * acc
+        it += 1

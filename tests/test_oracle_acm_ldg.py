@@ -135,3 +135,25 @@ def test_half_beta_takes_the_minus_side():
         assert (np.abs(Q0[0] - Q1[0]).max() <= 1e-14 * scale) == same
         # ex = 2: its minus-x neighbour changed
         assert np.abs(Q0[2] - Q1[2]).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize("bdf2,tol,maxit", [(True, 1.2e-3, 400), (False, 1e-30, 6)])
+def test_dual_step_reduces_to_acmhd(bdf2, tol, maxit):
+    """At nu = 0 and tau = 0 the standard ACM dual step is the ACM-HD dual step
+    (the C oracle) restricted to P and V: same states, norms and iteration counts."""
+    from paper_2107_14027_amd import inputs
+    p, n = 3, (2, 2, 2)
+    Unm1 = inputs.tgv(p, n, noise=1e-4, seed=2)
+    Un = oracle.rk4(p, n, Unm1, ZETA, 0.0, 0.3, 2.5e-3, 4)
+    G = 2 * Un - Unm1
+    Um = Unm1 if bdf2 else None
+    Uo, ito, reso, rco = oracle.dual_step(p, n, G, Un, Um, ZETA, 0.0, 0.3, 1e-2, 1e-3, tol, maxit,
+                                          order=2 if bdf2 else 1)
+    sel = lambda X: np.asarray(X).reshape(-1, 13, (p + 1) ** 3)[:, :4]
+    U, it, res, rc = A.dual_step(p, n, sel(G), sel(Un), None if Um is None else sel(Um), ZETA, 0.0,
+                                 1e-2, 1e-3, tol, maxit, beta=0.5, tau=0.0)
+    assert rc == rco and it == ito
+    assert res == pytest.approx(reso, rel=1e-11)
+    assert np.max(np.abs(U - sel(Uo))) <= 1e-12 * np.max(np.abs(sel(Uo)))
+    if bdf2:
+        assert rc == 0 and it > 1
