@@ -213,6 +213,45 @@ def time_acm(p=4, N=51, reps=10):
             "acm_ldg_over_acm_hd_time": round(ms / hd, 3)}
 
 
+def compare_dual(p=3, N=32, dt=1e-2, dtaus=(2e-3, 8e-3), tol=1e-4, max_iters=400):
+    """One BDF1 physical step of the Taylor-Green vortex (Re 1600, zeta = 2.5,
+    T = 5e-3, FP64) from its initial state by classical RK4 pseudo-steps of a
+    fixed size, for standard ACM with LDG and for ACM-HD: pseudo-steps to reach
+    tol and wall time (the norm is read back every pseudo-step in both)."""
+    import torch
+    from paper_2107_14027_amd import binding as B
+    from paper_2107_14027_amd import inputs
+    nu, _ = inputs.nu_T_from_length(1600.0, 1.0 / (2.0 * math.pi))
+    n = (N, N, N)
+    plan = B.Plan(p, n, 2.5, nu, 5e-3)
+    acm = B.Acm(plan, 0.5, 0.1)
+    U0 = torch.tensor(inputs.tgv(p, n), device="cuda")
+    A0 = U0.view(-1, NV, (p + 1) ** 3)[:, :4].contiguous().view(-1)
+    out = {"workload": "one BDF1 step (dt %g) of the Taylor-Green vortex from t = 0, p=%d on %d^3, "
+                       "Re 1600, FP64, RK4 pseudo-steps to RMS(R*_V) < %g" % (dt, p, N, tol)}
+    for dtau in dtaus:
+        row = {}
+        for name in ("acm_hd", "acm_ldg"):
+            W = (U0 if name == "acm_hd" else A0).clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if name == "acm_hd":
+                rc, it, res = B.fr_dual_step(plan.handle, W, U0, None, dt, dtau, tol, max_iters,
+                                             check_every=1, raise_on_error=False)
+            else:
+                rc, it, res = acm.dual_step(W, A0, None, dt, dtau, tol, max_iters, raise_on_error=False)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t)
+            row[name] = {"converged": rc == B.FR_OK, "pseudo_steps": it, "ms": round(ms, 2),
+                         "ms_per_pseudo_step": round(ms / max(1, it), 3)}
+        out["dtau_%g" % dtau] = row
+    acm.close()
+    plan.close()
+    del U0, A0
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_mlp(p=3, N=64, rows=1 << 16, reps=10):
     """The learned guess's kernels on their own: one network guess over every
     point of a p=3, 64^3 FP64 state (three states read, one written: 416 B per
@@ -427,6 +466,7 @@ def main():
     acm = None
     if not args.no_acm:
         acm = time_acm()
+        acm["dual_step"] = compare_dual()
         log("standard ACM: %s" % acm)
 
     learned = None

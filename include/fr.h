@@ -256,6 +256,25 @@ int fr_acm_residual(fr_acm *a, const double *U, double *R, fr_stream_t s);
  */
 int fr_acm_gradient(fr_acm *a, const double *U, double *Q, fr_stream_t s);
 
+/*
+ * fr_acm_dual_step -- one physical time step of this system by dual time
+ * stepping (Sec. 5): classical RK4 pseudo-steps of size dtau on
+ * dU/dtau = R*(U), with the BDF source on the velocity only,
+ *     R*(U) = R(U) - M_V (3U - 4Un + Unm1) / (2 dt)    (Unm1 != NULL, BDF2)
+ *     R*(U) = R(U) - M_V (U - Un) / dt                 (Unm1 == NULL, BDF1)
+ * until the root mean square over all points of the velocity part of R*
+ * falls below tol, tested on the first-stage residual of a pseudo-step every
+ * check_every steps (and when max_iters is reached).  U: in the initial
+ * guess, out the last iterate; iters, resid: out, completed pseudo-steps and
+ * the last norm computed.  Device states as fr_acm_residual; U may alias
+ * neither Un nor Unm1.  Allocates four more state-sized arrays and a pinned
+ * host word on first use; synchronises the stream at every check.  Returns
+ * FR_OK, FR_ENOCONV (U holds the last iterate), FR_ENONFINITE or FR_EINVAL.
+ */
+int fr_acm_dual_step(fr_acm *a, double *U, const double *Un, const double *Unm1, double dt,
+                     double dtau, double tol, int max_iters, int check_every, int *iters,
+                     double *resid, fr_stream_t s);
+
 /* Release the intermediates (waits for the device). */
 void fr_acm_destroy(fr_acm *a);
 

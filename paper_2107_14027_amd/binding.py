@@ -25,7 +25,8 @@ EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_des
             "fr_mlp_state_floats", "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm",
             "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess",
             "fr_pmg_create", "fr_pmg_dual_step", "fr_pmg_destroy", "fr_diagnostics",
-            "fr_acm_create", "fr_acm_residual", "fr_acm_gradient", "fr_acm_destroy")
+            "fr_acm_create", "fr_acm_residual", "fr_acm_gradient", "fr_acm_dual_step",
+            "fr_acm_destroy")
 
 
 class FrError(RuntimeError):
@@ -85,13 +86,14 @@ def lib():
         L.fr_acm_create.restype = _vp
         L.fr_acm_residual.argtypes = [_vp, _vp, _vp, _vp]
         L.fr_acm_gradient.argtypes = [_vp, _vp, _vp, _vp]
+        L.fr_acm_dual_step.argtypes = [_vp, _vp, _vp, _vp, D, D, D, I, I, ctypes.POINTER(I), _dp, _vp]
         L.fr_acm_destroy.argtypes = [_vp]
         L.fr_acm_destroy.restype = None
         for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step", "fr_pmg_dual_step", "fr_diagnostics",
                   "fr_dual_step", "fr_guess_extrap", "fr_plan_operators", "fr_plan_kernel_stats",
                   "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm", "fr_mlp_forward",
                   "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess", "fr_acm_residual",
-                  "fr_acm_gradient"):
+                  "fr_acm_gradient", "fr_acm_dual_step"):
             getattr(L, n).restype = I
         _lib = L
     return _lib
@@ -251,6 +253,21 @@ def fr_acm_gradient(acm, U, Q, n, stream=None):
                                         _dev(Q, torch.float64, n // 4 * 9, "Q"), _stream(stream)))
 
 
+def fr_acm_dual_step(acm, U, Un, Unm1, dt, dtau, tol, max_iters, n, check_every=1, stream=None,
+                     raise_on_error=True):
+    """Returns (status, iters, resid) of one BDF physical step of the standard-ACM state U."""
+    import torch
+    it = ctypes.c_int()
+    res = ctypes.c_double()
+    rc = lib().fr_acm_dual_step(acm, _dev(U, torch.float64, n, "U"), _dev(Un, torch.float64, n, "Un"),
+                                None if Unm1 is None else _dev(Unm1, torch.float64, n, "Unm1"),
+                                float(dt), float(dtau), float(tol), int(max_iters), int(check_every),
+                                ctypes.byref(it), ctypes.byref(res), _stream(stream))
+    if raise_on_error and rc not in (FR_OK, FR_ENOCONV):
+        _check(rc)
+    return rc, it.value, res.value
+
+
 def fr_acm_destroy(acm):
     lib().fr_acm_destroy(acm)
 
@@ -389,6 +406,11 @@ class Acm:
 
     def gradient(self, U, Q, stream=None):
         return fr_acm_gradient(self.handle, U, Q, self.state_len, stream)
+
+    def dual_step(self, U, Un, Unm1, dt, dtau, tol, max_iters, check_every=1, stream=None,
+                  raise_on_error=True):
+        return fr_acm_dual_step(self.handle, U, Un, Unm1, dt, dtau, tol, max_iters, self.state_len,
+                                check_every, stream, raise_on_error)
 
     def close(self):
         if self.handle:

@@ -213,6 +213,90 @@ __global__ void __launch_bounds__(TB) k_acm_resid(const double *__restrict__ U,
     for (int v = 0; v < NA; ++v) Re[v * ns] = -div[v] * A.inv_det;
 }
 
+// Dual time stepping of this system (Sec. 5): dU/dtau = R*(U) with the BDF
+// source on the velocity only, dU/dt = a U + B (BDF2: a = 3/(2 dt),
+// B = (-4 Un + Unm1)/(2 dt); BDF1: a = 1/dt, B = -Un/dt), classical RK4
+// pseudo-steps of a fixed size.
+__global__ void __launch_bounds__(TB) k_acm_bdf(const double *__restrict__ Un,
+                                                const double *__restrict__ Unm1,
+                                                double *__restrict__ B, double dt, int64_t n, int ns)
+{
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    const int v = (int)((i / ns) % NA);
+    B[i] = v == 0 ? 0.0 : (Unm1 ? (-4.0 * Un[i] + Unm1[i]) / (2.0 * dt) : -Un[i] / dt);
+}
+
+__device__ __forceinline__ double pseudo_k(const double *R, const double *S, const double *B,
+                                           double a, int64_t i, int ns)
+{
+    const int v = (int)((i / ns) % NA);
+    return v == 0 ? R[i] : R[i] - (a * S[i] + B[i]);
+}
+
+// RK4 stage s of dU/dtau = k*, k* the pseudo-residual of the state S that
+// produced R:  s = 0: acc = k/6, S' = U + dtau/2 k;  s = 1, 2: acc += k/3,
+// S' = U + c dtau k;  s = 3: U += dtau (acc + k/6).  S may be S' (one thread
+// per index).
+__global__ void __launch_bounds__(TB) k_acm_stage(double *__restrict__ U, const double *S,
+                                                  const double *__restrict__ R,
+                                                  const double *__restrict__ B,
+                                                  double *__restrict__ acc, double *Sn, double a,
+                                                  double dtau, int s, int64_t n, int ns)
+{
+    const int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x;
+    if (i >= n) return;
+    const double k = pseudo_k(R, S, B, a, i, ns);
+    if (s == 0) {
+        acc[i] = k / 6.0;
+        Sn[i] = U[i] + (0.5 * dtau) * k;
+    } else if (s < 3) {
+        acc[i] += k / 3.0;
+        Sn[i] = U[i] + ((s == 1 ? 0.5 : 1.0) * dtau) * k;
+    } else {
+        U[i] += dtau * (acc[i] + k / 6.0);
+    }
+}
+
+constexpr int NORM_BLOCKS = 1024;
+
+// sum over the velocity values of k*^2: per-block partials in a fixed order
+__global__ void __launch_bounds__(TB) k_acm_norm(const double *__restrict__ U,
+                                                 const double *__restrict__ R,
+                                                 const double *__restrict__ B, double a, int64_t n,
+                                                 int ns, double *__restrict__ part)
+{
+    __shared__ double sh[TB];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)NORM_BLOCKS * TB)
+        if ((i / ns) % NA) {
+            const double k = pseudo_k(R, U, B, a, i, ns);
+            acc += k * k;
+        }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(TB) k_acm_norm_final(const double *__restrict__ part,
+                                                       double *__restrict__ out)
+{
+    __shared__ double sh[TB];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < NORM_BLOCKS; i += TB) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 unsigned blocks_for(int64_t n) { return (unsigned)((n + TB - 1) / TB); }
 
 }  // namespace
@@ -222,6 +306,10 @@ struct fr_acm {
     fr_plan *plan = nullptr;
     fr::AcmArgs args;
     double *utr = nullptr, *Q = nullptr, *FI = nullptr;
+    // dual time stepping (allocated on its first call): residual, stage state,
+    // RK accumulator, BDF constant, norm partials and result, pinned read-back
+    double *R = nullptr, *S = nullptr, *acc = nullptr, *B = nullptr, *part = nullptr;
+    double *host = nullptr;
 };
 
 using namespace fr;
@@ -246,6 +334,52 @@ int launch_front(fr_acm *a, const double *U, hipStream_t s)
     hipLaunchKernelGGL(k_acm_grad, dim3(blocks_for(ne * ns)), dim3(TB), 0, s, U, a->utr, a->Q,
                        a->args, ne);
     return check_hip(hipGetLastError(), "k_acm_grad launch");
+}
+
+int launch_residual(fr_acm *a, const double *U, double *R, hipStream_t s)
+{
+    const int64_t ne = a->plan->ne;
+    const int m = a->args.m, nfp = m * m, ns = nfp * m;
+    if (int rc = launch_front(a, U, s)) return rc;
+    hipLaunchKernelGGL(k_acm_common, dim3(blocks_for(ne * 3 * nfp)), dim3(TB), 0, s, a->utr, a->Q,
+                       a->FI, a->args, ne);
+    if (int rc = check_hip(hipGetLastError(), "k_acm_common launch")) return rc;
+    hipLaunchKernelGGL(k_acm_resid, dim3(blocks_for(ne * ns)), dim3(TB), 0, s, U, a->Q, a->FI, R,
+                       a->args, ne);
+    return check_hip(hipGetLastError(), "k_acm_resid launch");
+}
+
+int ensure_dual(fr_acm *a)
+{
+    if (a->R) return FR_OK;
+    const size_t n = (size_t)a->plan->ne * NA * a->args.m * a->args.m * a->args.m;
+    double **bufs[4] = {&a->R, &a->S, &a->acc, &a->B};
+    for (double **b : bufs)
+        if (int rc = check_hip(hipMalloc((void **)b, n * sizeof(double)), "hipMalloc(acm dual)")) return rc;
+    if (int rc = check_hip(hipMalloc((void **)&a->part, (NORM_BLOCKS + 1) * sizeof(double)),
+                           "hipMalloc(acm norm)"))
+        return rc;
+    return check_hip(hipHostMalloc((void **)&a->host, sizeof(double), hipHostMallocDefault),
+                     "hipHostMalloc(acm norm)");
+}
+
+// RMS of the velocity part of k* = R - M_V (a U + B), read back (synchronises s)
+int velocity_rms(fr_acm *a, const double *U, double a_bdf, double *out, hipStream_t s)
+{
+    const int64_t n = a->plan->ne * NA * a->args.m * a->args.m * a->args.m;
+    const int ns = a->args.m * a->args.m * a->args.m;
+    hipLaunchKernelGGL(k_acm_norm, dim3(NORM_BLOCKS), dim3(TB), 0, s, U, a->R, a->B, a_bdf, n, ns,
+                       a->part);
+    if (int rc = check_hip(hipGetLastError(), "k_acm_norm launch")) return rc;
+    hipLaunchKernelGGL(k_acm_norm_final, dim3(1), dim3(TB), 0, s, a->part, a->part + NORM_BLOCKS);
+    if (int rc = check_hip(hipGetLastError(), "k_acm_norm_final launch")) return rc;
+    if (int rc = check_hip(hipMemcpyAsync(a->host, a->part + NORM_BLOCKS, sizeof(double),
+                                          hipMemcpyDeviceToHost, s),
+                           "hipMemcpyAsync(acm norm)"))
+        return rc;
+    if (int rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize(acm norm)")) return rc;
+    *out = std::sqrt(*a->host / (3.0 * (double)a->plan->ne * ns));
+    return FR_OK;
 }
 
 }  // namespace
@@ -307,16 +441,54 @@ int fr_acm_gradient(fr_acm *a, const double *U, double *Q, fr_stream_t sv)
 int fr_acm_residual(fr_acm *a, const double *U, double *R, fr_stream_t sv)
 {
     if (int rc = acm_check(a, U, R, "fr_acm_residual")) return rc;
+    return launch_residual(a, U, R, (hipStream_t)sv);
+}
+
+int fr_acm_dual_step(fr_acm *a, double *U, const double *Un, const double *Unm1, double dt,
+                     double dtau, double tol, int max_iters, int check_every, int *iters,
+                     double *resid, fr_stream_t sv)
+{
+    if (!a || !U || !Un || !iters || !resid)
+        return set_error(FR_EINVAL, "fr_acm_dual_step: NULL argument");
+    if (U == Un || U == Unm1) return set_error(FR_EINVAL, "fr_acm_dual_step: U aliases a past state");
+    if (!(dt > 0.0) || !(dtau > 0.0) || !(tol > 0.0) || max_iters < 0 || check_every < 1)
+        return set_error(FR_EINVAL, "fr_acm_dual_step: dt=%g dtau=%g tol=%g max_iters=%d check_every=%d",
+                         dt, dtau, tol, max_iters, check_every);
+    if (((uintptr_t)U | (uintptr_t)Un | (uintptr_t)Unm1) & 7)
+        return set_error(FR_EINVAL, "fr_acm_dual_step: unaligned state");
+    *iters = 0;
+    *resid = NAN;
+    if (int rc = ensure_dual(a)) return rc;
     hipStream_t s = (hipStream_t)sv;
-    const int64_t ne = a->plan->ne;
-    const int m = a->args.m, nfp = m * m, ns = nfp * m;
-    if (int rc = launch_front(a, U, s)) return rc;
-    hipLaunchKernelGGL(k_acm_common, dim3(blocks_for(ne * 3 * nfp)), dim3(TB), 0, s, a->utr, a->Q,
-                       a->FI, a->args, ne);
-    if (int rc = check_hip(hipGetLastError(), "k_acm_common launch")) return rc;
-    hipLaunchKernelGGL(k_acm_resid, dim3(blocks_for(ne * ns)), dim3(TB), 0, s, U, a->Q, a->FI, R,
-                       a->args, ne);
-    return check_hip(hipGetLastError(), "k_acm_resid launch");
+    const int ns = a->args.m * a->args.m * a->args.m;
+    const int64_t n = a->plan->ne * NA * ns;
+    const unsigned g = blocks_for(n);
+    const double ab = Unm1 ? 1.5 / dt : 1.0 / dt;
+    hipLaunchKernelGGL(k_acm_bdf, dim3(g), dim3(TB), 0, s, Un, Unm1, a->B, dt, n, ns);
+    if (int rc = check_hip(hipGetLastError(), "k_acm_bdf launch")) return rc;
+    int it = 0;
+    double res = NAN;
+    for (;;) {
+        if (int rc = launch_residual(a, U, a->R, s)) return rc;
+        if (it % check_every == 0 || it >= max_iters) {
+            if (int rc = velocity_rms(a, U, ab, &res, s)) return rc;
+            *iters = it;
+            *resid = res;
+            if (!std::isfinite(res))
+                return set_error(FR_ENONFINITE, "pseudo-residual norm is %g after %d steps", res, it);
+            if (res < tol) return FR_OK;
+        }
+        if (it >= max_iters) break;
+        for (int st = 0; st < 4; ++st) {
+            if (st > 0)
+                if (int rc = launch_residual(a, a->S, a->R, s)) return rc;
+            hipLaunchKernelGGL(k_acm_stage, dim3(g), dim3(TB), 0, s, U, st == 0 ? U : a->S, a->R,
+                               a->B, a->acc, a->S, ab, dtau, st, n, ns);
+            if (int rc = check_hip(hipGetLastError(), "k_acm_stage launch")) return rc;
+        }
+        ++it;
+    }
+    return set_error(FR_ENOCONV, "no convergence in %d pseudo-steps (residual %g)", it, res);
 }
 
 void fr_acm_destroy(fr_acm *a)
@@ -325,6 +497,10 @@ void fr_acm_destroy(fr_acm *a)
     if (a->utr) (void)hipFree(a->utr);
     if (a->Q) (void)hipFree(a->Q);
     if (a->FI) (void)hipFree(a->FI);
+    double *bufs[5] = {a->R, a->S, a->acc, a->B, a->part};
+    for (double *b : bufs)
+        if (b) (void)hipFree(b);
+    if (a->host) (void)hipHostFree(a->host);
     delete a;
 }
 

@@ -116,3 +116,61 @@ def test_errors():
         acm.residual(U, torch.zeros(acm.state_len + 1, dtype=torch.float64, device="cuda"))
     acm.close()
     plan.close()
+
+
+def dual_case(p, n, seed):
+    from paper_2107_14027_amd import inputs
+    import oracle
+    Unm1 = inputs.tgv(p, n, noise=1e-4, seed=seed)
+    Un = oracle.rk4(p, n, Unm1, ZETA, 1.0 / 1600.0, T_CFG, 2.5e-3, 4)
+    sel = lambda X: np.ascontiguousarray(np.asarray(X).reshape(-1, 13, (p + 1) ** 3)[:, :4])
+    return sel(2 * Un - Unm1), sel(Un), sel(Unm1)
+
+
+@pytest.mark.parametrize("p,n,bdf2,tol,maxit,check", [(3, (2, 3, 2), True, 1e-30, 6, 1),
+                                                      (2, (3, 2, 2), False, 1e-30, 5, 2),
+                                                      (3, (2, 2, 2), True, 1.2e-3, 400, 1),
+                                                      (4, (2, 2, 2), True, 1e-30, 3, 1)])
+def test_dual_step_matches_oracle(p, n, bdf2, tol, maxit, check):
+    import torch
+    G, Un, Unm1 = dual_case(p, n, 3 + p)
+    Um = Unm1 if bdf2 else None
+    say("acm dual p=%d n=%s bdf2=%s tol=%g" % (p, n, bdf2, tol))
+    plan = B.Plan(p, n, ZETA, 1.0 / 1600.0, T_CFG)
+    acm = B.Acm(plan)
+    U = torch.from_numpy(G.copy()).to("cuda")
+    rc, it, res = acm.dual_step(U, torch.from_numpy(Un).to("cuda"),
+                                None if Um is None else torch.from_numpy(Um).to("cuda"),
+                                1e-2, 1e-3, tol, maxit, check_every=check, raise_on_error=False)
+    torch.cuda.synchronize()
+    Ug = U.cpu().numpy()
+    acm.close()
+    plan.close()
+    Uo, ito, reso, rco = A.dual_step(p, n, G, Un, Um, ZETA, 1.0 / 1600.0, 1e-2, 1e-3, tol, maxit)
+    if tol > 1e-20:
+        assert rc == B.FR_OK and rco == 0 and abs(it - ito) <= 1
+        if it != ito:
+            return
+    else:
+        assert rc == B.FR_ENOCONV and rco == -5 and it == ito == maxit
+    assert rel(Ug, Uo) <= 1e-11
+    assert rel(Ug - G, Uo - G) <= 1e-9
+    assert abs(res - reso) <= 1e-9 * reso
+
+
+def test_dual_step_errors():
+    import torch
+    plan = B.Plan(2, (2, 2, 2), ZETA, NU_V, T_CFG)
+    acm = B.Acm(plan)
+    U = torch.zeros(acm.state_len, dtype=torch.float64, device="cuda")
+    V = torch.zeros_like(U)
+    for args in ((U, U, None, 1e-2, 1e-3, 1e-3, 3), (U, V, None, -1.0, 1e-3, 1e-3, 3),
+                 (U, V, None, 1e-2, 1e-3, 1e-3, -1)):
+        with pytest.raises(B.FrError):
+            acm.dual_step(*args)
+    bad = torch.zeros_like(U)
+    bad[7] = float("nan")
+    rc, it, res = acm.dual_step(bad, V, None, 1e-2, 1e-3, 1e-3, 3, raise_on_error=False)
+    assert rc == B.FR_ENONFINITE
+    acm.close()
+    plan.close()

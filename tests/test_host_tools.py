@@ -86,3 +86,9 @@ def test_new_entry_points_validate_arguments():
                               ctypes.byref(res), None) == B.FR_EINVAL
     out = (ctypes.c_double * 2)()
     assert L.fr_diagnostics(None, None, out, None) == B.FR_EINVAL
+    assert L.fr_acm_create(None, 0.5, 0.1) is None
+    L.fr_acm_destroy(None)
+    assert L.fr_acm_residual(None, None, None, None) == B.FR_EINVAL
+    assert L.fr_acm_gradient(None, None, None, None) == B.FR_EINVAL
+    assert L.fr_acm_dual_step(None, None, None, None, 1e-2, 1e-3, 1e-6, 3, 1, ctypes.byref(it),
+                              ctypes.byref(res), None) == B.FR_EINVAL
