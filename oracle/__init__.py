@@ -33,6 +33,9 @@ Pin status (tests/test_oracle_*.py):
                                                  one-sided gradient at beta = 1/2)
   acm_ldg.dual_step                              pinned (equals the ACM-HD dual step on P, V
                                                  at nu = tau = 0: states, norms, iterations)
+  linear_hex.residual (linear_hex.py)            pinned (affine corners = constant-Jacobian
+                                                 residual, free stream on distorted meshes,
+                                                 conservation, smooth-field convergence)
 """
 import ctypes
 import os

@@ -15,6 +15,8 @@ Fields (Sec. 5 of the paper defines the Taylor-Green vortex on [0, 2 pi]^3):
             P = P0 + (1/16)(cos 2x + cos 2y)(cos 2z + 2), aux = exact gradients
   fourier   random Fourier velocity and pressure, |k|_2 <= kmax, unit RMS
   sines     P = u = v = w = sin x sin y sin z, aux = exact gradients
+Meshes of linear hexahedra (corner lists, seeded vertex displacements) come
+from linear_hex_corners.
 """
 import numpy as np
 
@@ -174,3 +176,47 @@ def nu_T_from_length(Re, Lr):
     """nu = 1/Re; relaxation time T = Lr^2 / nu for a relaxation length Lr."""
     nu = 1.0 / Re
     return nu, Lr * Lr / nu
+
+
+def linear_hex_corners(n, amp=0.0, seed=0, smooth=0.0):
+    """Corner coordinates C[e][8][3] of a periodic lattice of linear hexahedra
+    filling [0, 2 pi]^3 (corner c = c0 + 2 c1 + 4 c2, c_d = 0 at xi_d = -1).
+    Vertex (i, j, k) sits at 2 pi (i/nx, j/ny, k/nz) moved by
+      amp * h * uniform(-1, 1)^3            (seeded, periodic in the vertex lattice)
+      + smooth * (sin y sin z, sin z sin x, sin x sin y)   at the undisplaced position,
+    h the smallest element width.  Each element stores its own corners, with
+    2 pi added across the periodic seam, so elements sharing a face store the
+    same face up to that shift."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    h = 2 * np.pi / max(n)
+    disp = amp * h * rng.uniform(-1.0, 1.0, size=(nz, ny, nx, 3))
+    e = np.arange(nx * ny * nz)
+    ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+    C = np.empty((len(e), 8, 3))
+    for c in range(8):
+        cx, cy, cz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+        ix, iy, iz = ex + cx, ey + cy, ez + cz
+        X = np.stack([2 * np.pi * ix / nx, 2 * np.pi * iy / ny, 2 * np.pi * iz / nz], axis=1)
+        X = X + disp[iz % nz, iy % ny, ix % nx]
+        x0, y0, z0 = (2 * np.pi * ix / nx, 2 * np.pi * iy / ny, 2 * np.pi * iz / nz)
+        X[:, 0] += smooth * np.sin(y0) * np.sin(z0)
+        X[:, 1] += smooth * np.sin(z0) * np.sin(x0)
+        X[:, 2] += smooth * np.sin(x0) * np.sin(y0)
+        C[:, c] = X
+    return C
+
+
+def linear_hex_points(p, C):
+    """Physical coordinates x[e][3][m^3] of the solution points of linear
+    hexahedra with corners C[e][8][3] (trilinear interpolation of the corners)."""
+    m = p + 1
+    xg, _ = nodes(p)
+    q = np.arange(m ** 3)
+    xi = np.stack([xg[q % m], xg[(q // m) % m], xg[q // (m * m)]], axis=1)   # [m^3][3]
+    out = np.zeros((C.shape[0], 3, m ** 3))
+    for c in range(8):
+        s = np.array([2 * (c & 1) - 1, 2 * ((c >> 1) & 1) - 1, 2 * ((c >> 2) & 1) - 1])
+        N = np.prod(0.5 * (1 + s[None, :] * xi), axis=1)                       # [m^3]
+        out += C[:, c, :, None] * N[None, None, :]
+    return out
