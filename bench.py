@@ -213,6 +213,38 @@ def time_acm(p=4, N=51, reps=10):
             "acm_ldg_over_acm_hd_time": round(ms / hd, 3)}
 
 
+def time_lhex(p=4, N=51, reps=10):
+    """ACM-HD residual on linear hexahedra (corners only, metric evaluated in
+    the kernels) on a randomly distorted p, N^3 mesh, FP64: ms per residual by
+    HIP events on the launch stream, with the sweep's Fourier state."""
+    import torch
+    from paper_2107_14027_amd import binding as B
+    from paper_2107_14027_amd import inputs
+    n = (N, N, N)
+    plan = B.Plan(p, n, ZETA, NU, TRELAX)
+    lh = B.LinearHex(plan)
+    C = torch.tensor(inputs.linear_hex_corners(n, amp=0.2, seed=7, smooth=0.1), device="cuda")
+    U = inputs.fourier(p, n, seed=1000 + p, device="cuda")
+    R = torch.empty_like(U)
+    lh.residual(C, U, R)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lh.residual(C, U, R)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    lh.close()
+    plan.close()
+    del U, R, C
+    torch.cuda.empty_cache()
+    npts = N ** 3 * (p + 1) ** 3
+    return {"workload": "one ACM-HD residual on a distorted mesh of linear hexahedra, p=%d on %d^3 "
+                        "(%d solution points), FP64" % (p, N, npts),
+            "residual_ms": round(ms, 3), "GDOF_per_s": round(npts * NV / ms / 1e6, 2)}
+
+
 def compare_dual(p=3, N=32, dt=1e-2, dtaus=(2e-3, 8e-3), tol=1e-4, max_iters=400):
     """One BDF1 physical step of the Taylor-Green vortex (Re 1600, zeta = 2.5,
     T = 5e-3, FP64) from its initial state by classical RK4 pseudo-steps of a
@@ -321,7 +353,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-guess study (pseudo-iterations per physical step)")
     ap.add_argument("--no-acm", action="store_true",
-                    help="skip the standard ACM (LDG) residual timing beside ACM-HD")
+                    help="skip the comparison-system timings: standard ACM (LDG) beside ACM-HD, "
+                         "and ACM-HD on linear hexahedra")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -463,11 +496,13 @@ def main():
         timestep = time_steps()
         log("time steps: %s" % timestep)
 
-    acm = None
+    acm = lhex = None
     if not args.no_acm:
         acm = time_acm()
         acm["dual_step"] = compare_dual()
         log("standard ACM: %s" % acm)
+        lhex = time_lhex()
+        log("linear hexahedra: %s" % lhex)
 
     learned = None
     if not args.no_learned:
@@ -547,6 +582,7 @@ def main():
         "cpu_baseline": cpu,
         "time_step": timestep,
         "standard_acm_ldg": acm,
+        "linear_hexahedra": lhex,
         "learned_guess": learned,
         "sweep": sweep,
         "kernel_ms": {str(p): {"trace": round(kstats[p]["trace_ms"], 4),

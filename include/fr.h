@@ -279,6 +279,40 @@ int fr_acm_dual_step(fr_acm *a, double *U, const double *Un, const double *Unm1,
 void fr_acm_destroy(fr_acm *a);
 
 /*
+ * Linear hexahedra: the ACM-HD residual (as fr_residual, double precision) on
+ * elements whose Jacobian varies inside the element, which the paper leaves
+ * as future work, noting that linear elements need only their corners
+ * (Sec. 6).  Element e is the trilinear image of [-1, 1]^3 with corners
+ * corners[e][c][0..2], c = c0 + 2 c1 + 4 c2 (c_d = 0 at xi_d = -1); the
+ * metric rows S_d = det J J^{-T} e_d and det J are evaluated from the corners
+ * wherever they are needed (nothing per point is stored).  Elements keep the
+ * plan's lattice connectivity (neighbours along +-xi_d, periodic) and must be
+ * conforming: the plus face of an element and the minus face of its
+ * neighbour are the same quadrilateral (a periodic shift of it is allowed:
+ * only tangents enter).  The common flux on a face is evaluated once, with
+ * the minus-side element's metric.  det J must be positive at every solution
+ * point (not checked).  With affine corners the result is fr_residual's.
+ *
+ * fr_lhex_create -- bind to the plan (borrowed; its order, lattice, zeta, nu
+ * and T are used, its Jacobian, precision and variant are not) and allocate
+ * the face traces (78 m^2 doubles per element) and common fluxes (39 m^2) on
+ * the current device.  Returns NULL on error.
+ */
+typedef struct fr_lhex fr_lhex;
+fr_lhex *fr_lhex_create(fr_plan *plan);
+
+/*
+ * fr_lhex_residual -- R = -div F + S(U) of the device state U[ne][13][m^3]
+ * (double) on the elements described by the device array corners[ne][8][3]
+ * (double).  8-byte aligned; R may not alias U.  Asynchronous on s; calls
+ * that overlap on one object race on its intermediates.
+ */
+int fr_lhex_residual(fr_lhex *h, const double *corners, const double *U, double *R, fr_stream_t s);
+
+/* Release the intermediates (waits for the device). */
+void fr_lhex_destroy(fr_lhex *h);
+
+/*
  * fr_diagnostics -- flow diagnostics of a double state U (Sec. 5 follows the
  * Taylor-Green run through them):
  *   out[0] = kinetic energy  (1/|Omega|) int |V|^2 / 2 dx

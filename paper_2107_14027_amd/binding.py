@@ -26,7 +26,7 @@ EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_des
             "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess",
             "fr_pmg_create", "fr_pmg_dual_step", "fr_pmg_destroy", "fr_diagnostics",
             "fr_acm_create", "fr_acm_residual", "fr_acm_gradient", "fr_acm_dual_step",
-            "fr_acm_destroy")
+            "fr_acm_destroy", "fr_lhex_create", "fr_lhex_residual", "fr_lhex_destroy")
 
 
 class FrError(RuntimeError):
@@ -87,13 +87,18 @@ def lib():
         L.fr_acm_residual.argtypes = [_vp, _vp, _vp, _vp]
         L.fr_acm_gradient.argtypes = [_vp, _vp, _vp, _vp]
         L.fr_acm_dual_step.argtypes = [_vp, _vp, _vp, _vp, D, D, D, I, I, ctypes.POINTER(I), _dp, _vp]
+        L.fr_lhex_create.argtypes = [_vp]
+        L.fr_lhex_create.restype = _vp
+        L.fr_lhex_residual.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.fr_lhex_destroy.argtypes = [_vp]
+        L.fr_lhex_destroy.restype = None
         L.fr_acm_destroy.argtypes = [_vp]
         L.fr_acm_destroy.restype = None
         for n in ("fr_plan_set_int", "fr_plan_get_int", "fr_residual", "fr_rk_step", "fr_pmg_dual_step", "fr_diagnostics",
                   "fr_dual_step", "fr_guess_extrap", "fr_plan_operators", "fr_plan_kernel_stats",
                   "fr_mlp_init", "fr_mlp_sample", "fr_mlp_fit_norm", "fr_mlp_forward",
                   "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess", "fr_acm_residual",
-                  "fr_acm_gradient", "fr_acm_dual_step"):
+                  "fr_acm_gradient", "fr_acm_dual_step", "fr_lhex_residual"):
             getattr(L, n).restype = I
         _lib = L
     return _lib
@@ -390,6 +395,36 @@ def fr_plan_operators(p):
         r[name] = out[o:o + size].reshape(shape)
         o += size
     return r
+
+
+class LinearHex:
+    """Owning wrapper around an fr_lhex handle: the ACM-HD residual on linear
+    hexahedra given by their corners (the plan must stay open)."""
+
+    def __init__(self, plan):
+        self.plan = plan
+        self.handle = lib().fr_lhex_create(plan.handle)
+        if not self.handle:
+            raise FrError(FR_EINVAL, lib().fr_last_error().decode())
+
+    def residual(self, corners, U, R, stream=None):
+        import torch
+        n = self.plan.state_len
+        ne = n // NV // (self.plan.p + 1) ** 3
+        return _check(lib().fr_lhex_residual(self.handle, _dev(corners, torch.float64, ne * 24, "corners"),
+                                             _dev(U, torch.float64, n, "U"), _dev(R, torch.float64, n, "R"),
+                                             _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().fr_lhex_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Acm:

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfr.so")
-SOURCES = ["plan.cpp", "capi.cpp", "fused.hip", "unfused.hip", "timeint.hip", "mlp.hip", "pmg.hip", "diag.hip", "acm.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "fused.hip", "unfused.hip", "timeint.hip", "mlp.hip", "pmg.hip", "diag.hip", "acm.hip", "linhex.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",

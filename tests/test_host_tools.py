@@ -92,3 +92,6 @@ def test_new_entry_points_validate_arguments():
     assert L.fr_acm_gradient(None, None, None, None) == B.FR_EINVAL
     assert L.fr_acm_dual_step(None, None, None, None, 1e-2, 1e-3, 1e-6, 3, 1, ctypes.byref(it),
                               ctypes.byref(res), None) == B.FR_EINVAL
+    assert L.fr_lhex_create(None) is None
+    L.fr_lhex_destroy(None)
+    assert L.fr_lhex_residual(None, None, None, None, None) == B.FR_EINVAL
