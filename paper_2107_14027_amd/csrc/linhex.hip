@@ -12,7 +12,8 @@
 //   partially corrected operator, the common flux |S_d| F^I(n_hat = S_d/|S_d|)
 //   at every face point (once per interface, from the minus-side element's
 //   metric), R = -div / det J + S(U).
-// Three plain kernels, one thread per output value, double precision:
+// Three kernels, double precision, one thread per output value (the residual
+// kernel stages the transformed flux of its elements in LDS):
 //   k_lh_trace   U -> face traces of the 13 variables   utr[e][6][13][m^2]
 //   k_lh_common  corners, utr -> |S| F^I               FI[e][3][13][m^2]  (plus faces)
 //   k_lh_resid   corners, U, FI -> R
@@ -147,49 +148,63 @@ __global__ void __launch_bounds__(TB) k_lh_common(const double *__restrict__ cor
     }
 }
 
-__global__ void __launch_bounds__(TB) k_lh_resid(const double *__restrict__ corners,
-                                                 const double *__restrict__ U,
-                                                 const double *__restrict__ FI,
-                                                 double *__restrict__ R, LhArgs A, int64_t ne)
+// Residual: a workgroup holds `epb` elements, one thread per solution point.
+// Each thread evaluates the metric at its own point once; per direction d it
+// writes its transformed flux F . S_d to LDS, and after a barrier contracts
+// the partially corrected operator along its d-line from LDS, so the flux is
+// evaluated three times per point rather than on every point of three lines.
+constexpr int RES_TB = 384;
+
+__global__ void __launch_bounds__(RES_TB) k_lh_resid(const double *__restrict__ corners,
+                                                     const double *__restrict__ U,
+                                                     const double *__restrict__ FI,
+                                                     double *__restrict__ R, LhArgs A, int64_t ne,
+                                                     int epb)
 {
+    extern __shared__ double lds[];   // [epb][13][m^3]
     const int m = A.m, nfp = m * m, ns = nfp * m;
-    const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (t >= ne * ns) return;
-    const int q = (int)(t % ns);
-    const int64_t e = t / ns;
+    const int el = threadIdx.x / ns, q = threadIdx.x % ns;
+    const int64_t e = (int64_t)blockIdx.x * epb + el;
+    const bool on = el < epb && e < ne;
     const int pi[3] = {q % m, (q / m) % m, q / nfp};
-    double bc[8][3];
-    trilinear(corners + e * 24, bc);
-    const double *Ue = U + e * NV * ns;
-    double div[NV];
+    double S[3][3], det = 1.0, Up[NV], div[NV];
     for (int v = 0; v < NV; ++v) div[v] = 0.0;
-    for (int d = 0; d < 3; ++d) {
-        const int l0 = pi[d];
-        const int a = d == 0 ? pi[1] : pi[0], b = d == 2 ? pi[1] : pi[2];
-        for (int l = 0; l < m; ++l) {
-            int ix[3] = {pi[0], pi[1], pi[2]};
-            ix[d] = l;
-            const int pt = ix[0] + m * (ix[1] + m * ix[2]);
-            double S[3];
-            metric_row(bc, A.x[ix[0]], A.x[ix[1]], A.x[ix[2]], d, S, nullptr);
-            double Up[NV], F[NV];
-            for (int v = 0; v < NV; ++v) Up[v] = Ue[v * ns + pt];
-            dev::flux_dot<double>(Up, S, A.zeta, A.nu, A.invT, F);
-            const double w = A.Dt[l0 * m + l];
-            for (int v = 0; v < NV; ++v) div[v] += w * F[v];
-        }
-        const int ab = a + m * b;
-        const int64_t em = nbr_plus(A, e, d, -1);
-        const double *Fp = FI + (e * 3 + d) * NV * nfp + ab;
-        const double *Fm = FI + (em * 3 + d) * NV * nfp + ab;
-        for (int v = 0; v < NV; ++v) div[v] += A.gl[l0] * Fm[v * nfp] + A.gr[l0] * Fp[v * nfp];
+    if (on) {
+        double bc[8][3];
+        trilinear(corners + e * 24, bc);
+        for (int d = 0; d < 3; ++d)
+            metric_row(bc, A.x[pi[0]], A.x[pi[1]], A.x[pi[2]], d, S[d], d == 0 ? &det : nullptr);
+        for (int v = 0; v < NV; ++v) Up[v] = U[(e * NV + v) * ns + q];
     }
-    double S[3], det;
-    metric_row(bc, A.x[pi[0]], A.x[pi[1]], A.x[pi[2]], 0, S, &det);
+    double *F = lds + (size_t)el * NV * ns;
+    for (int d = 0; d < 3; ++d) {
+        if (on) {
+            double Fh[NV];
+            dev::flux_dot<double>(Up, S[d], A.zeta, A.nu, A.invT, Fh);
+            for (int v = 0; v < NV; ++v) F[v * ns + q] = Fh[v];
+        }
+        __syncthreads();
+        if (on) {
+            const int l0 = pi[d];
+            const int a = d == 0 ? pi[1] : pi[0], b = d == 2 ? pi[1] : pi[2];
+            for (int l = 0; l < m; ++l) {
+                const int pt = lpt(m, d, a, b, l);
+                const double w = A.Dt[l0 * m + l];
+                for (int v = 0; v < NV; ++v) div[v] += w * F[v * ns + pt];
+            }
+            const int ab = a + m * b;
+            const int64_t em = nbr_plus(A, e, d, -1);
+            const double *Fp = FI + (e * 3 + d) * NV * nfp + ab;
+            const double *Fm = FI + (em * 3 + d) * NV * nfp + ab;
+            for (int v = 0; v < NV; ++v) div[v] += A.gl[l0] * Fm[v * nfp] + A.gr[l0] * Fp[v * nfp];
+        }
+        __syncthreads();
+    }
+    if (!on) return;
     double *Re = R + e * NV * ns + q;
     for (int v = 0; v < NV; ++v) {
         double r = -div[v] / det;
-        if (v >= 4) r -= Ue[v * ns + q] * A.invT;
+        if (v >= 4) r -= Up[v] * A.invT;
         Re[v * ns] = r;
     }
 }
@@ -251,8 +266,13 @@ int fr_lhex_residual(fr_lhex *h, const double *corners, const double *U, double 
     hipLaunchKernelGGL(k_lh_common, dim3(blocks_of(ne * 3 * nfp)), dim3(TB), 0, s, corners, h->utr, h->FI,
                        h->args, ne);
     if (int rc = check_hip(hipGetLastError(), "k_lh_common launch")) return rc;
-    hipLaunchKernelGGL(k_lh_resid, dim3(blocks_of(ne * ns)), dim3(TB), 0, s, corners, U, h->FI, R, h->args,
-                       ne);
+    // elements per workgroup: as many whole elements as fit 256 threads (one if
+    // an element has more points), the block rounded up to whole waves
+    const int epb = ns >= 256 ? 1 : 256 / ns;
+    const int threads = (epb * ns + 63) / 64 * 64;
+    const size_t lds = (size_t)epb * NV * ns * sizeof(double);
+    hipLaunchKernelGGL(k_lh_resid, dim3((unsigned)((ne + epb - 1) / epb)), dim3(threads), lds, s, corners, U,
+                       h->FI, R, h->args, ne, epb);
     return check_hip(hipGetLastError(), "k_lh_resid launch");
 }
 
