@@ -12,8 +12,8 @@
 //   partially corrected operator, the common flux |S_d| F^I(n_hat = S_d/|S_d|)
 //   at every face point (once per interface, from the minus-side element's
 //   metric), R = -div / det J + S(U).
-// Three kernels, double precision, one thread per output value (the residual
-// kernel stages the transformed flux of its elements in LDS):
+// Three kernels, double precision (the trace kernel stages its elements'
+// states in LDS, the residual kernel their transformed fluxes):
 //   k_lh_trace   U -> face traces of the 13 variables   utr[e][6][13][m^2]
 //   k_lh_common  corners, utr -> |S| F^I               FI[e][3][13][m^2]  (plus faces)
 //   k_lh_resid   corners, U, FI -> R
@@ -89,22 +89,32 @@ __device__ __forceinline__ void metric_row(const double b[8][3], double x0, doub
     }
 }
 
+// Face traces: a workgroup loads the states of `epb` elements into LDS with
+// coalesced reads, then produces their traces in output order (consecutive
+// threads write consecutive values).
 __global__ void __launch_bounds__(TB) k_lh_trace(const double *__restrict__ U,
-                                                 double *__restrict__ utr, LhArgs A, int64_t ne)
+                                                 double *__restrict__ utr, LhArgs A, int64_t ne,
+                                                 int epb)
 {
+    extern __shared__ double lds[];   // [epb][13][m^3]
     const int m = A.m, nfp = m * m, ns = nfp * m;
-    const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (t >= ne * 6 * nfp) return;
-    const int ab = (int)(t % nfp);
-    const int f = (int)((t / nfp) % 6);
-    const int64_t e = t / (6 * nfp);
-    const int d = f >> 1, a = ab % m, b = ab / m;
-    const double *L = (f & 1) ? A.lp : A.lm;
-    const double *Ue = U + e * NV * ns;
-    for (int v = 0; v < NV; ++v) {
-        double s = 0.0;
-        for (int l = 0; l < m; ++l) s += L[l] * Ue[v * ns + lpt(m, d, a, b, l)];
-        utr[((e * 6 + f) * NV + v) * nfp + ab] = s;
+    const int64_t e0 = (int64_t)blockIdx.x * epb;
+    const int nel = (int)(ne - e0 < epb ? ne - e0 : epb);
+    const int nin = nel * NV * ns;
+    const double *Ub = U + e0 * NV * ns;
+    for (int i = threadIdx.x; i < nin; i += TB) lds[i] = Ub[i];
+    __syncthreads();
+    const int per = 6 * NV * nfp;
+    double *ob = utr + e0 * per;
+    for (int o = threadIdx.x; o < nel * per; o += TB) {
+        const int el = o / per, r = o % per;
+        const int f = r / (NV * nfp), v = (r / nfp) % NV, ab = r % nfp;
+        const int d = f >> 1, a = ab % m, b = ab / m;
+        const double *L = (f & 1) ? A.lp : A.lm;
+        const double *X = lds + (el * NV + v) * ns;
+        double acc = 0.0;
+        for (int l = 0; l < m; ++l) acc += L[l] * X[lpt(m, d, a, b, l)];
+        ob[o] = acc;
     }
 }
 
@@ -261,18 +271,20 @@ int fr_lhex_residual(fr_lhex *h, const double *corners, const double *U, double 
     hipStream_t s = (hipStream_t)sv;
     const int64_t ne = h->plan->ne;
     const int m = h->args.m, nfp = m * m, ns = nfp * m;
-    hipLaunchKernelGGL(k_lh_trace, dim3(blocks_of(ne * 6 * nfp)), dim3(TB), 0, s, U, h->utr, h->args, ne);
+    // elements per workgroup of the trace and residual kernels: as many whole
+    // elements as fit 256 threads (one if an element has more points)
+    const int epb = ns >= 256 ? 1 : 256 / ns;
+    const size_t lds = (size_t)epb * NV * ns * sizeof(double);
+    const unsigned groups = (unsigned)((ne + epb - 1) / epb);
+    hipLaunchKernelGGL(k_lh_trace, dim3(groups), dim3(TB), lds, s, U, h->utr, h->args, ne, epb);
     if (int rc = check_hip(hipGetLastError(), "k_lh_trace launch")) return rc;
     hipLaunchKernelGGL(k_lh_common, dim3(blocks_of(ne * 3 * nfp)), dim3(TB), 0, s, corners, h->utr, h->FI,
                        h->args, ne);
     if (int rc = check_hip(hipGetLastError(), "k_lh_common launch")) return rc;
-    // elements per workgroup: as many whole elements as fit 256 threads (one if
-    // an element has more points), the block rounded up to whole waves
-    const int epb = ns >= 256 ? 1 : 256 / ns;
+    // the residual kernel takes one thread per point, rounded up to whole waves
     const int threads = (epb * ns + 63) / 64 * 64;
-    const size_t lds = (size_t)epb * NV * ns * sizeof(double);
-    hipLaunchKernelGGL(k_lh_resid, dim3((unsigned)((ne + epb - 1) / epb)), dim3(threads), lds, s, corners, U,
-                       h->FI, R, h->args, ne, epb);
+    hipLaunchKernelGGL(k_lh_resid, dim3(groups), dim3(threads), lds, s, corners, U, h->FI, R, h->args, ne,
+                       epb);
     return check_hip(hipGetLastError(), "k_lh_resid launch");
 }
 
