@@ -11,9 +11,10 @@
 //   u^I   = (u_L + u_R)/2 + beta (u_L - u_R)
 //   F_v^I = (F_vL + F_vR).n/2 - beta (F_vL - F_vR).n + tau (u_L - u_R)   (velocity)
 //
-// Four plain kernels, one thread per output value, every intermediate through
-// HBM (this is the unfused multi-step pipeline that hyperbolised diffusion
-// removes):
+// Four kernels, one thread per output value, every intermediate through HBM
+// (this is the unfused multi-step pipeline that hyperbolised diffusion
+// removes); the gradient and residual kernels stage their elements' line data
+// in LDS:
 //   k_acm_trace   U -> face traces of P, V         utr[e][6][4][m^2]
 //   k_acm_grad    U, utr -> corrected gradient     Q[e][9][m^3]   (du_i/dx_j at 3 i + j)
 //   k_acm_common  utr, Q -> common normal flux     FI[e][3][4][m^2] (plus face of e)
@@ -85,17 +86,27 @@ __global__ void __launch_bounds__(TB) k_acm_trace(const double *__restrict__ U,
     }
 }
 
-__global__ void __launch_bounds__(TB) k_acm_grad(const double *__restrict__ U,
-                                                 const double *__restrict__ utr,
-                                                 double *__restrict__ Q, AcmArgs A, int64_t ne)
+// Workgroups of the gradient and residual kernels hold `epb` whole elements,
+// one thread per solution point (block rounded up to whole waves, at most
+// RES_TB threads); the element data they contract along lines sit in LDS.
+constexpr int RES_TB = 384;
+
+__global__ void __launch_bounds__(RES_TB) k_acm_grad(const double *__restrict__ U,
+                                                     const double *__restrict__ utr,
+                                                     double *__restrict__ Q, AcmArgs A, int64_t ne,
+                                                     int epb)
 {
+    extern __shared__ double lds[];   // [epb][3][m^3] velocity
     const int m = A.m, nfp = m * m, ns = nfp * m;
-    const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (t >= ne * ns) return;
-    const int q = (int)(t % ns);
-    const int64_t e = t / ns;
+    const int el = threadIdx.x / ns, q = threadIdx.x % ns;
+    const int64_t e = (int64_t)blockIdx.x * epb + el;
+    const bool on = el < epb && e < ne;
+    double *Vl = lds + (size_t)el * 3 * ns;
+    if (on)
+        for (int c = 0; c < 3; ++c) Vl[c * ns + q] = U[(e * NA + 1 + c) * ns + q];
+    __syncthreads();
+    if (!on) return;
     const int i = q % m, j = (q / m) % m, k = q / nfp;
-    const double *Ue = U + e * NA * ns;
     double g[3][3];  // g[c][d]: d/dxi_d of velocity component c
     for (int d = 0; d < 3; ++d) {
         int l0, a, b;
@@ -105,7 +116,7 @@ __global__ void __launch_bounds__(TB) k_acm_grad(const double *__restrict__ U,
         for (int c = 0; c < 3; ++c) {
             const int v = 1 + c;
             double s = 0.0;
-            for (int l = 0; l < m; ++l) s += A.D[l0 * m + l] * Ue[v * ns + line_pt(m, d, a, b, l)];
+            for (int l = 0; l < m; ++l) s += A.D[l0 * m + l] * Vl[c * ns + line_pt(m, d, a, b, l)];
             const double om = utr[((e * 6 + 2 * d) * NA + v) * nfp + ab];
             const double op = utr[((e * 6 + 2 * d + 1) * NA + v) * nfp + ab];
             const double nm = utr[((em * 6 + 2 * d + 1) * NA + v) * nfp + ab];  // e-1's plus face
@@ -171,44 +182,59 @@ __global__ void __launch_bounds__(TB) k_acm_common(const double *__restrict__ ut
     }
 }
 
-__global__ void __launch_bounds__(TB) k_acm_resid(const double *__restrict__ U,
-                                                  const double *__restrict__ Q,
-                                                  const double *__restrict__ FI,
-                                                  double *__restrict__ R, AcmArgs A, int64_t ne)
+// Residual: each thread forms the transformed flux (F . n_d, four values) at
+// its own point for one direction at a time, in LDS; after a barrier it
+// contracts the partially corrected operator along its d-line.
+__global__ void __launch_bounds__(RES_TB) k_acm_resid(const double *__restrict__ U,
+                                                      const double *__restrict__ Q,
+                                                      const double *__restrict__ FI,
+                                                      double *__restrict__ R, AcmArgs A, int64_t ne,
+                                                      int epb)
 {
+    extern __shared__ double lds[];   // [epb][4][m^3]
     const int m = A.m, nfp = m * m, ns = nfp * m;
-    const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (t >= ne * ns) return;
-    const int q = (int)(t % ns);
-    const int64_t e = t / ns;
+    const int el = threadIdx.x / ns, q = threadIdx.x % ns;
+    const int64_t e = (int64_t)blockIdx.x * epb + el;
+    const bool on = el < epb && e < ne;
     const int i = q % m, j = (q / m) % m, k = q / nfp;
-    const double *Ue = U + e * NA * ns;
-    const double *Qe = Q + e * 9 * ns;
+    double P = 0.0, V[3] = {0.0, 0.0, 0.0}, G[9];
+    if (on) {
+        P = U[e * NA * ns + q];
+        for (int c = 0; c < 3; ++c) V[c] = U[(e * NA + 1 + c) * ns + q];
+        for (int t = 0; t < 9; ++t) G[t] = Q[(e * 9 + t) * ns + q];
+    }
+    double *F = lds + (size_t)el * NA * ns;
     double div[NA] = {0.0, 0.0, 0.0, 0.0};
     for (int d = 0; d < 3; ++d) {
-        int l0, a, b;
-        line_of(d, i, j, k, l0, a, b);
-        const double *nv = A.nvec + 3 * d;
-        for (int l = 0; l < m; ++l) {
-            const int pt = line_pt(m, d, a, b, l);
-            const double w = A.Dt[l0 * m + l];
-            const double P = Ue[pt], V[3] = {Ue[ns + pt], Ue[2 * ns + pt], Ue[3 * ns + pt]};
+        if (on) {
+            const double *nv = A.nvec + 3 * d;
             const double vn = V[0] * nv[0] + V[1] * nv[1] + V[2] * nv[2];
-            div[0] += w * A.zeta * vn;
+            F[q] = A.zeta * vn;
             for (int c = 0; c < 3; ++c) {
                 // (V_c V + P e_c - nu grad u_c) . n_d
-                const double gn = Qe[(3 * c) * ns + pt] * nv[0] + Qe[(3 * c + 1) * ns + pt] * nv[1] +
-                                  Qe[(3 * c + 2) * ns + pt] * nv[2];
-                div[1 + c] += w * (V[c] * vn + P * nv[c] - A.nu * gn);
+                const double gn = G[3 * c] * nv[0] + G[3 * c + 1] * nv[1] + G[3 * c + 2] * nv[2];
+                F[(1 + c) * ns + q] = V[c] * vn + P * nv[c] - A.nu * gn;
             }
         }
-        const int ab = a + m * b;
-        const int64_t em = nbr(A, e, d, -1);
-        const double *Fp = FI + (e * 3 + d) * NA * nfp + ab;
-        const double *Fm = FI + (em * 3 + d) * NA * nfp + ab;
-        for (int v = 0; v < NA; ++v)
-            div[v] += A.nmag[d] * (A.gl[l0] * Fm[v * nfp] + A.gr[l0] * Fp[v * nfp]);
+        __syncthreads();
+        if (on) {
+            int l0, a, b;
+            line_of(d, i, j, k, l0, a, b);
+            for (int l = 0; l < m; ++l) {
+                const int pt = line_pt(m, d, a, b, l);
+                const double w = A.Dt[l0 * m + l];
+                for (int v = 0; v < NA; ++v) div[v] += w * F[v * ns + pt];
+            }
+            const int ab = a + m * b;
+            const int64_t em = nbr(A, e, d, -1);
+            const double *Fp = FI + (e * 3 + d) * NA * nfp + ab;
+            const double *Fm = FI + (em * 3 + d) * NA * nfp + ab;
+            for (int v = 0; v < NA; ++v)
+                div[v] += A.nmag[d] * (A.gl[l0] * Fm[v * nfp] + A.gr[l0] * Fp[v * nfp]);
+        }
+        __syncthreads();
     }
+    if (!on) return;
     double *Re = R + e * NA * ns + q;
     for (int v = 0; v < NA; ++v) Re[v * ns] = -div[v] * A.inv_det;
 }
@@ -331,8 +357,9 @@ int launch_front(fr_acm *a, const double *U, hipStream_t s)
     hipLaunchKernelGGL(k_acm_trace, dim3(blocks_for(ne * 6 * nfp)), dim3(TB), 0, s, U, a->utr,
                        a->args, ne);
     if (int rc = check_hip(hipGetLastError(), "k_acm_trace launch")) return rc;
-    hipLaunchKernelGGL(k_acm_grad, dim3(blocks_for(ne * ns)), dim3(TB), 0, s, U, a->utr, a->Q,
-                       a->args, ne);
+    const int epb = ns >= 256 ? 1 : 256 / ns;
+    hipLaunchKernelGGL(k_acm_grad, dim3((unsigned)((ne + epb - 1) / epb)), dim3((epb * ns + 63) / 64 * 64),
+                       (size_t)epb * 3 * ns * sizeof(double), s, U, a->utr, a->Q, a->args, ne, epb);
     return check_hip(hipGetLastError(), "k_acm_grad launch");
 }
 
@@ -344,8 +371,9 @@ int launch_residual(fr_acm *a, const double *U, double *R, hipStream_t s)
     hipLaunchKernelGGL(k_acm_common, dim3(blocks_for(ne * 3 * nfp)), dim3(TB), 0, s, a->utr, a->Q,
                        a->FI, a->args, ne);
     if (int rc = check_hip(hipGetLastError(), "k_acm_common launch")) return rc;
-    hipLaunchKernelGGL(k_acm_resid, dim3(blocks_for(ne * ns)), dim3(TB), 0, s, U, a->Q, a->FI, R,
-                       a->args, ne);
+    const int epb = ns >= 256 ? 1 : 256 / ns;
+    hipLaunchKernelGGL(k_acm_resid, dim3((unsigned)((ne + epb - 1) / epb)), dim3((epb * ns + 63) / 64 * 64),
+                       (size_t)epb * NA * ns * sizeof(double), s, U, a->Q, a->FI, R, a->args, ne, epb);
     return check_hip(hipGetLastError(), "k_acm_resid launch");
 }
 
