@@ -377,18 +377,29 @@ int launch_residual(fr_acm *a, const double *U, double *R, hipStream_t s)
     return check_hip(hipGetLastError(), "k_acm_resid launch");
 }
 
+// Allocates the dual-stepping arrays all together: after a failure nothing is
+// kept, so a later call tries again from scratch.
 int ensure_dual(fr_acm *a)
 {
-    if (a->R) return FR_OK;
+    if (a->host) return FR_OK;
     const size_t n = (size_t)a->plan->ne * NA * a->args.m * a->args.m * a->args.m;
-    double **bufs[4] = {&a->R, &a->S, &a->acc, &a->B};
-    for (double **b : bufs)
-        if (int rc = check_hip(hipMalloc((void **)b, n * sizeof(double)), "hipMalloc(acm dual)")) return rc;
-    if (int rc = check_hip(hipMalloc((void **)&a->part, (NORM_BLOCKS + 1) * sizeof(double)),
-                           "hipMalloc(acm norm)"))
+    double *dev[5] = {};
+    double *host = nullptr;
+    const size_t sizes[5] = {n, n, n, n, NORM_BLOCKS + 1};
+    int rc = FR_OK;
+    for (int i = 0; i < 5 && rc == FR_OK; ++i)
+        rc = check_hip(hipMalloc((void **)&dev[i], sizes[i] * sizeof(double)), "hipMalloc(acm dual)");
+    if (rc == FR_OK)
+        rc = check_hip(hipHostMalloc((void **)&host, sizeof(double), hipHostMallocDefault),
+                       "hipHostMalloc(acm norm)");
+    if (rc != FR_OK) {
+        for (double *p : dev)
+            if (p) (void)hipFree(p);
         return rc;
-    return check_hip(hipHostMalloc((void **)&a->host, sizeof(double), hipHostMallocDefault),
-                     "hipHostMalloc(acm norm)");
+    }
+    a->R = dev[0], a->S = dev[1], a->acc = dev[2], a->B = dev[3], a->part = dev[4];
+    a->host = host;
+    return FR_OK;
 }
 
 // RMS of the velocity part of k* = R - M_V (a U + B), read back (synchronises s)
