@@ -92,12 +92,13 @@ __device__ __forceinline__ void metric_row(const double b[8][3], double x0, doub
 // Face traces: a workgroup loads the states of `epb` elements into LDS with
 // coalesced reads, then produces their traces in output order (consecutive
 // threads write consecutive values).
+template <int M>
 __global__ void __launch_bounds__(TB) k_lh_trace(const double *__restrict__ U,
                                                  double *__restrict__ utr, LhArgs A, int64_t ne,
                                                  int epb)
 {
     extern __shared__ double lds[];   // [epb][13][m^3]
-    const int m = A.m, nfp = m * m, ns = nfp * m;
+    constexpr int m = M, nfp = m * m, ns = nfp * m;
     const int64_t e0 = (int64_t)blockIdx.x * epb;
     const int nel = (int)(ne - e0 < epb ? ne - e0 : epb);
     const int nin = nel * NV * ns;
@@ -118,11 +119,12 @@ __global__ void __launch_bounds__(TB) k_lh_trace(const double *__restrict__ U,
     }
 }
 
+template <int M>
 __global__ void __launch_bounds__(TB) k_lh_common(const double *__restrict__ corners,
                                                   const double *__restrict__ utr,
                                                   double *__restrict__ FI, LhArgs A, int64_t ne)
 {
-    const int m = A.m, nfp = m * m;
+    constexpr int m = M, nfp = m * m;
     const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (t >= ne * 3 * nfp) return;
     const int ab = (int)(t % nfp);
@@ -165,6 +167,8 @@ __global__ void __launch_bounds__(TB) k_lh_common(const double *__restrict__ cor
 // evaluated three times per point rather than on every point of three lines.
 constexpr int RES_TB = 384;
 
+// (The order stays a run-time value here: unrolling the line loops for a
+// fixed order costs registers, 230 or more from p = 4 up, and spills at p = 5, 6.)
 __global__ void __launch_bounds__(RES_TB) k_lh_resid(const double *__restrict__ corners,
                                                      const double *__restrict__ U,
                                                      const double *__restrict__ FI,
@@ -232,6 +236,33 @@ struct fr_lhex {
 
 using namespace fr;
 
+namespace {
+
+// Launches for order M - 1: elements per workgroup of the trace and residual
+// kernels are as many whole elements as fit 256 threads (one if an element has
+// more points); the residual kernel takes one thread per point, rounded up to
+// whole waves.
+template <int M>
+int launch_lhex(fr_lhex *h, const double *corners, const double *U, double *R, hipStream_t s)
+{
+    constexpr int nfp = M * M, ns = nfp * M;
+    const int64_t ne = h->plan->ne;
+    const int epb = ns >= 256 ? 1 : 256 / ns;
+    const size_t lds = (size_t)epb * NV * ns * sizeof(double);
+    const unsigned groups = (unsigned)((ne + epb - 1) / epb);
+    hipLaunchKernelGGL(k_lh_trace<M>, dim3(groups), dim3(TB), lds, s, U, h->utr, h->args, ne, epb);
+    if (int rc = check_hip(hipGetLastError(), "k_lh_trace launch")) return rc;
+    hipLaunchKernelGGL(k_lh_common<M>, dim3(blocks_of(ne * 3 * nfp)), dim3(TB), 0, s, corners, h->utr,
+                       h->FI, h->args, ne);
+    if (int rc = check_hip(hipGetLastError(), "k_lh_common launch")) return rc;
+    const int threads = (epb * ns + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_lh_resid, dim3(groups), dim3(threads), lds, s, corners, U, h->FI, R, h->args,
+                       ne, epb);
+    return check_hip(hipGetLastError(), "k_lh_resid launch");
+}
+
+}  // namespace
+
 extern "C" {
 
 fr_lhex *fr_lhex_create(fr_plan *plan)
@@ -269,23 +300,15 @@ int fr_lhex_residual(fr_lhex *h, const double *corners, const double *U, double 
         return set_error(FR_EINVAL, "fr_lhex_residual: unaligned array");
     if (U == R) return set_error(FR_EINVAL, "fr_lhex_residual: R may not alias U");
     hipStream_t s = (hipStream_t)sv;
-    const int64_t ne = h->plan->ne;
-    const int m = h->args.m, nfp = m * m, ns = nfp * m;
-    // elements per workgroup of the trace and residual kernels: as many whole
-    // elements as fit 256 threads (one if an element has more points)
-    const int epb = ns >= 256 ? 1 : 256 / ns;
-    const size_t lds = (size_t)epb * NV * ns * sizeof(double);
-    const unsigned groups = (unsigned)((ne + epb - 1) / epb);
-    hipLaunchKernelGGL(k_lh_trace, dim3(groups), dim3(TB), lds, s, U, h->utr, h->args, ne, epb);
-    if (int rc = check_hip(hipGetLastError(), "k_lh_trace launch")) return rc;
-    hipLaunchKernelGGL(k_lh_common, dim3(blocks_of(ne * 3 * nfp)), dim3(TB), 0, s, corners, h->utr, h->FI,
-                       h->args, ne);
-    if (int rc = check_hip(hipGetLastError(), "k_lh_common launch")) return rc;
-    // the residual kernel takes one thread per point, rounded up to whole waves
-    const int threads = (epb * ns + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_lh_resid, dim3(groups), dim3(threads), lds, s, corners, U, h->FI, R, h->args, ne,
-                       epb);
-    return check_hip(hipGetLastError(), "k_lh_resid launch");
+    switch (h->args.m) {
+    case 2: return launch_lhex<2>(h, corners, U, R, s);
+    case 3: return launch_lhex<3>(h, corners, U, R, s);
+    case 4: return launch_lhex<4>(h, corners, U, R, s);
+    case 5: return launch_lhex<5>(h, corners, U, R, s);
+    case 6: return launch_lhex<6>(h, corners, U, R, s);
+    case 7: return launch_lhex<7>(h, corners, U, R, s);
+    default: return set_error(FR_EUNSUPPORTED, "fr_lhex_residual: order %d", h->args.m - 1);
+    }
 }
 
 void fr_lhex_destroy(fr_lhex *h)
