@@ -295,7 +295,7 @@ void fr_acm_destroy(fr_acm *a);
  *
  * fr_lhex_create -- bind to the plan (borrowed; its order, lattice, zeta, nu
  * and T are used, its Jacobian, precision and variant are not) and allocate
- * the face traces (78 m^2 doubles per element) and common fluxes (39 m^2) on
+ * the face traces (42 m^2 doubles per element) and common fluxes (39 m^2) on
  * the current device.  Returns NULL on error.
  */
 typedef struct fr_lhex fr_lhex;

@@ -14,7 +14,8 @@
 //   metric), R = -div / det J + S(U).
 // Three kernels, double precision (the trace kernel stages its elements'
 // states in LDS, the residual kernel their transformed fluxes):
-//   k_lh_trace   U -> face traces of the 13 variables   utr[e][6][13][m^2]
+//   k_lh_trace   corners, U -> face traces of P, V and (grad V) n_hat
+//                                                      utr[e][6][7][m^2]
 //   k_lh_common  corners, utr -> |S| F^I               FI[e][3][13][m^2]  (plus faces)
 //   k_lh_resid   corners, U, FI -> R
 #include <cmath>
@@ -89,11 +90,29 @@ __device__ __forceinline__ void metric_row(const double b[8][3], double x0, doub
     }
 }
 
+// unit normal n_hat = S_d / |S_d| and |S_d| at face point (a, b) of face f
+// (xi_d = -1 or +1; the normal points along +xi_d on both faces)
+__device__ __forceinline__ double face_normal(const double b[8][3], const LhArgs &A, int f, int a, int bb,
+                                              double nh[3])
+{
+    const int d = f >> 1;
+    const double xs = (f & 1) ? 1.0 : -1.0, xa = A.x[a], xb = A.x[bb];
+    const double x0 = d == 0 ? xs : xa, x1 = d == 0 ? xa : (d == 1 ? xs : xb), x2 = d == 2 ? xs : xb;
+    double S[3];
+    metric_row(b, x0, x1, x2, d, S, nullptr);
+    const double nmag = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+    nh[0] = S[0] / nmag, nh[1] = S[1] / nmag, nh[2] = S[2] / nmag;
+    return nmag;
+}
+
 // Face traces: a workgroup loads the states of `epb` elements into LDS with
-// coalesced reads, then produces their traces in output order (consecutive
-// threads write consecutive values).
+// coalesced reads; one thread per (element, face, face point) then writes the
+// 7 values the common flux needs, P, V and (grad V) n_hat, with n_hat from
+// the element's own corners (utr[e][f][7][m^2]; consecutive threads write
+// consecutive face points).
 template <int M>
-__global__ void __launch_bounds__(TB) k_lh_trace(const double *__restrict__ U,
+__global__ void __launch_bounds__(TB) k_lh_trace(const double *__restrict__ corners,
+                                                 const double *__restrict__ U,
                                                  double *__restrict__ utr, LhArgs A, int64_t ne,
                                                  int epb)
 {
@@ -105,20 +124,30 @@ __global__ void __launch_bounds__(TB) k_lh_trace(const double *__restrict__ U,
     const double *Ub = U + e0 * NV * ns;
     for (int i = threadIdx.x; i < nin; i += TB) lds[i] = Ub[i];
     __syncthreads();
-    const int per = 6 * NV * nfp;
-    double *ob = utr + e0 * per;
-    for (int o = threadIdx.x; o < nel * per; o += TB) {
-        const int el = o / per, r = o % per;
-        const int f = r / (NV * nfp), v = (r / nfp) % NV, ab = r % nfp;
+    for (int o = threadIdx.x; o < nel * 6 * nfp; o += TB) {
+        const int el = o / (6 * nfp), f = (o / nfp) % 6, ab = o % nfp;
         const int d = f >> 1, a = ab % m, b = ab / m;
+        double bc[8][3], nh[3];
+        trilinear(corners + (e0 + el) * 24, bc);
+        face_normal(bc, A, f, a, b, nh);
         const double *L = (f & 1) ? A.lp : A.lm;
-        const double *X = lds + (el * NV + v) * ns;
-        double acc = 0.0;
-        for (int l = 0; l < m; ++l) acc += L[l] * X[lpt(m, d, a, b, l)];
-        ob[o] = acc;
+        const double *X = lds + el * NV * ns;
+        double t[NV];
+        for (int v = 0; v < NV; ++v) {
+            double acc = 0.0;
+            for (int l = 0; l < m; ++l) acc += L[l] * X[v * ns + lpt(m, d, a, b, l)];
+            t[v] = acc;
+        }
+        double *out = utr + ((e0 + el) * 6 + f) * NTR * nfp + ab;
+        for (int c = 0; c < 4; ++c) out[c * nfp] = t[c];
+        for (int i = 0; i < 3; ++i)
+            out[(4 + i) * nfp] = t[4 + 3 * i] * nh[0] + t[5 + 3 * i] * nh[1] + t[6 + 3 * i] * nh[2];
     }
 }
 
+// Common flux at the plus faces: Rusanov on (P, V), mean of the two normal
+// fluxes for the auxiliary equations, from the 7-value traces, along the
+// minus-side element's normal, times |S_d|.
 template <int M>
 __global__ void __launch_bounds__(TB) k_lh_common(const double *__restrict__ corners,
                                                   const double *__restrict__ utr,
@@ -131,32 +160,26 @@ __global__ void __launch_bounds__(TB) k_lh_common(const double *__restrict__ cor
     const int d = (int)((t / nfp) % 3);
     const int64_t e = t / (3 * nfp);
     const int a = ab % m, b = ab / m;
-    double bc[8][3];
+    double bc[8][3], nh[3];
     trilinear(corners + e * 24, bc);
-    // plus face of e: xi_d = +1, tangential points (a, b) in increasing direction order
-    const double xa = A.x[a], xb = A.x[b];
-    const double x0 = d == 0 ? 1.0 : xa, x1 = d == 0 ? xa : (d == 1 ? 1.0 : xb), x2 = d == 2 ? 1.0 : xb;
-    double S[3];
-    metric_row(bc, x0, x1, x2, d, S, nullptr);
-    const double nmag = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
-    const double nh[3] = {S[0] / nmag, S[1] / nmag, S[2] / nmag};
+    const double nmag = face_normal(bc, A, 2 * d + 1, a, b, nh);
     const int64_t er = nbr_plus(A, e, d, +1);
-    double UL[NV], UR[NV];
-    for (int v = 0; v < NV; ++v) {
-        UL[v] = utr[((e * 6 + 2 * d + 1) * NV + v) * nfp + ab];
-        UR[v] = utr[((er * 6 + 2 * d) * NV + v) * nfp + ab];
+    double L[NTR], R[NTR];
+    for (int c = 0; c < NTR; ++c) {
+        L[c] = utr[((e * 6 + 2 * d + 1) * NTR + c) * nfp + ab];
+        R[c] = utr[((er * 6 + 2 * d) * NTR + c) * nfp + ab];
     }
-    double FL[NV], FR[NV];
-    dev::flux_dot<double>(UL, nh, A.zeta, A.nu, A.invT, FL);
-    dev::flux_dot<double>(UR, nh, A.zeta, A.nu, A.invT, FR);
-    const double vnL = UL[1] * nh[0] + UL[2] * nh[1] + UL[3] * nh[2];
-    const double vnR = UR[1] * nh[0] + UR[2] * nh[1] + UR[3] * nh[2];
+    const double vnL = L[1] * nh[0] + L[2] * nh[1] + L[3] * nh[2];
+    const double vnR = R[1] * nh[0] + R[2] * nh[1] + R[3] * nh[2];
     const double lam = fmax(fabs(vnL) + sqrt(vnL * vnL + A.zeta), fabs(vnR) + sqrt(vnR * vnR + A.zeta));
     double *out = FI + (e * 3 + d) * NV * nfp + ab;
-    for (int v = 0; v < NV; ++v) {
-        double F = 0.5 * (FL[v] + FR[v]);
-        if (v < 4) F -= 0.5 * lam * (UR[v] - UL[v]);
-        out[v * nfp] = nmag * F;
+    out[0] = nmag * (0.5 * A.zeta * (vnL + vnR) - 0.5 * lam * (R[0] - L[0]));
+    for (int i = 0; i < 3; ++i) {
+        const double fl = L[1 + i] * vnL + L[0] * nh[i] - A.nu * L[4 + i];
+        const double fr = R[1 + i] * vnR + R[0] * nh[i] - A.nu * R[4 + i];
+        out[(1 + i) * nfp] = nmag * (0.5 * (fl + fr) - 0.5 * lam * (R[1 + i] - L[1 + i]));
+        const double vm = -0.5 * A.invT * (L[1 + i] + R[1 + i]);
+        for (int k = 0; k < 3; ++k) out[(4 + 3 * i + k) * nfp] = nmag * (vm * nh[k]);
     }
 }
 
@@ -250,7 +273,7 @@ int launch_lhex(fr_lhex *h, const double *corners, const double *U, double *R, h
     const int epb = ns >= 256 ? 1 : 256 / ns;
     const size_t lds = (size_t)epb * NV * ns * sizeof(double);
     const unsigned groups = (unsigned)((ne + epb - 1) / epb);
-    hipLaunchKernelGGL(k_lh_trace<M>, dim3(groups), dim3(TB), lds, s, U, h->utr, h->args, ne, epb);
+    hipLaunchKernelGGL(k_lh_trace<M>, dim3(groups), dim3(TB), lds, s, corners, U, h->utr, h->args, ne, epb);
     if (int rc = check_hip(hipGetLastError(), "k_lh_trace launch")) return rc;
     hipLaunchKernelGGL(k_lh_common<M>, dim3(blocks_of(ne * 3 * nfp)), dim3(TB), 0, s, corners, h->utr,
                        h->FI, h->args, ne);
@@ -285,7 +308,7 @@ fr_lhex *fr_lhex_create(fr_plan *plan)
     A.nu = plan->nu;
     A.invT = 1.0 / plan->T;
     const size_t nfp = (size_t)m * m, ne = (size_t)plan->ne;
-    if (check_hip(hipMalloc((void **)&h->utr, ne * 6 * NV * nfp * sizeof(double)), "hipMalloc(lhex traces)") ||
+    if (check_hip(hipMalloc((void **)&h->utr, ne * 6 * NTR * nfp * sizeof(double)), "hipMalloc(lhex traces)") ||
         check_hip(hipMalloc((void **)&h->FI, ne * 3 * NV * nfp * sizeof(double)), "hipMalloc(lhex fluxes)")) {
         fr_lhex_destroy(h);
         return nullptr;
