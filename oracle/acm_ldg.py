@@ -11,7 +11,7 @@ with a common solution at the interfaces, then the FR divergence of the flux
 evaluated with that gradient.  Interface treatment (Sec. 5): Rusanov on the
 inviscid part (the same wave speed as for ACM-HD), LDG with parameters beta and
 tau on the viscous part.  Readings taken where the paper gives only the two
-numbers (listed in the design notes): at the interface between L (element on
+numbers: at the interface between L (element on
 the minus side of a face) and R (plus side), unit normal n along +xi_d,
 
     common solution        u^I = (u_L + u_R)/2 + beta (u_L - u_R)

@@ -4,7 +4,7 @@ Sec. 5 monitors the Taylor-Green run through the enstrophy
     eps(t) = (nu / |Omega|) int_Omega omega . omega dx,  omega = curl V,
 which in the incompressible limit equals the kinetic-energy dissipation rate,
 and through the kinetic energy (1 / |Omega|) int_Omega |V|^2 / 2 dx.
-Readings (listed in the design notes): the integrals are the Gauss quadrature
+Readings taken where the paper is silent: the integrals are the Gauss quadrature
 of the solution points (exact for the nodal polynomials' squares), and omega is
 formed from the auxiliary variables, which hyperbolised diffusion drives to
 the velocity gradient: omega = (s_y - r_z, q_z - s_x, r_x - q_y) with

@@ -22,7 +22,7 @@
  *   - physical time: Sec. 5 (BDF2 dual time stepping; the pseudo-time solver
  *     here is classical RK4 with a fixed pseudo step).
  *
- * Readings taken where the paper is silent (each is listed in the design doc):
+ * Readings taken where the paper is silent:
  *   - correction functions: the DG (right/left Radau) member,
  *       h_l = ((-1)^p / 2) (P_p - P_{p+1}),   h_r = (1/2)(P_p + P_{p+1}),
  *     which satisfies the endpoint conditions the paper states in Sec. 2.1;
@@ -34,8 +34,7 @@
  * v in [P, u, v, w, q_x, q_y, q_z, r_x, r_y, r_z, s_x, s_y, s_z] where
  * q = grad u, r = grad v, s = grad w.
  *
- * Pin status of every function is documented in the design doc and tested in
- * tests/test_oracle_*.py.
+ * Every function is pinned by tests/test_oracle_*.py.
  */
 #include <math.h>
 #include <stdint.h>

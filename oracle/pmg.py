@@ -5,8 +5,7 @@ its pseudo-time iterations with a P-multigrid cycle (Sec. 5 and its cycle figure
 [(4,1), (3,1), (2,1), (1,4), (2,1), (3,1), (4,7)] of (order, pseudo-steps),
 with the pseudo-step grown by a constant factor of 1.75 per level below the
 finest).  The paper gives the cycle and the factor only; the rest is the
-standard full-approximation-scheme (FAS) multigrid, read as follows (each
-reading is listed in the design notes):
+standard full-approximation-scheme (FAS) multigrid, read as follows:
 
   * level l solves dU/dtau = R*_l(U) + d_l with the BDF pseudo-residual
       R*_l(U) = R_l(U) - M_V (a U + B_l),  a = 3/(2 dt) (BDF2) or 1/dt (BDF1),

@@ -3,7 +3,7 @@ INFRASTRUCTURE ONLY (part of the oracle).
 
 Sec. 5 runs its pseudo-iterations with an embedded RK34 pair and locally
 adaptive pseudo-steps (citing earlier work for both); it prints neither the
-coefficients nor the controller.  Readings (listed in the design notes):
+coefficients nor the controller.  Readings taken here:
   * the pair is Kennedy, Carpenter and Lewis's four-stage, third-order,
     two-register scheme with an embedded second-order solution
     (RK3(2)4[2R+]C): stage i uses U + sum_{j < i-1} b_j h k_j + a_{i,i-1} h k_{i-1};
