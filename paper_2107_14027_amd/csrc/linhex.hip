@@ -190,8 +190,9 @@ __global__ void __launch_bounds__(TB) k_lh_common(const double *__restrict__ cor
 // evaluated three times per point rather than on every point of three lines.
 constexpr int RES_TB = 384;
 
-// (The order stays a run-time value here: unrolling the line loops for a
+// (Compiled per order with the line loop kept rolled: unrolling it for a
 // fixed order costs registers, 230 or more from p = 4 up, and spills at p = 5, 6.)
+template <int M>
 __global__ void __launch_bounds__(RES_TB) k_lh_resid(const double *__restrict__ corners,
                                                      const double *__restrict__ U,
                                                      const double *__restrict__ FI,
@@ -199,7 +200,7 @@ __global__ void __launch_bounds__(RES_TB) k_lh_resid(const double *__restrict__ 
                                                      int epb)
 {
     extern __shared__ double lds[];   // [epb][13][m^3]
-    const int m = A.m, nfp = m * m, ns = nfp * m;
+    constexpr int m = M, nfp = m * m, ns = nfp * m;
     const int el = threadIdx.x / ns, q = threadIdx.x % ns;
     const int64_t e = (int64_t)blockIdx.x * epb + el;
     const bool on = el < epb && e < ne;
@@ -224,6 +225,7 @@ __global__ void __launch_bounds__(RES_TB) k_lh_resid(const double *__restrict__ 
         if (on) {
             const int l0 = pi[d];
             const int a = d == 0 ? pi[1] : pi[0], b = d == 2 ? pi[1] : pi[2];
+#pragma unroll 1
             for (int l = 0; l < m; ++l) {
                 const int pt = lpt(m, d, a, b, l);
                 const double w = A.Dt[l0 * m + l];
@@ -279,7 +281,7 @@ int launch_lhex(fr_lhex *h, const double *corners, const double *U, double *R, h
                        h->FI, h->args, ne);
     if (int rc = check_hip(hipGetLastError(), "k_lh_common launch")) return rc;
     const int threads = (epb * ns + 63) / 64 * 64;
-    hipLaunchKernelGGL(k_lh_resid, dim3(groups), dim3(threads), lds, s, corners, U, h->FI, R, h->args,
+    hipLaunchKernelGGL(k_lh_resid<M>, dim3(groups), dim3(threads), lds, s, corners, U, h->FI, R, h->args,
                        ne, epb);
     return check_hip(hipGetLastError(), "k_lh_resid launch");
 }
