@@ -91,13 +91,14 @@ __global__ void __launch_bounds__(TB) k_acm_trace(const double *__restrict__ U,
 // RES_TB threads); the element data they contract along lines sit in LDS.
 constexpr int RES_TB = 384;
 
+template <int M>
 __global__ void __launch_bounds__(RES_TB) k_acm_grad(const double *__restrict__ U,
                                                      const double *__restrict__ utr,
                                                      double *__restrict__ Q, AcmArgs A, int64_t ne,
                                                      int epb)
 {
     extern __shared__ double lds[];   // [epb][3][m^3] velocity
-    const int m = A.m, nfp = m * m, ns = nfp * m;
+    constexpr int m = M, nfp = m * m, ns = nfp * m;
     const int el = threadIdx.x / ns, q = threadIdx.x % ns;
     const int64_t e = (int64_t)blockIdx.x * epb + el;
     const bool on = el < epb && e < ne;
@@ -116,6 +117,7 @@ __global__ void __launch_bounds__(RES_TB) k_acm_grad(const double *__restrict__ 
         for (int c = 0; c < 3; ++c) {
             const int v = 1 + c;
             double s = 0.0;
+#pragma unroll 1
             for (int l = 0; l < m; ++l) s += A.D[l0 * m + l] * Vl[c * ns + line_pt(m, d, a, b, l)];
             const double om = utr[((e * 6 + 2 * d) * NA + v) * nfp + ab];
             const double op = utr[((e * 6 + 2 * d + 1) * NA + v) * nfp + ab];
@@ -133,11 +135,12 @@ __global__ void __launch_bounds__(RES_TB) k_acm_grad(const double *__restrict__ 
                 A.Jinv[jx] * g[c][0] + A.Jinv[3 + jx] * g[c][1] + A.Jinv[6 + jx] * g[c][2];
 }
 
+template <int M>
 __global__ void __launch_bounds__(TB) k_acm_common(const double *__restrict__ utr,
                                                    const double *__restrict__ Q,
                                                    double *__restrict__ FI, AcmArgs A, int64_t ne)
 {
-    const int m = A.m, nfp = m * m, ns = nfp * m;
+    constexpr int m = M, nfp = m * m, ns = nfp * m;
     const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
     if (t >= ne * 3 * nfp) return;
     const int ab = (int)(t % nfp);
@@ -185,6 +188,7 @@ __global__ void __launch_bounds__(TB) k_acm_common(const double *__restrict__ ut
 // Residual: each thread forms the transformed flux (F . n_d, four values) at
 // its own point for one direction at a time, in LDS; after a barrier it
 // contracts the partially corrected operator along its d-line.
+template <int M>
 __global__ void __launch_bounds__(RES_TB) k_acm_resid(const double *__restrict__ U,
                                                       const double *__restrict__ Q,
                                                       const double *__restrict__ FI,
@@ -192,7 +196,7 @@ __global__ void __launch_bounds__(RES_TB) k_acm_resid(const double *__restrict__
                                                       int epb)
 {
     extern __shared__ double lds[];   // [epb][4][m^3]
-    const int m = A.m, nfp = m * m, ns = nfp * m;
+    constexpr int m = M, nfp = m * m, ns = nfp * m;
     const int el = threadIdx.x / ns, q = threadIdx.x % ns;
     const int64_t e = (int64_t)blockIdx.x * epb + el;
     const bool on = el < epb && e < ne;
@@ -220,6 +224,7 @@ __global__ void __launch_bounds__(RES_TB) k_acm_resid(const double *__restrict__
         if (on) {
             int l0, a, b;
             line_of(d, i, j, k, l0, a, b);
+#pragma unroll 1
             for (int l = 0; l < m; ++l) {
                 const int pt = line_pt(m, d, a, b, l);
                 const double w = A.Dt[l0 * m + l];
@@ -350,6 +355,38 @@ int acm_check(fr_acm *a, const void *U, const void *out, const char *what)
     return FR_OK;
 }
 
+template <int M>
+int launch_grad(fr_acm *a, const double *U, int64_t ne, int epb, hipStream_t s)
+{
+    constexpr int ns = M * M * M;
+    hipLaunchKernelGGL(k_acm_grad<M>, dim3((unsigned)((ne + epb - 1) / epb)), dim3((epb * ns + 63) / 64 * 64),
+                       (size_t)epb * 3 * ns * sizeof(double), s, U, a->utr, a->Q, a->args, ne, epb);
+    return check_hip(hipGetLastError(), "k_acm_grad launch");
+}
+
+template <int M>
+int launch_back(fr_acm *a, const double *U, double *R, int64_t ne, int epb, hipStream_t s)
+{
+    constexpr int nfp = M * M, ns = nfp * M;
+    hipLaunchKernelGGL(k_acm_common<M>, dim3(blocks_for(ne * 3 * nfp)), dim3(TB), 0, s, a->utr, a->Q, a->FI,
+                       a->args, ne);
+    if (int rc = check_hip(hipGetLastError(), "k_acm_common launch")) return rc;
+    hipLaunchKernelGGL(k_acm_resid<M>, dim3((unsigned)((ne + epb - 1) / epb)), dim3((epb * ns + 63) / 64 * 64),
+                       (size_t)epb * NA * ns * sizeof(double), s, U, a->Q, a->FI, R, a->args, ne, epb);
+    return check_hip(hipGetLastError(), "k_acm_resid launch");
+}
+
+#define FR_ACM_ORDERS(CALL)                                                                       \
+    switch (a->args.m) {                                                                         \
+    case 2: return CALL(2);                                                                      \
+    case 3: return CALL(3);                                                                      \
+    case 4: return CALL(4);                                                                      \
+    case 5: return CALL(5);                                                                      \
+    case 6: return CALL(6);                                                                      \
+    case 7: return CALL(7);                                                                      \
+    default: return set_error(FR_EUNSUPPORTED, "standard ACM: order %d", a->args.m - 1);         \
+    }
+
 int launch_front(fr_acm *a, const double *U, hipStream_t s)
 {
     const int64_t ne = a->plan->ne;
@@ -358,23 +395,20 @@ int launch_front(fr_acm *a, const double *U, hipStream_t s)
                        a->args, ne);
     if (int rc = check_hip(hipGetLastError(), "k_acm_trace launch")) return rc;
     const int epb = ns >= 256 ? 1 : 256 / ns;
-    hipLaunchKernelGGL(k_acm_grad, dim3((unsigned)((ne + epb - 1) / epb)), dim3((epb * ns + 63) / 64 * 64),
-                       (size_t)epb * 3 * ns * sizeof(double), s, U, a->utr, a->Q, a->args, ne, epb);
-    return check_hip(hipGetLastError(), "k_acm_grad launch");
+#define FR_ACM_GRAD(M) launch_grad<M>(a, U, ne, epb, s)
+    FR_ACM_ORDERS(FR_ACM_GRAD)
+#undef FR_ACM_GRAD
 }
 
 int launch_residual(fr_acm *a, const double *U, double *R, hipStream_t s)
 {
     const int64_t ne = a->plan->ne;
-    const int m = a->args.m, nfp = m * m, ns = nfp * m;
+    const int ns = a->args.m * a->args.m * a->args.m;
     if (int rc = launch_front(a, U, s)) return rc;
-    hipLaunchKernelGGL(k_acm_common, dim3(blocks_for(ne * 3 * nfp)), dim3(TB), 0, s, a->utr, a->Q,
-                       a->FI, a->args, ne);
-    if (int rc = check_hip(hipGetLastError(), "k_acm_common launch")) return rc;
     const int epb = ns >= 256 ? 1 : 256 / ns;
-    hipLaunchKernelGGL(k_acm_resid, dim3((unsigned)((ne + epb - 1) / epb)), dim3((epb * ns + 63) / 64 * 64),
-                       (size_t)epb * NA * ns * sizeof(double), s, U, a->Q, a->FI, R, a->args, ne, epb);
-    return check_hip(hipGetLastError(), "k_acm_resid launch");
+#define FR_ACM_BACK(M) launch_back<M>(a, U, R, ne, epb, s)
+    FR_ACM_ORDERS(FR_ACM_BACK)
+#undef FR_ACM_BACK
 }
 
 // Allocates the dual-stepping arrays all together: after a failure nothing is
