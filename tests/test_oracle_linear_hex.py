@@ -97,3 +97,25 @@ def test_smooth_field_on_curved_mapping():
     e1, e2 = smooth_error(p, 4, 0.2), smooth_error(p, 8, 0.2)
     assert e2 < 1e-3
     assert e1 / e2 > 2 ** (p - 1)
+
+
+def test_mesh_generator_is_conforming():
+    """Neighbouring elements share their face corners (up to a 2 pi shift across
+    the periodic seam), and every element keeps a positive Jacobian."""
+    n = (4, 3, 2)
+    C = inputs.linear_hex_corners(n, amp=0.25, seed=8, smooth=0.1)
+    nx, ny, nz = n
+    two_pi = 2 * np.pi
+    for e in range(nx * ny * nz):
+        ex, ey, ez = e % nx, (e // nx) % ny, e // (nx * ny)
+        for d, (step, period) in enumerate(((1, nx), (nx, ny), (nx * ny, nz))):
+            idx = (ex, ey, ez)[d]
+            nb = e + step if idx + 1 < period else e - (period - 1) * step
+            plus = [c for c in range(8) if (c >> d) & 1]
+            minus = [c - (1 << d) for c in plus]
+            shift = np.zeros(3)
+            if idx + 1 == period:
+                shift[d] = two_pi
+            assert np.allclose(C[e, plus], C[nb, minus] + shift, rtol=0, atol=1e-12)
+    for p in (1, 3):
+        assert np.all(L.jacobian_det(p, C) > 0)
