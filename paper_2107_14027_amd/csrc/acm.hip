@@ -11,10 +11,9 @@
 //   u^I   = (u_L + u_R)/2 + beta (u_L - u_R)
 //   F_v^I = (F_vL + F_vR).n/2 - beta (F_vL - F_vR).n + tau (u_L - u_R)   (velocity)
 //
-// Four kernels, one thread per output value, every intermediate through HBM
-// (this is the unfused multi-step pipeline that hyperbolised diffusion
-// removes); the gradient and residual kernels stage their elements' line data
-// in LDS:
+// Four kernels compiled per order, every intermediate through HBM (this is
+// the unfused multi-step pipeline that hyperbolised diffusion removes); the
+// trace, gradient and residual kernels stage their elements' data in LDS:
 //   k_acm_trace   U -> face traces of P, V         utr[e][6][4][m^2]
 //   k_acm_grad    U, utr -> corrected gradient     Q[e][9][m^3]   (du_i/dx_j at 3 i + j)
 //   k_acm_common  utr, Q -> common normal flux     FI[e][3][4][m^2] (plus face of e)
@@ -67,22 +66,32 @@ __device__ __forceinline__ void line_of(int d, int i, int j, int k, int &l0, int
     else l0 = k, a = i, b = j;
 }
 
+// Face traces of (P, V): a workgroup loads the states of `epb` elements into
+// LDS with coalesced reads, then writes their traces in output order
+// (utr[e][6][4][m^2], consecutive threads write consecutive values).
+template <int M>
 __global__ void __launch_bounds__(TB) k_acm_trace(const double *__restrict__ U,
-                                                  double *__restrict__ utr, AcmArgs A, int64_t ne)
+                                                  double *__restrict__ utr, AcmArgs A, int64_t ne,
+                                                  int epb)
 {
-    const int m = A.m, nfp = m * m, ns = nfp * m;
-    const int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x;
-    if (t >= ne * 6 * nfp) return;
-    const int ab = (int)(t % nfp);
-    const int f = (int)((t / nfp) % 6);
-    const int64_t e = t / (6 * nfp);
-    const int d = f >> 1, side = f & 1, a = ab % m, b = ab / m;
-    const double *L = side ? A.lp : A.lm;
-    const double *Ue = U + e * NA * ns;
-    for (int v = 0; v < NA; ++v) {
-        double s = 0.0;
-        for (int l = 0; l < m; ++l) s += L[l] * Ue[v * ns + line_pt(m, d, a, b, l)];
-        utr[((e * 6 + f) * NA + v) * nfp + ab] = s;
+    extern __shared__ double lds[];   // [epb][4][m^3]
+    constexpr int m = M, nfp = m * m, ns = nfp * m;
+    const int64_t e0 = (int64_t)blockIdx.x * epb;
+    const int nel = (int)(ne - e0 < epb ? ne - e0 : epb);
+    const double *Ub = U + e0 * NA * ns;
+    for (int i = threadIdx.x; i < nel * NA * ns; i += TB) lds[i] = Ub[i];
+    __syncthreads();
+    constexpr int per = 6 * NA * nfp;
+    double *ob = utr + e0 * per;
+    for (int o = threadIdx.x; o < nel * per; o += TB) {
+        const int el = o / per, r = o % per;
+        const int f = r / (NA * nfp), v = (r / nfp) % NA, ab = r % nfp;
+        const int d = f >> 1, a = ab % m, b = ab / m;
+        const double *L = (f & 1) ? A.lp : A.lm;
+        const double *X = lds + (el * NA + v) * ns;
+        double acc = 0.0;
+        for (int l = 0; l < m; ++l) acc += L[l] * X[line_pt(m, d, a, b, l)];
+        ob[o] = acc;
     }
 }
 
@@ -355,10 +364,15 @@ int acm_check(fr_acm *a, const void *U, const void *out, const char *what)
     return FR_OK;
 }
 
+// Trace and gradient kernels for order M - 1; the workgroups of both hold
+// `epb` whole elements.
 template <int M>
 int launch_grad(fr_acm *a, const double *U, int64_t ne, int epb, hipStream_t s)
 {
     constexpr int ns = M * M * M;
+    hipLaunchKernelGGL(k_acm_trace<M>, dim3((unsigned)((ne + epb - 1) / epb)), dim3(TB),
+                       (size_t)epb * NA * ns * sizeof(double), s, U, a->utr, a->args, ne, epb);
+    if (int rc = check_hip(hipGetLastError(), "k_acm_trace launch")) return rc;
     hipLaunchKernelGGL(k_acm_grad<M>, dim3((unsigned)((ne + epb - 1) / epb)), dim3((epb * ns + 63) / 64 * 64),
                        (size_t)epb * 3 * ns * sizeof(double), s, U, a->utr, a->Q, a->args, ne, epb);
     return check_hip(hipGetLastError(), "k_acm_grad launch");
@@ -390,10 +404,7 @@ int launch_back(fr_acm *a, const double *U, double *R, int64_t ne, int epb, hipS
 int launch_front(fr_acm *a, const double *U, hipStream_t s)
 {
     const int64_t ne = a->plan->ne;
-    const int m = a->args.m, nfp = m * m, ns = nfp * m;
-    hipLaunchKernelGGL(k_acm_trace, dim3(blocks_for(ne * 6 * nfp)), dim3(TB), 0, s, U, a->utr,
-                       a->args, ne);
-    if (int rc = check_hip(hipGetLastError(), "k_acm_trace launch")) return rc;
+    const int ns = a->args.m * a->args.m * a->args.m;
     const int epb = ns >= 256 ? 1 : 256 / ns;
 #define FR_ACM_GRAD(M) launch_grad<M>(a, U, ne, epb, s)
     FR_ACM_ORDERS(FR_ACM_GRAD)
