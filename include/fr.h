@@ -400,6 +400,25 @@ int fr_mlp_guess(fr_plan *plan, const float *state, const double *Un, const doub
                  const double *Unm2, double *G, fr_stream_t s);
 
 /*
+ * fr_mlp_guess_checked -- the learned guess with plain extrapolation as its
+ * fallback.  G receives the network's guess (as fr_mlp_guess) when its initial
+ * pseudo-residual is not larger than accept_ratio times that of the
+ * extrapolation the network corrects (FR_OPT_GUESS_BASE), and that
+ * extrapolation otherwise (also when the network's guess is not finite).  The
+ * initial pseudo-residual is the root mean square over all points of the
+ * velocity part of R* = R(U) - M_V (3U - 4Un + Unm1) / (2 dt), the norm
+ * fr_dual_step tests (BDF2 with the physical step dt > 0).  The pseudo-time
+ * iteration that follows still decides the converged state, so the rule only
+ * chooses where it starts.  norms (host, 2 doubles) receives the network's and
+ * the extrapolation's initial norms, *used_network 1 or 0.  accept_ratio >= 0
+ * (1: not worse).  G may alias none of the inputs.  Allocates one state array
+ * of scratch on first use; synchronises the stream twice (norm read-backs).
+ */
+int fr_mlp_guess_checked(fr_plan *plan, const float *state, const double *Un, const double *Unm1,
+                         const double *Unm2, double dt, double accept_ratio, double *G,
+                         int *used_network, double norms[2], fr_stream_t s);
+
+/*
  * fr_plan_kernel_stats -- with FR_OPT_PROFILE set, every kernel launch of the
  * plan is bracketed by two HIP events recorded on the launch stream.  This call
  * waits for the recorded events, adds their elapsed times to per-kernel totals
@@ -427,6 +446,16 @@ const char *fr_last_error(void);
  * i.e. m*(6 + 2m) doubles.  Returns FR_EINVAL for p outside 1..6.
  */
 int fr_plan_operators(int p, double *out);
+
+/*
+ * fr_launch_shape -- host-only description of how the fused residual launches
+ * its kernels for order p (1..6) and precision (FR_F64 / FR_F32); no device
+ * work.  kernel = FR_K_TRACE (face-trace projection) or FR_K_FUSED (stages
+ * 2-6).  out receives {elements per batch (the largest FR_OPT_BLOCK value the
+ * kernel accepts), threads per workgroup, dynamic LDS bytes per workgroup}.
+ * Returns FR_EINVAL for other arguments.
+ */
+int fr_launch_shape(int p, int precision, int kernel, int out[3]);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,10 @@ Pin status (tests/test_oracle_*.py):
                                                  controller on an h^3 error, convergence)
   diagnostics.diagnostics (diagnostics.py)       pinned (Taylor-Green closed forms, single
                                                  modes per curl entry, irrotational field)
-  mlp_*                                          pinned (finite differences, autograd)
+  mlp_*                                          pinned (finite differences, autograd; the
+                                                 bfloat16 operand mode against autograd
+                                                 through products with rounded operands and
+                                                 torch's bfloat16 conversion)
   acm_ldg.residual, acm_ldg.gradient             pinned (reduction to the ACM-HD residual at
   (standard ACM with LDG, acm_ldg.py)            nu = 0, smooth-field convergence, conservation,
                                                  LDG energy identity for any beta and tau,
@@ -94,8 +97,9 @@ def lib():
         L.orc_dual_step.argtypes = [I, I, I, I, _dp, D, D, D, _dp, _dp, _dp, I, D, D, D, I,
                                     _ip, _dp]
         L.orc_extrap.argtypes = [ctypes.c_int64, _dp, _dp, _dp, I, _dp]
-        L.orc_mlp_forward.argtypes = [ctypes.c_int64] + [_dp] * 9
-        L.orc_mlp_loss_grad.argtypes = [ctypes.c_int64] + [_dp] * 14
+        L.orc_mlp_forward.argtypes = [ctypes.c_int64] + [_dp] * 9 + [ctypes.c_int]
+        L.orc_bf16.argtypes = [ctypes.c_int64, _dp, _dp]
+        L.orc_mlp_loss_grad.argtypes = [ctypes.c_int64] + [_dp] * 14 + [ctypes.c_int]
         L.orc_adam.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, D, D, D, D, I]
         for name in ("orc_gauss_legendre", "orc_residual", "orc_residual_elems",
                      "orc_geometry", "orc_rk4", "orc_dual_step", "orc_extrap"):
@@ -262,25 +266,38 @@ MLP_SHAPES = (("W1", (64, 12)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
               ("W3", (4, 64)), ("b3", (4,)))
 
 
-def mlp_forward(X, params, return_hidden=False):
-    """Pointwise network 12 -> 64 -> 64 -> 4 (tanh hidden layers), FP64."""
+def bf16_round(x):
+    """The bfloat16 rounding of the operand mode (binary32 first, then 8
+    significant bits, nearest, ties to even), elementwise, as float64."""
+    x = _f64(x)
+    y = np.zeros_like(x)
+    lib().orc_bf16(x.size, _p(x), _p(y))
+    return y
+
+
+def mlp_forward(X, params, return_hidden=False, bf16_operands=False):
+    """Pointwise network 12 -> 64 -> 64 -> 4 (tanh hidden layers), FP64; with
+    bf16_operands every matrix-product operand is rounded to bfloat16 first
+    (accumulation stays in double; see mlp_oracle.c)."""
     X = _f64(X).reshape(-1, 12)
     P = [_f64(params[k]) for k, _ in MLP_SHAPES]
     Y = np.zeros((X.shape[0], 4))
     H = np.zeros((X.shape[0], 128)) if return_hidden else None
     lib().orc_mlp_forward(X.shape[0], _p(X), *[_p(a) for a in P], _p(Y),
-                          _p(H) if H is not None else None)
+                          _p(H) if H is not None else None, int(bool(bf16_operands)))
     return (Y, H) if return_hidden else Y
 
 
-def mlp_loss_grad(X, Tg, params):
-    """Mean-squared error and its parameter gradients (textbook back-propagation)."""
+def mlp_loss_grad(X, Tg, params, bf16_operands=False):
+    """Mean-squared error and its parameter gradients (textbook back-propagation);
+    bf16_operands rounds every operand of every forward and backward matrix
+    product to bfloat16 (mlp_oracle.c)."""
     X = _f64(X).reshape(-1, 12)
     Tg = _f64(Tg).reshape(-1, 4)
     P = [_f64(params[k]) for k, _ in MLP_SHAPES]
     G = [np.zeros(s) for _, s in MLP_SHAPES]
     loss = lib().orc_mlp_loss_grad(X.shape[0], _p(X), _p(Tg), *[_p(a) for a in P],
-                                   *[_p(g) for g in G])
+                                   *[_p(g) for g in G], int(bool(bf16_operands)))
     return loss, {k: g for (k, _), g in zip(MLP_SHAPES, G)}
 
 

@@ -16,6 +16,7 @@ FR_OK, FR_EINVAL, FR_ENOMEM, FR_EHIP, FR_ENONFINITE, FR_ENOCONV, FR_EUNSUPPORTED
 KERNELS = ("trace", "fused", "u_project", "u_flux", "u_div", "u_common", "u_correct",
            "u_negsrc", "stage")
 FR_F64, FR_F32 = 0, 1
+FR_K_TRACE, FR_K_FUSED = 0, 1
 FR_FUSED, FR_UNFUSED = 0, 1
 NV = 13
 
@@ -26,7 +27,8 @@ EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_des
             "fr_mlp_forward", "fr_mlp_grad", "fr_mlp_train_step", "fr_mlp_guess",
             "fr_pmg_create", "fr_pmg_dual_step", "fr_pmg_destroy", "fr_diagnostics",
             "fr_acm_create", "fr_acm_residual", "fr_acm_gradient", "fr_acm_dual_step",
-            "fr_acm_destroy", "fr_lhex_create", "fr_lhex_residual", "fr_lhex_destroy")
+            "fr_acm_destroy", "fr_lhex_create", "fr_lhex_residual", "fr_lhex_destroy",
+            "fr_launch_shape", "fr_mlp_guess_checked")
 
 
 class FrError(RuntimeError):
@@ -65,6 +67,7 @@ def lib():
         L.fr_last_error.argtypes = []
         L.fr_last_error.restype = ctypes.c_char_p
         L.fr_plan_operators.argtypes = [I, _dp]
+        L.fr_launch_shape.argtypes = [I, I, I, ctypes.POINTER(I)]
         L.fr_plan_kernel_stats.argtypes = [_vp, I, _dp, ctypes.POINTER(ctypes.c_int64), I]
         I64, F = ctypes.c_int64, ctypes.c_float
         L.fr_mlp_state_floats.argtypes = []
@@ -76,6 +79,8 @@ def lib():
         L.fr_mlp_grad.argtypes = [_vp, _vp, _vp, _vp, I64, _vp, _vp, _vp]
         L.fr_mlp_train_step.argtypes = [_vp, _vp, _vp, _vp, I64, F, I, _vp, _vp]
         L.fr_mlp_guess.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.fr_mlp_guess_checked.argtypes = [_vp, _vp, _vp, _vp, _vp, D, D, _vp, ctypes.POINTER(I),
+                                           _dp, _vp]
         L.fr_pmg_create.argtypes = [_vp, I, ctypes.POINTER(I), ctypes.POINTER(I), D]
         L.fr_pmg_create.restype = _vp
         L.fr_pmg_dual_step.argtypes = [_vp, _vp, _vp, _vp, D, D, D, I, ctypes.POINTER(I), _dp, _vp]
@@ -381,6 +386,30 @@ def fr_mlp_guess(plan, state, Un, Unm1, Unm2, G, stream=None):
                                      _dev(Unm1, torch.float64, ns, "Unm1"),
                                      _dev(Unm2, torch.float64, ns, "Unm2"),
                                      _dev(G, torch.float64, ns, "G"), _stream(stream)))
+
+
+def fr_mlp_guess_checked(plan, state, Un, Unm1, Unm2, dt, G, accept_ratio=1.0, stream=None):
+    """Learned guess with extrapolation as fallback; returns (used_network,
+    network's initial norm, extrapolation's initial norm)."""
+    import torch
+    ns = fr_state_len(plan)
+    used = ctypes.c_int(0)
+    norms = np.zeros(2)
+    _check(lib().fr_mlp_guess_checked(plan, _dev(state, torch.float32, None, "state"),
+                                      _dev(Un, torch.float64, ns, "Un"),
+                                      _dev(Unm1, torch.float64, ns, "Unm1"),
+                                      _dev(Unm2, torch.float64, ns, "Unm2"), dt, accept_ratio,
+                                      _dev(G, torch.float64, ns, "G"), ctypes.byref(used),
+                                      norms.ctypes.data_as(_dp), _stream(stream)))
+    return bool(used.value), float(norms[0]), float(norms[1])
+
+
+def fr_launch_shape(p, precision, kernel):
+    """Host-only: (elements per batch, threads per workgroup, LDS bytes) of the
+    fused path's trace (FR_K_TRACE) or fused (FR_K_FUSED) kernel."""
+    out = (ctypes.c_int * 3)()
+    _check(lib().fr_launch_shape(p, precision, kernel, out))
+    return tuple(out)
 
 
 def fr_plan_operators(p):

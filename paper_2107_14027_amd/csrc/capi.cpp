@@ -402,4 +402,50 @@ int fr_guess_extrap(fr_plan *pl, const double *Un, const double *Unm1, const dou
                          (int64_t)fr_state_len(pl), (hipStream_t)s);
 }
 
+int fr_mlp_guess_checked(fr_plan *pl, const float *state, const double *Un, const double *Unm1,
+                         const double *Unm2, double dt, double accept_ratio, double *G,
+                         int *used_network, double norms[2], fr_stream_t sv)
+{
+    if (!pl) return set_error(FR_EINVAL, "fr_mlp_guess_checked: NULL plan");
+    if (int rc = check_array(Un, "Un")) return rc;
+    if (int rc = check_array(Unm1, "Unm1")) return rc;
+    if (int rc = check_array(Unm2, "Unm2")) return rc;
+    if (int rc = check_array(G, "G")) return rc;
+    if (!state || !used_network || !norms || !(dt > 0.0) || !(accept_ratio >= 0.0))
+        return set_error(FR_EINVAL, "fr_mlp_guess_checked: state=%p dt=%g ratio=%g", (const void *)state,
+                         dt, accept_ratio);
+    const size_t n = fr_state_len(pl);
+    const size_t bytes = n * 8;
+    if (overlap(G, bytes, Un, bytes) || overlap(G, bytes, Unm1, bytes) ||
+        overlap(G, bytes, Unm2, bytes))
+        return set_error(FR_EINVAL, "fr_mlp_guess_checked: G overlaps an input");
+    hipStream_t s = (hipStream_t)sv;
+    const bool f64 = pl->precision == FR_F64;
+    const size_t nB = (size_t)pl->ne * 3 * pl->m * pl->m * pl->m;
+    if (int rc = ensure_scratch(pl->guess, bytes)) return rc;
+    if (int rc = ensure_scratch(pl->dual, (nB + (f64 ? 0 : n)) * sizeof(double))) return rc;
+    double *E = (double *)pl->guess.ptr;
+    double *B = (double *)pl->dual.ptr;
+    // the extrapolation the network corrects, and the network's guess
+    if (int rc = launch_extrap(Un, Unm1, Unm2, pl->guess_base, 0, E, (int64_t)n, s)) return rc;
+    if (int rc = fr_mlp_guess(pl, state, Un, Unm1, Unm2, G, sv)) return rc;
+    // initial pseudo-residual RMS (velocity part of R*, BDF2) of each: the first
+    // stage of a pseudo-step without completing it, so neither guess changes
+    if (int rc = launch_bdf_const(pl, Un, Unm1, dt, B, s)) return rc;
+    const double a = 1.5 / dt;
+    int it = 0, conv = 0;
+    double rn = NAN, re = NAN;
+    int rc = pseudo_iterate(pl, G, B, a, nullptr, dt, 0.0, 0, 1, true, &it, &rn, &conv, s);
+    if (rc && rc != FR_ENONFINITE) return rc;
+    if (rc == FR_ENONFINITE) rn = INFINITY;
+    rc = pseudo_iterate(pl, E, B, a, nullptr, dt, 0.0, 0, 1, true, &it, &re, &conv, s);
+    if (rc) return rc;
+    norms[0] = rn;
+    norms[1] = re;
+    *used_network = std::isfinite(rn) && rn <= accept_ratio * re;
+    if (!*used_network)
+        return check_hip(hipMemcpyAsync(G, E, bytes, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync(G)");
+    return FR_OK;
+}
+
 }  // extern "C"

@@ -122,6 +122,7 @@ struct fr_plan {
     fr::Scratch norm;       // partial sums (double)
     fr::Scratch mlp;        // MLP gradient partials / moments
     fr::Scratch diag;       // partial sums of the flow diagnostics
+    fr::Scratch guess;      // the fallback extrapolation of the checked learned guess (double)
     double *norm_host = nullptr;  // pinned host word for the norm read-back
     // optional per-kernel event timing
     int profile = 0;

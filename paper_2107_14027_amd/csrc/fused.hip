@@ -1056,4 +1056,52 @@ int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *
     return fused_any(pl, U, nullptr, &sp, nparts, s);
 }
 
+// Launch shape of the fused path's kernels (host only): elements per batch,
+// threads per workgroup and dynamic LDS bytes, as fused_impl launches them.
+template <int P, typename T>
+void shape_of(int kernel, int out[3])
+{
+    constexpr int M = P + 1, NS = M * M * M;
+    if (kernel == FR_K_TRACE) {
+        constexpr int E = TraceShape<P, T>::EMAX;
+        out[0] = E;
+        out[1] = TraceShape<P, T>::NT;
+        out[2] = (int)(((size_t)E * NV * TracePad<M>::NSP + 2 * M) * sizeof(T) + 6 * E * sizeof(int));
+    } else {
+        constexpr int E = Shape<P, T>::EMAX;
+        out[0] = E;
+        out[1] = Shape<P, T>::NT;
+        out[2] = (int)(((size_t)E * (NV + 9) * NS + (size_t)6 * E * TraceLayout<M, T>::CHP +
+                        OpsLayout<M>::size + 24) * sizeof(T));
+    }
+}
+
+}  // namespace fr
+
+extern "C" int fr_launch_shape(int p, int precision, int kernel, int out[3])
+{
+    using namespace fr;
+    if (p < 1 || p > PMAX || !out || (precision != FR_F64 && precision != FR_F32) ||
+        (kernel != FR_K_TRACE && kernel != FR_K_FUSED))
+        return set_error(FR_EINVAL, "fr_launch_shape: p=%d precision=%d kernel=%d", p, precision,
+                         kernel);
+    const bool f64 = precision == FR_F64;
+    switch (p) {
+#define FR_SHAPE_CASE(PP)                                                  \
+    case PP:                                                               \
+        f64 ? shape_of<PP, double>(kernel, out) : shape_of<PP, float>(kernel, out); \
+        break;
+        FR_SHAPE_CASE(1)
+        FR_SHAPE_CASE(2)
+        FR_SHAPE_CASE(3)
+        FR_SHAPE_CASE(4)
+        FR_SHAPE_CASE(5)
+        FR_SHAPE_CASE(6)
+#undef FR_SHAPE_CASE
+    }
+    return FR_OK;
+}
+
+namespace fr {
+
 }  // namespace fr

@@ -445,6 +445,7 @@ void fr_plan_destroy(fr_plan *pl)
     free_scratch(pl->mlp);
     free_scratch(pl->diag);
     free_scratch(pl->rk34);
+    free_scratch(pl->guess);
     if (pl->norm_host) hipHostFree(pl->norm_host);
     if (pl->ops64) hipFree(pl->ops64);
     if (pl->ops32) hipFree(pl->ops32);

@@ -8,9 +8,12 @@ Protocol (dual time stepping, BDF2, RK4 pseudo-steps, Taylor-Green field):
   (normalisation from the rows, Adam); then the evaluation phase runs four
   times from the identical state at the end of training: with quadratic
   extrapolation, with linear extrapolation, with the network, and with the
-  network kept only where its initial pseudo-residual is not larger than the
-  quadratic extrapolation's, recording the completed pseudo-steps of every
-  physical step.  The network corrects the extrapolation chosen by guess_base.
+  library's checked guess (fr_mlp_guess_checked: the network kept only where
+  its initial pseudo-residual is not larger than that of the extrapolation it
+  corrects), recording the completed pseudo-steps of every physical step.  The
+  network corrects the extrapolation chosen by guess_base.  A ratio between
+  two modes is reported only if neither capped a step (a capped step did not
+  reach the tolerance, so the counts would not compare equal work).
   With solver="pmg" every physical step runs P-multigrid cycles instead (the
   paper's cycle shape for order p, pseudo-step x1.75 per level), and the counts
   are completed cycles.
@@ -41,7 +44,8 @@ def log(*a):
 def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
         eval_steps=20, samples_per_step=1 << 14, epochs=2000, lr=2e-3, batch=1 << 16,
         zeta=4.0, Re=1600.0, Lr=1.0 / (2.0 * math.pi), seed=5, precision=B.FR_F64, guess_base=2,
-        solver="rk4", max_cycles=400):
+        solver="rk4", max_cycles=400, train_guess=2,
+        modes=("extrap", "extrap1", "mlp", "mlp_fallback"), progress_every=5):
     import torch
     nu, T = inputs.nu_T_from_length(Re, Lr)
     n = (N, N, N)
@@ -85,7 +89,7 @@ def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
         if s == 1:
             U, it, res, rc = step(hist[-1], hist[-1], None)
         else:
-            order = 1 if s == 2 else 2
+            order = 1 if s == 2 else train_guess
             B.fr_guess_extrap(plan.handle, hist[-1], hist[-2], hist[-3] if order == 2 else None,
                               order, G)
             U, it, res, rc = step(G, hist[-1], hist[-2])
@@ -99,7 +103,7 @@ def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
         train_log.append((it, res, rc))
         hist.append(U)
         hist = hist[-3:]
-        if s % 10 == 0 or s <= 3:
+        if s % progress_every == 0 or s <= 3:
             log("train step %d: %d %s, residual %.3e, rc %d (%.0f s)" %
                 (s, it, unit, res, rc, time.time() - t0))
     # fit the network
@@ -122,20 +126,21 @@ def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
     start = [h.clone() for h in hist]
     E = torch.empty_like(G)
     res_by = {}
-    for mode in ("extrap", "extrap1", "mlp", "mlp_fallback"):
+    for mode in modes:
         hs = [h.clone() for h in start]
         its, r0s, rcs, fallback = [], [], [], 0
         t1 = time.time()
         for s in range(eval_steps):
             B.fr_guess_extrap(plan.handle, hs[-1], hs[-2], hs[-3], 1 if mode == "extrap1" else 2, E)
             guess = E
-            if mode.startswith("mlp"):
+            if mode == "mlp":
                 B.fr_mlp_guess(plan.handle, state, hs[-1], hs[-2], hs[-3], G)
                 guess = G
-                if mode == "mlp_fallback" and initial_residual(G, hs[-1], hs[-2]) > \
-                        initial_residual(E, hs[-1], hs[-2]):
-                    guess = E
-                    fallback += 1
+            elif mode == "mlp_fallback":
+                used, _, _ = B.fr_mlp_guess_checked(plan.handle, state, hs[-1], hs[-2], hs[-3],
+                                                    dt, G)
+                guess = G
+                fallback += 0 if used else 1
             r0 = initial_residual(guess, hs[-1], hs[-2])
             r0s.append(r0)
             U, it, res, rc = step(guess, hs[-1], hs[-2])
@@ -143,7 +148,7 @@ def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
             rcs.append(rc)
             hs.append(U)
             hs = hs[-3:]
-            if s % 5 == 0:
+            if s % progress_every == 0:
                 log("%s step %d: %d %s, initial residual %.3e, rc %d" % (mode, s, it, unit, r0, rc))
         res_by[mode] = {"iters": its, "initial_residual": r0s, "rc": rcs, "fallback": fallback,
                         "seconds": time.time() - t1}
@@ -160,18 +165,28 @@ def run(p=3, N=16, dt=5e-2, dtau=5e-3, tol=1e-6, max_iters=3000, train_steps=20,
                          "initial_residual_median": float(np.median(r["initial_residual"])),
                          "fallbacks": r["fallback"], "iters": r["iters"],
                          "initial_residual": r["initial_residual"]}
+
+    def ratio(a, b):
+        if a not in summary or b not in summary:
+            return None
+        ma, mb = summary[a], summary[b]
+        if ma["capped"] or mb["capped"]:
+            return None
+        return ma["iters_mean"] / max(1e-9, mb["iters_mean"])
+
     return {
         "config": {"p": p, "lattice": N, "dt": dt, "dtau": dtau, "tol": tol,
                    "max_iters": max_iters, "train_steps": train_steps, "eval_steps": eval_steps,
                    "samples": nrows, "epochs": epochs, "lr": lr, "zeta": zeta, "nu": nu, "T": T,
-                   "guess_base": guess_base, "solver": solver,
+                   "guess_base": guess_base, "solver": solver, "train_guess": train_guess,
                    "max_cycles": max_cycles if solver == "pmg" else None},
         "train_iters_mean": float(np.mean([t[0] for t in train_log])),
         "train_capped": int(sum(1 for t in train_log if t[2] != 0)),
         "loss_curve": losses,
         "modes": summary,
-        "mlp_vs_quadratic_iters": summary["mlp"]["iters_mean"] / max(1e-9, summary["extrap"]["iters_mean"]),
-        "mlp_vs_linear_iters": summary["mlp"]["iters_mean"] / max(1e-9, summary["extrap1"]["iters_mean"]),
+        "mlp_vs_quadratic_iters": ratio("mlp", "extrap"),
+        "mlp_vs_linear_iters": ratio("mlp", "extrap1"),
+        "checked_vs_linear_iters": ratio("mlp_fallback", "extrap1"),
     }
 
 if __name__ == "__main__":

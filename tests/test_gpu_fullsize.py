@@ -12,7 +12,7 @@ import pytest
 import oracle
 from paper_2107_14027_amd import binding as B
 from paper_2107_14027_amd import inputs
-from gpu_util import NU, T_CFG, TOL, ZETA, gpu_residual, rel, say
+from gpu_util import NU, T_CFG, TOL, ZETA, check_groups, gpu_residual, rel, say
 from test_oracle_residual import sines_exact_residual
 
 pytestmark = pytest.mark.gpu
@@ -55,6 +55,7 @@ def test_order_sweep_full_size_sampled(p):
         del R
         say("  prec=%d var=%d rel %.2e" % (prec, var, rel(Rs, Ro[prec])))
         assert rel(Rs, Ro[prec]) <= TOL[prec], (prec, var, rel(Rs, Ro[prec]))
+        check_groups(Rs, Ro[prec], prec, Uh[sel], what="p=%d prec=%d var=%d" % (p, prec, var))
     del Ud
     torch.cuda.empty_cache()
 
@@ -81,6 +82,7 @@ def test_manufactured_64cubed_p4_sampled():
         del R
         say("  prec=%d rel %.2e" % (prec, rel(Rs, Ro[prec])))
         assert rel(Rs, Ro[prec]) <= TOL[prec]
+        check_groups(Rs, Ro[prec], prec, U[sel], what="manufactured prec=%d" % prec)
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])

@@ -1,7 +1,8 @@
 """GPU parity of the learned initial guess (pointwise 12-64-64-4 network on
 BF16 matrix cores) through the C ABI: forward and gradients against the CPU
-oracle evaluated on BF16-rounded operands, Adam against the oracle, training
-rows and normalisation against numpy, and the guess against extrapolation."""
+oracle in its bfloat16-operand mode (every matrix-product operand rounded,
+double accumulation) to 1e-3 relative, Adam against the oracle, training rows
+and normalisation against numpy, and the guess against extrapolation."""
 import numpy as np
 import pytest
 
@@ -19,11 +20,6 @@ def torch():
     return t
 
 
-def bf16(a):
-    t = torch()
-    return t.tensor(np.asarray(a, dtype=np.float32)).to(t.bfloat16).to(t.float64).numpy()
-
-
 def random_state(seed, scale=0.3):
     t = torch()
     st = B.mlp_new_state(seed)
@@ -37,26 +33,14 @@ def random_state(seed, scale=0.3):
     return st
 
 
-def host_params(st, rounded):
-    P = {k: v.double().cpu().numpy() for k, v in B.mlp_params(st).items()}
-    if rounded:
-        for k in ("W1", "W2", "W3"):
-            P[k] = bf16(P[k])
-    return P
+def host_params(st):
+    return {k: v.double().cpu().numpy() for k, v in B.mlp_params(st).items()}
 
 
 def norm_x(st, X):
     s = st.cpu().numpy()
     mu, isd = s[5252:5264], s[5264:5276]
     return ((X.astype(np.float32) - mu) * isd).astype(np.float32)
-
-
-def emulated_forward(P, xn):
-    """Reference with the matrix-core roundings: BF16 operands, wide accumulation."""
-    x = bf16(xn)
-    h1 = bf16(np.tanh(x @ P["W1"].T + P["b1"]))
-    h2 = bf16(np.tanh(h1 @ P["W2"].T + P["b2"]))
-    return h2 @ P["W3"].T + P["b3"]
 
 
 def test_init_state():
@@ -82,12 +66,11 @@ def test_forward_matches_oracle(n):
     t.cuda.synchronize()
     y = Yd.cpu().numpy()
     xn = norm_x(st, X)
-    Pr = host_params(st, rounded=True)
-    yo = oracle.mlp_forward(bf16(xn), Pr)
-    ye = emulated_forward(Pr, xn)
-    scale = max(1.0, np.abs(yo).max())
-    assert np.max(np.abs(y - yo)) <= 3e-2 * scale
-    assert np.max(np.abs(y - ye)) <= 5e-3 * scale
+    # the oracle rounds every matrix-product operand to bfloat16 itself
+    yo = oracle.mlp_forward(xn, host_params(st), bf16_operands=True)
+    err = np.max(np.abs(y - yo)) / max(1.0, np.abs(yo).max())
+    say("  max error %.2e" % err)
+    assert err <= 1e-3
     plan.close()
 
 
@@ -106,15 +89,18 @@ def test_gradients_match_oracle():
     t.cuda.synchronize()
     s = st.cpu().numpy()
     ysd = s[5276:5280]
-    Pr = host_params(st, rounded=True)
-    lo, go = oracle.mlp_loss_grad(bf16(norm_x(st, X)), Y / ysd, Pr)
-    assert abs(float(loss.item()) - lo) <= 2e-2 * lo
+    lo, go = oracle.mlp_loss_grad(norm_x(st, X), Y / ysd, host_params(st),
+                                  bf16_operands=True)
+    say("  loss %.6e oracle %.6e" % (float(loss.item()), lo))
+    assert abs(float(loss.item()) - lo) <= 1e-3 * lo
     gg = g.cpu().numpy()
     o = 0
     for k, shp in B.MLP_SHAPES:
         sz = int(np.prod(shp))
         a, b = gg[o:o + sz].reshape(shp), go[k]
-        assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(b) + 1e-7, k
+        e = np.linalg.norm(a - b) / np.linalg.norm(b)
+        say("  grad %s rel %.2e" % (k, e))
+        assert e <= 1e-3, k
         o += sz
     # deterministic: the fixed-order reduction repeats bitwise
     g2 = t.zeros_like(g)

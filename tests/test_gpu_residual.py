@@ -8,16 +8,13 @@ import pytest
 import oracle
 from paper_2107_14027_amd import binding as B
 from paper_2107_14027_amd import inputs
-from gpu_util import NU, T_CFG, TOL, ZETA, gpu_residual, rel, say
+from gpu_util import NU, T_CFG, TOL, ZETA, check_groups, gpu_residual, rel, say
 
 pytestmark = pytest.mark.gpu
 
 def fused_emax(p, prec):
     """Elements per batch of the fused kernel's launch shape for order p."""
-    import os
-    import re
-    src = os.path.join(os.path.dirname(__file__), "..", "paper_2107_14027_amd", "csrc", "fused.hip")
-    return int(re.search(r"#define FR_E%d_%s (\d+)" % (p, prec), open(src).read()).group(1))
+    return B.fr_launch_shape(p, B.FR_F64 if prec == "D" else B.FR_F32, B.FR_K_FUSED)[0]
 
 
 SKEW = np.array([[0.30, 0.05, -0.02], [0.01, 0.25, 0.04], [-0.03, 0.02, 0.35]])
@@ -42,6 +39,7 @@ def test_config1_tgv_noise(prec, var):
     R = gpu_residual(p, n, U, precision=prec, variant=var)
     Ro = oracle.residual(p, n, U, ZETA, NU, T_CFG)
     assert rel(R, Ro) <= TOL[prec]
+    check_groups(R, Ro, prec, U, what="config1")
 
 
 # lattices sized so that every order spans several workgroups with a ragged tail
@@ -60,6 +58,7 @@ def test_orders_ragged(p, n, prec, var, jac):
     R = gpu_residual(p, n, U, precision=prec, variant=var, jac=J)
     Ro = oracle.residual(p, n, U, ZETA, NU, T_CFG, J)
     assert rel(R, Ro) <= TOL[prec], rel(R, Ro)
+    check_groups(R, Ro, prec, U, what="p=%d jac=%s" % (p, jac))
 
 
 @pytest.mark.parametrize("n", [(1, 1, 1), (1, 2, 1), (2, 1, 1)])
@@ -71,7 +70,9 @@ def test_degenerate_lattices(n, prec):
     say("degenerate n=%s prec=%d" % (n, prec))
     for var in VAR:
         R = gpu_residual(p, n, U, precision=prec, variant=var)
-        assert rel(R, oracle.residual(p, n, U, ZETA, NU, T_CFG)) <= TOL[prec]
+        Ro = oracle.residual(p, n, U, ZETA, NU, T_CFG)
+        assert rel(R, Ro) <= TOL[prec]
+        check_groups(R, Ro, prec, U, what="degenerate")
 
 
 def test_free_stream_and_paper_T():
@@ -85,7 +86,9 @@ def test_free_stream_and_paper_T():
     assert np.max(np.abs(R)) < 1e-12
     U = inputs.tgv(p, n, noise=1e-3, seed=1)
     R = gpu_residual(p, n, U, zeta=2.5, T=5e-3)
-    assert rel(R, oracle.residual(p, n, U, 2.5, NU, 5e-3)) <= 1e-12
+    Ro = oracle.residual(p, n, U, 2.5, NU, 5e-3)
+    assert rel(R, Ro) <= 1e-12
+    check_groups(R, Ro, B.FR_F64, U, zeta=2.5, T=5e-3, what="paper T")
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 5])

@@ -1,20 +1,22 @@
-"""Host-side checks of the fused kernels' launch invariants, read from the
-kernel source's shape table: LDS fits a compute unit, the per-batch neighbour
+"""Host-side checks of the fused kernels' launch invariants, with the launch
+shapes the library reports (fr_launch_shape, no device work): LDS fits a
+compute unit, the per-batch neighbour
 table is fully covered by the workgroup's threads, every receiving trace
 block is written by exactly one (element, face), and every staged read lies
 inside the trace array.  These mirror the index formulas of k_trace and
 k_fused (face f = 2d + side, neighbour across a face, padded trace blocks)."""
-import os
-import re
-
 import pytest
 
-SRC = os.path.join(os.path.dirname(__file__), "..", "paper_2107_14027_amd", "csrc", "fused.hip")
+from paper_2107_14027_amd import binding as B
+
 NV, NTR, LDS_BYTES = 13, 7, 160 * 1024
+PREC = {"D": B.FR_F64, "F": B.FR_F32}
 
 
-def shape(name):
-    return int(re.search(r"#define %s (\d+)" % name, open(SRC).read()).group(1))
+def shapes(p, prec):
+    """(trace E, trace threads, trace LDS), (fused E, fused threads, fused LDS)."""
+    return (B.fr_launch_shape(p, PREC[prec], B.FR_K_TRACE),
+            B.fr_launch_shape(p, PREC[prec], B.FR_K_FUSED))
 
 
 def neighbour(e, f, nx, ny, nz):
@@ -44,11 +46,10 @@ def layout(p, prec):
 def test_lds_fits(p, prec):
     esz, m, chp, _ = layout(p, prec)
     ns = m ** 3
-    te, e = shape("FR_TE%d_%s" % (p, prec)), shape("FR_E%d_%s" % (p, prec))
-    nt, tnt = shape("FR_NT%d_%s" % (p, prec)), shape("FR_TNT%d_%s" % (p, prec))
+    (te, tnt, tlds), (e, nt, lds) = shapes(p, prec)
     mp = m + 1 if (m % 2 == 0 and m >= 4) else m        # padded x-line pitch of k_trace
-    assert (te * NV * mp * m * m + 2 * m) * esz + 6 * te * 4 <= LDS_BYTES
-    assert (e * (NV + 9) * ns + 6 * e * chp + m * m + 4 * m + 24) * esz <= LDS_BYTES
+    assert tlds == (te * NV * mp * m * m + 2 * m) * esz + 6 * te * 4 <= LDS_BYTES
+    assert lds == (e * (NV + 9) * ns + 6 * e * chp + m * m + 4 * m + 24) * esz <= LDS_BYTES
     assert nt % 64 == 0 and tnt % 64 == 0 and nt >= 2 * m and tnt >= 2 * m
 
 
@@ -59,8 +60,7 @@ LATTICES = [(5, 3, 4), (1, 1, 1), (2, 1, 1), (1, 2, 3), (4, 4, 4), (3, 5, 2)]
 @pytest.mark.parametrize("p", range(1, 7))
 def test_trace_blocks_written_once_and_reads_in_range(p, prec):
     _, _, _, chv = layout(p, prec)
-    temax, tnt = shape("FR_TE%d_%s" % (p, prec)), shape("FR_TNT%d_%s" % (p, prec))
-    emax, nt = shape("FR_E%d_%s" % (p, prec)), shape("FR_NT%d_%s" % (p, prec))
+    (temax, tnt, _), (emax, nt, _) = shapes(p, prec)
     for nx, ny, nz in LATTICES:
         ne = nx * ny * nz
         te = min(temax, ne)
@@ -87,3 +87,10 @@ def test_trace_blocks_written_once_and_reads_in_range(p, prec):
                 f, o = divmod(k, run)
                 if nel == emax or o < nel * chv:
                     assert 0 <= (f * ne + e0) * chv + o < 6 * ne * chv
+
+
+def test_launch_shape_rejects_bad_arguments():
+    for args in ((0, B.FR_F64, B.FR_K_FUSED), (7, B.FR_F64, B.FR_K_FUSED), (3, 2, B.FR_K_FUSED),
+                 (3, B.FR_F64, 2)):
+        with pytest.raises(B.FrError):
+            B.fr_launch_shape(*args)
