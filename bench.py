@@ -11,8 +11,11 @@ R = -div F + S at every order, all inputs resident in HBM.
 Prints ONE JSON line on stdout; progress goes to stderr.
   value      GDOF/s = sum over orders of ne (p+1)^3 13, divided by the step time
   roofline   the dominant kernel (largest share of the step), HBM bound:
-             algorithmic bytes per launch / its mean launch time, timed with
-             HIP events on the launch stream inside the timed region
+             algorithmic bytes per launch (the floor: read U once, write R
+             once, 26 values per point) / its mean launch time, timed with HIP
+             events on the launch stream inside the timed region; the bytes
+             this design moves (the neighbours' face traces as well) are
+             reported beside it
   sweep      per order: fused vs unfused, FP64 vs FP32 GDOF/s and each kernel's
              fraction of the 8 TB/s HBM peak
   cpu_baseline  the serial C oracle on a bounded sample of the same workload
@@ -27,6 +30,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2107_14027_amd import bytemodel as BM  # noqa: E402
+
 LATTICE = {1: 128, 2: 85, 3: 64, 4: 51, 5: 43, 6: 40}
 ZETA, NU = 4.0, 1.0 / 1600.0
 TRELAX = (1.0 / (2.0 * 3.141592653589793)) ** 2 / NU
@@ -34,22 +39,38 @@ HBM_PEAK_GBS = 8000.0
 NV = 13
 
 
+def rnd4(x):
+    return None if x is None else round(x, 4)
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def floor_bytes(p, ne, esz):
+    """Algorithmic HBM bytes of one residual: read U and write R once (26 values
+    per point)."""
+    return BM.bytes_per_launch(BM.floor_values(), ne * (p + 1) ** 3, esz)
+
+
 def fused_bytes(p, ne, esz):
-    """Algorithmic HBM bytes of one fused-kernel launch: read U and write R once
-    (26 values per point) plus the neighbours' face traces (6 faces x 7 values
-    x m^2 points per element)."""
-    m = p + 1
-    return ne * (2 * NV * m ** 3 + 6 * 7 * m * m) * esz
+    """Bytes the fused kernel moves by design: read U, the neighbours' face traces
+    (6 faces x 7 values x m^2 points per element), write R."""
+    return BM.bytes_per_launch(BM.fused_values(p + 1), ne * (p + 1) ** 3, esz)
 
 
 def trace_bytes(p, ne, esz):
     """Face-trace kernel: read U once, write 6 x 7 x m^2 trace values per element."""
-    m = p + 1
-    return ne * (NV * m ** 3 + 6 * 7 * m * m) * esz
+    return BM.bytes_per_launch(BM.trace_values(p + 1), ne * (p + 1) ** 3, esz)
+
+
+PAPER_CONTEXT = {
+    "kernel_fusion_speedup": "3-4x fused vs unfused flux and divergence kernels, NVIDIA TITAN V, "
+                             "CUDA 11.2 (abstract, Sec. 4); bandwidth bound 4x (stages 2+3) and "
+                             "5.346x (2+3+6), Sec. 3",
+    "end_to_end": "about 2.3x (FP32) and 2.2x (FP64) ACM-HD with fused kernels against standard "
+                  "ACM, Taylor-Green to t = 10, NVIDIA V100 (Sec. 5)",
+}
 
 
 def read_traffic(kernel_name):
@@ -432,21 +453,30 @@ def main():
         tr_ms, tr_n = B.fr_plan_kernel_stats(plan.handle, 0)
         fu_ms, fu_n = B.fr_plan_kernel_stats(plan.handle, 1)
         plan.set(B.FR_OPT_PROFILE, 0)
-        kstats[p] = dict(trace_ms=tr_ms / max(tr_n, 1), fused_ms=fu_ms / max(fu_n, 1),
-                         fused_total=fu_ms, launches=fu_n,
-                         fused_gbs=fused_bytes(p, ne, 8) / (fu_ms / max(fu_n, 1)) / 1e6,
-                         trace_gbs=trace_bytes(p, ne, 8) / (tr_ms / max(tr_n, 1)) / 1e6)
+        fms, tms = fu_ms / max(fu_n, 1), tr_ms / max(tr_n, 1)
+        kstats[p] = dict(trace_ms=tms, fused_ms=fms, fused_total=fu_ms, launches=fu_n,
+                         fused_floor_gbs=floor_bytes(p, ne, 8) / fms / 1e6,
+                         fused_gbs=fused_bytes(p, ne, 8) / fms / 1e6,
+                         trace_gbs=trace_bytes(p, ne, 8) / tms / 1e6,
+                         residual_floor_gbs=floor_bytes(p, ne, 8) / (fms + tms) / 1e6)
     pdom = max(kstats, key=lambda p: kstats[p]["fused_total"])
     ndom = lattices[pdom]
-    dom_bytes = fused_bytes(pdom, ndom[0] * ndom[1] * ndom[2], 8)
+    nedom = ndom[0] * ndom[1] * ndom[2]
+    dom_bytes = floor_bytes(pdom, nedom, 8)
     achieved = dom_bytes / kstats[pdom]["fused_ms"] / 1e6
     kname = "k_fused_p%d_f64" % pdom
     traffic = read_traffic(kname)
+    design = fused_bytes(pdom, nedom, 8)
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
                 "bytes_per_launch": dom_bytes,
+                "bytes_per_point": 26 * 8,
+                "points_per_launch": nedom * (pdom + 1) ** 3,
                 "mean_launch_ms": round(kstats[pdom]["fused_ms"], 4),
+                "design_bytes_per_launch": design,
+                "design_frac": round(design / kstats[pdom]["fused_ms"] / 1e6 / HBM_PEAK_GBS, 4),
+                "whole_residual_frac": round(kstats[pdom]["residual_floor_gbs"] / HBM_PEAK_GBS, 4),
                 "measured_reference_gbs": hbm_ref,
                 "frac_of_measured_copy": (round(achieved / hbm_ref["copy_gbs"], 4) if hbm_ref else None)}
 
@@ -454,12 +484,25 @@ def main():
     if not args.no_sweep:
         for p, n, plan, U, R in work:
             ne = n[0] * n[1] * n[2]
-            dof = ne * NV * (p + 1) ** 3
-            row = {"fused_f64": dof / (kstats[p]["fused_ms"] + kstats[p]["trace_ms"]) / 1e6,
-                   "fused_kernel_f64_hbm_frac": kstats[p]["fused_gbs"] / HBM_PEAK_GBS,
-                   "trace_kernel_f64_hbm_frac": kstats[p]["trace_gbs"] / HBM_PEAK_GBS}
+            m = p + 1
+            dof = ne * NV * m ** 3
+            ks = kstats[p]
+            row = {"fused_f64": dof / (ks["fused_ms"] + ks["trace_ms"]) / 1e6,
+                   "fused_kernel_f64_floor_frac": ks["fused_floor_gbs"] / HBM_PEAK_GBS,
+                   "fused_kernel_f64_design_frac": ks["fused_gbs"] / HBM_PEAK_GBS,
+                   "trace_kernel_f64_hbm_frac": ks["trace_gbs"] / HBM_PEAK_GBS,
+                   "fused_residual_f64_floor_frac": ks["residual_floor_gbs"] / HBM_PEAK_GBS}
             pu = B.Plan(p, n, ZETA, NU, TRELAX, precision=B.FR_F64, variant=B.FR_UNFUSED)
+            pu.set(B.FR_OPT_PROFILE, 1)
             row["unfused_f64"] = dof / time_residual(B, torch, pu, U, R, 3) / 1e6
+            # each unfused kernel's bandwidth by its own byte model (Table 1's arrays)
+            uv = BM.unfused_values(m)
+            for kid, stage in zip(range(2, 8), ("stage1", "stage2", "stage3", "stage4", "stage5",
+                                                "stage6")):
+                kms, kn = B.fr_plan_kernel_stats(pu.handle, kid)
+                row["unfused_%s_f64_hbm_frac" % stage] = (
+                    BM.bytes_per_launch(uv[stage], ne * m ** 3, 8) / (kms / max(kn, 1)) / 1e6
+                    / HBM_PEAK_GBS)
             pu.close()
             U32 = U.float()
             R32 = torch.empty_like(U32)
@@ -469,13 +512,21 @@ def main():
                 row[key] = dof / time_residual(B, torch, pf, U32, R32, 3) / 1e6
                 if var == B.FR_FUSED:
                     fu_ms, fu_n = B.fr_plan_kernel_stats(pf.handle, 1)
-                    row["fused_kernel_f32_hbm_frac"] = (fused_bytes(p, ne, 4) / (fu_ms / fu_n) / 1e6
-                                                        / HBM_PEAK_GBS)
+                    tr_ms, tr_n = B.fr_plan_kernel_stats(pf.handle, 0)
+                    fms, tms = fu_ms / fu_n, tr_ms / tr_n
+                    row["fused_kernel_f32_floor_frac"] = (floor_bytes(p, ne, 4) / fms / 1e6
+                                                          / HBM_PEAK_GBS)
+                    row["fused_kernel_f32_design_frac"] = (fused_bytes(p, ne, 4) / fms / 1e6
+                                                           / HBM_PEAK_GBS)
+                    row["fused_residual_f32_floor_frac"] = (floor_bytes(p, ne, 4) / (fms + tms)
+                                                            / 1e6 / HBM_PEAK_GBS)
                 pf.close()
             del U32, R32
             torch.cuda.empty_cache()
             row["speedup_fused_vs_unfused_f64"] = row["fused_f64"] / row["unfused_f64"]
             row["speedup_fused_vs_unfused_f32"] = row["fused_f32"] / row["unfused_f32"]
+            # the byte-model bound on that speed-up: unfused bytes / fused-residual bytes
+            row["byte_model_speedup_bound"] = (sum(uv.values()) / BM.fused_residual_values(m))
             sweep[str(p)] = {k: round(v, 4) for k, v in row.items()}
             log("sweep p=%d: %s" % (p, sweep[str(p)]))
 
@@ -526,11 +577,12 @@ def main():
             "learned": round(m["mlp"]["iters_mean"], 2),
             "quadratic_extrap": round(m["extrap"]["iters_mean"], 2),
             "linear_extrap": round(m["extrap1"]["iters_mean"], 2),
-            "learned_with_residual_fallback": round(m["mlp_fallback"]["iters_mean"], 2),
+            "learned_checked": round(m["mlp_fallback"]["iters_mean"], 2),
             "capped": {k: m[v]["capped"] for k, v in (("learned", "mlp"), ("quadratic_extrap", "extrap"),
                                                       ("linear_extrap", "extrap1"))},
-            "learned_vs_quadratic": round(r["mlp_vs_quadratic_iters"], 4),
-            "learned_vs_linear": round(r["mlp_vs_linear_iters"], 4),
+            "learned_vs_quadratic": rnd4(r["mlp_vs_quadratic_iters"]),
+            "learned_vs_linear": rnd4(r["mlp_vs_linear_iters"]),
+            "checked_vs_linear": rnd4(r["checked_vs_linear_iters"]),
             "training_loss": r["loss_curve"][-1][1],
             "seconds": round(t1 - t0, 1),
             "pmg_solver": {
@@ -539,7 +591,7 @@ def main():
                 "learned": round(mp["mlp"]["iters_mean"], 2),
                 "quadratic_extrap": round(mp["extrap"]["iters_mean"], 2),
                 "linear_extrap": round(mp["extrap1"]["iters_mean"], 2),
-                "learned_with_residual_fallback": round(mp["mlp_fallback"]["iters_mean"], 2),
+                "learned_checked": round(mp["mlp_fallback"]["iters_mean"], 2),
                 "capped": {k: mp[v]["capped"] for k, v in (("learned", "mlp"),
                                                            ("quadratic_extrap", "extrap"),
                                                            ("linear_extrap", "extrap1"))},
@@ -549,8 +601,9 @@ def main():
                 "rk4_ms_per_step": {k: round(m[v]["ms_per_step"], 1) for k, v in
                                     (("learned", "mlp"), ("quadratic_extrap", "extrap"),
                                      ("linear_extrap", "extrap1"))},
-                "learned_vs_quadratic": round(rp["mlp_vs_quadratic_iters"], 4),
-                "learned_vs_linear": round(rp["mlp_vs_linear_iters"], 4),
+                "learned_vs_quadratic": rnd4(rp["mlp_vs_quadratic_iters"]),
+                "learned_vs_linear": rnd4(rp["mlp_vs_linear_iters"]),
+                "checked_vs_linear": rnd4(rp["checked_vs_linear_iters"]),
                 "seconds": round(time.perf_counter() - t1, 1)},
             "kernels": kern}
         log("learned guess: %s" % learned)
@@ -580,6 +633,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "paper_context": PAPER_CONTEXT,
         "time_step": timestep,
         "standard_acm_ldg": acm,
         "linear_hexahedra": lhex,

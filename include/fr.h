@@ -56,7 +56,7 @@ typedef enum fr_status {
 
 typedef enum fr_option {
     FR_OPT_PRECISION = 1, /* FR_F64 (default) or FR_F32: working precision of the residual */
-    FR_OPT_VARIANT = 2,   /* FR_FUSED (default) or FR_UNFUSED                              */
+    FR_OPT_VARIANT = 2,   /* FR_FUSED (default), FR_UNFUSED or FR_MFMA (see fr_residual)   */
     FR_OPT_BLOCK = 3,     /* elements per workgroup of the fused kernel; 0 = tuned default  */
     FR_OPT_PROFILE = 4,   /* 1: record HIP events around every kernel launch (see below)   */
     FR_OPT_GUESS_BASE = 5,/* extrapolation the learned guess corrects: 2 quadratic (default),
@@ -98,7 +98,7 @@ typedef enum fr_kernel {
 } fr_kernel;
 
 enum { FR_F64 = 0, FR_F32 = 1 };
-enum { FR_FUSED = 0, FR_UNFUSED = 1 };
+enum { FR_FUSED = 0, FR_UNFUSED = 1, FR_MFMA = 2 };
 
 /*
  * fr_plan_create -- build the 1D operators (Sec. 2.1: Gauss-Legendre solution
@@ -138,7 +138,15 @@ size_t fr_state_len(const fr_plan *plan);
  * FR_FUSED runs two kernels: a face-trace projection (stage 1) and one fused
  * kernel for stages 2-6 (flux, partially corrected divergence, common flux,
  * correction, source); FR_UNFUSED runs the six stages as six kernels through
- * HBM, as in Table 1.  Allocates the plan's trace scratch on first use.
+ * HBM, as in Table 1.  FR_MFMA is FR_FUSED with the partially corrected
+ * divergence and the correction (Table 1 stages 3 and 5; Sec. 4 treats the
+ * operator application as a small matrix multiplication) applied on the
+ * matrix cores: per direction, the m x (m + 2) block [Dt | g_L' | g_R']
+ * multiplies, for a batch of 16 element lines at a time, each line's m values
+ * followed by its two common interface values, in single-precision operands
+ * with single-precision accumulation (v_mfma_f32_16x16x4f32).  It requires
+ * FR_F32 (FR_EUNSUPPORTED in FR_F64); fr_rk_step and fr_dual_step then use the
+ * separate stage kernel.  Allocates the plan's trace scratch on first use.
  */
 int fr_residual(fr_plan *plan, const void *U, void *R, fr_stream_t s);
 

@@ -17,7 +17,7 @@ KERNELS = ("trace", "fused", "u_project", "u_flux", "u_div", "u_common", "u_corr
            "u_negsrc", "stage")
 FR_F64, FR_F32 = 0, 1
 FR_K_TRACE, FR_K_FUSED = 0, 1
-FR_FUSED, FR_UNFUSED = 0, 1
+FR_FUSED, FR_UNFUSED, FR_MFMA = 0, 1, 2
 NV = 13
 
 EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_destroy",

@@ -30,8 +30,7 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb)
 
 int residual(fr_plan *pl, const void *U, void *R, hipStream_t s)
 {
-    return pl->variant == FR_FUSED ? launch_residual_fused(pl, U, R, s)
-                                   : launch_residual_unfused(pl, U, R, s);
+    return launch_residual(pl, U, R, s);
 }
 
 struct RkBufs {
@@ -114,6 +113,16 @@ int graph_run(fr_plan *pl, GraphCache &gc, const uint64_t (&key)[20], hipStream_
 }  // namespace
 
 namespace fr {
+
+int launch_residual(fr_plan *pl, const void *U, void *R, hipStream_t s)
+{
+    switch (pl->variant) {
+        case FR_FUSED: return launch_residual_fused(pl, U, R, s);
+        case FR_UNFUSED: return launch_residual_unfused(pl, U, R, s);
+        case FR_MFMA: return launch_residual_mfma(pl, U, R, s);
+    }
+    return set_error(FR_EINVAL, "variant %d", pl->variant);
+}
 
 int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const double *D,
                    double dtau, double tol, int max_iters, int check_every, bool norm_last,

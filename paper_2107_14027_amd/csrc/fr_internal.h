@@ -105,8 +105,8 @@ struct fr_plan {
     fr::GraphCache graphs[3];
     // persistent grid sizes of the fused path on this plan's device, per
     // (order, precision, diagonal Jacobian): [0] trace kernel, [1] fused kernel,
-    // [2] fused kernel with the stage epilogue
-    int fused_grid[3][fr::PMAX + 1][2][2] = {};
+    // [2] fused kernel with the stage epilogue, [3] its matrix-core form
+    int fused_grid[4][fr::PMAX + 1][2][2] = {};
     int device;
     // host copies of the operators (double)
     double x[8], w[8], D[64], lm[8], lp[8], gl[8], gr[8], Dt[64];
@@ -154,11 +154,15 @@ void graphs_reset(fr_plan *pl);
 // launchers (return FR_OK or an error code)
 int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s);
 int launch_residual_unfused(fr_plan *pl, const void *U, void *R, hipStream_t s);
+int launch_residual_mfma(fr_plan *pl, const void *U, void *R, hipStream_t s);
+// the residual of the plan's variant (fused, unfused or matrix-core)
+int launch_residual(fr_plan *pl, const void *U, void *R, hipStream_t s);
 // fused residual of U followed by the stage update sp (no residual array);
 // *nparts receives the number of partial sums written when sp.partial is set
 int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *nparts,
                           hipStream_t s);
 bool fused_stage_available(const fr_plan *pl);
+
 
 // Up to max_iters classical RK4 pseudo-steps of dU/dtau = R(U) - M_V (a U + B)
 // + D (D may be null) on plan pl, from U (double, in place).  The RMS of the

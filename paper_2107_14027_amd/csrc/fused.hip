@@ -525,11 +525,12 @@ template <int P, typename T, bool DIAG> struct StageEpilogue {
         LineDiv<P, DIAG>::value || Shape<P, T>::EMAX * NS <= Shape<P, T>::NT;
 };
 
-template <int P, typename T, bool DIAG, bool STG>
+template <int P, typename T, bool DIAG, bool STG, bool MF = false>
 __global__ void __launch_bounds__((Shape<P, T>::NT))
     k_fused(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
             const T *__restrict__ ops, Consts<T> c, int ne, int E, int nbatch, StageSpec sp)
 {
+    static_assert(!MF || (sizeof(T) == 4 && !STG), "matrix-core form: single precision residual");
     constexpr int M = P + 1, NS = M * M * M, NF = M * M;
     using TL = TraceLayout<M, T>;
     constexpr int CHP = TL::CHP;
@@ -559,6 +560,21 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
     const T *Dt = sop + OL::Dt;
     const T *gl = sop + OL::gl;
     const T *gr = sop + OL::gr;
+    // MF: this lane's A operands of [Dt | gl | gr] (rows i = lane % 16, K rows
+    // 4 s + lane / 16; zero outside the m x (m + 2) block)
+    constexpr int KS = (M + 2 + 3) / 4;
+    T amf[MF ? KS : 1];
+    if constexpr (MF) {
+        const int i = threadIdx.x & 15, kq = (threadIdx.x & 63) >> 4;
+#pragma unroll
+        for (int st2 = 0; st2 < KS; ++st2) {
+            const int kap = 4 * st2 + kq;
+            amf[st2] = i >= M ? T(0)
+                              : (kap < M ? ops[OL::Dt + i * M + kap]
+                                         : (kap == M ? ops[OL::gl + i]
+                                                     : (kap == M + 1 ? ops[OL::gr + i] : T(0))));
+        }
+    }
     // STG: sum of (k*_V)^2 over this workgroup's stage updates
     double ss = 0.0;
     for (; b < nbatch; b += gridDim.x) {
@@ -638,67 +654,89 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
         //      at once (stored over S, which is no longer needed) and the
         //      divergence (accumulated over P); flux derivatives are stored over
         //      the consumed flux values.  A final pass writes R.
-        if constexpr (LineDiv<P, DIAG>::value) {
-            constexpr int NTASK = EMAX * 6 * NF;
-            constexpr int TPT = (NTASK + NT - 1) / NT;
-            const int ntask = nel * 6 * NF;
-            const T *gD = ops + OL::Dt;   // uniform operator entries
-            const T *gL = ops + OL::gl;
-            const T *gR = ops + OL::gr;
+        if constexpr (MF) {
+            // ---- stages 3, 5, 6 on the matrix cores (FP32 operands, FP32
+            //      accumulation).  Per direction the corrected derivative of a
+            //      line is [Dt | gl | gr] (m x (m + 2)) times the line's m values
+            //      followed by its two common-flux values; 16 lines (element,
+            //      face point) are the 16 columns of one v_mfma_f32_16x16x4f32
+            //      chain over K = m + 2 (padded to a multiple of 4), one chain per
+            //      field (the three velocities and the direction's three
+            //      transformed momentum fluxes).  Lane l owns column l % 16: it
+            //      supplies that line's K rows 4 s + l / 16 and receives output
+            //      rows 4 (l / 16) + t.  Velocity derivatives update the auxiliary
+            //      slots (S - (1/det J) sum_d n_d,k du_a/dxi_d, over S) and the
+            //      velocity divergence (over P); flux derivatives replace the
+            //      consumed flux values; a final pass writes R.
+            constexpr int NGMAX = (EMAX * NF + 15) / 16;
+            constexpr int NW = NT / 64;
+            constexpr int GPW = (NGMAX + NW - 1) / NW;
+            typedef float v4f __attribute__((ext_vector_type(4)));
+            const int lane = tid & 63, wv = tid >> 6, qt = lane >> 4, cl = lane & 15;
+            const int ncol = nel * NF;
             auto direction = [&](auto dc) {
                 constexpr int d = decltype(dc)::value;
                 constexpr int str = d == 0 ? 1 : (d == 1 ? M : M * M);
-                T outv[TPT][M];
+                v4f out[GPW][6];
 #pragma unroll
-                for (int u = 0; u < TPT; ++u) {
-                    const unsigned t = tid + u * NT;
-                    if ((int)t < ntask) {
-                        const unsigned el = t / (6 * NF), r = t - el * (6 * NF);
-                        const unsigned f = r / NF, L = r - f * NF;
-                        const unsigned a = L % M, bb = L / M;
-                        const unsigned base = d == 0 ? M * L : (d == 1 ? a + M * M * bb : L);
+                for (int u = 0; u < GPW; ++u) {
+                    const int col = (wv + u * NW) * 16 + cl;
+                    const bool ok = col < ncol;
+                    const int el = ok ? col / NF : 0, L = ok ? col - el * NF : 0;
+                    const int a = L % M, bb = L / M;
+                    const int base = d == 0 ? M * L : (d == 1 ? a + M * M * bb : L);
+                    const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + L;
+#pragma unroll
+                    for (int f = 0; f < 6; ++f) {
                         const T *fld = f < 3 ? sU + (el * NV + 1 + f) * NS
                                              : sF + (el * 9 + 3 * d + f - 3) * NS;
-                        const unsigned comp = f < 3 ? 4 + f : f - 2;
-                        const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + comp * NF + L;
-                        const T fm = FIm[0], fpl = FIm[EMAX * CHP];
-                        T in[M];
+                        const int comp = f < 3 ? 4 + f : f - 2;
+                        v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                        for (int l = 0; l < M; ++l) in[l] = fld[base + l * str];
-#pragma unroll
-                        for (int i = 0; i < M; ++i) {
-                            T v = T(0);
-#pragma unroll
-                            for (int l = 0; l < M; ++l) v = fma(gD[i * M + l], in[l], v);
-                            outv[u][i] = fma(gL[i], fm, fma(gR[i], fpl, v));
+                        for (int st2 = 0; st2 < KS; ++st2) {
+                            const int kap = 4 * st2 + qt;
+                            T bv = T(0);
+                            if (ok) {
+                                if (kap < M) bv = fld[base + kap * str];
+                                else if (kap == M) bv = FIm[comp * NF];
+                                else if (kap == M + 1) bv = FIm[EMAX * CHP + comp * NF];
+                            }
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(amf[st2], bv, acc, 0, 0, 0);
                         }
+                        out[u][f] = acc;
                     }
                 }
                 __syncthreads();  // every read of this direction's flux values is done
-                const T ndd = c.nvec[d][d];
+                const T nv[3] = {c.nvec[d][0], c.nvec[d][1], c.nvec[d][2]};
 #pragma unroll
-                for (int u = 0; u < TPT; ++u) {
-                    const unsigned t = tid + u * NT;
-                    if ((int)t < ntask) {
-                        const unsigned el = t / (6 * NF), r = t - el * (6 * NF);
-                        const unsigned f = r / NF, L = r - f * NF;
-                        const unsigned a = L % M, bb = L / M;
-                        const unsigned base = d == 0 ? M * L : (d == 1 ? a + M * M * bb : L);
-                        T *Ue = sU + el * NV * NS;
-                        if (f < 3) {
-                            // g[3f+d] = n_dd (corrected d u_f / d xi_d); aux residual (f, d)
+                for (int u = 0; u < GPW; ++u) {
+                    const int col = (wv + u * NW) * 16 + cl;
+                    if (col >= ncol) continue;
+                    const int el = col / NF, L = col - el * NF;
+                    const int a = L % M, bb = L / M;
+                    const int base = d == 0 ? M * L : (d == 1 ? a + M * M * bb : L);
+                    T *Ue = sU + el * NV * NS;
+                    T *Fe = sF + el * 9 * NS;
 #pragma unroll
-                            for (int i = 0; i < M; ++i) {
-                                const unsigned q = base + i * str;
-                                const T gv = outv[u][i] * ndd;
-                                T *sq = Ue + (4 + 3 * f + d) * NS + q;
-                                *sq = c.invT * fma(c.inv_det, gv, -*sq);
-                                if ((int)f == d) Ue[q] = d == 0 ? gv : Ue[q] + gv;
+                    for (int t = 0; t < 4; ++t) {
+                        const int i = 4 * qt + t;
+                        if (i < M) {
+                            const int q = base + i * str;
+                            T dv = T(0);
+#pragma unroll
+                            for (int f = 0; f < 3; ++f) {
+                                const T cd = out[u][f][t];
+#pragma unroll
+                                for (int k = 0; k < 3; ++k) {
+                                    if (DIAG && k != d) continue;
+                                    T *slot = Ue + (4 + 3 * f + k) * NS + q;
+                                    *slot = fma(-c.inv_det * nv[k], cd, *slot);
+                                }
+                                if (!DIAG || f == d) dv = fma(nv[f], cd, dv);
                             }
-                        } else {
-                            T *Fq = sF + (el * 9 + 3 * d + f - 3) * NS + base;
+                            Ue[q] = d == 0 ? dv : Ue[q] + dv;
 #pragma unroll
-                            for (int i = 0; i < M; ++i) Fq[i * str] = outv[u][i];
+                            for (int a2 = 0; a2 < 3; ++a2) Fe[(3 * d + a2) * NS + q] = out[u][3 + a2][t];
                         }
                     }
                 }
@@ -720,7 +758,110 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
                     const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + fp;
                     dissP = fma(gl[id], FIm[0], fma(gr[id], FIm[EMAX * CHP], dissP));
                 }
-                const T rP = -c.inv_det * fma(c.zeta, Ue[q], dissP);
+                T *Re = R + ((int64_t)(e0 + el) * NV) * NS + q;
+                __builtin_nontemporal_store(-c.inv_det * fma(c.zeta, Ue[q], dissP), Re);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    __builtin_nontemporal_store(
+                        -c.inv_det * ((Fe[a * NS + q] + Fe[(3 + a) * NS + q]) + Fe[(6 + a) * NS + q]),
+                        Re + (1 + a) * NS);
+#pragma unroll
+                for (int k = 0; k < 9; ++k)
+                    __builtin_nontemporal_store(-c.invT * Ue[(4 + k) * NS + q], Re + (4 + k) * NS);
+            }
+        } else if constexpr (LineDiv<P, DIAG>::value) {
+            // The three directions' tasks (direction, element, field, line) are
+            // read in one phase (882 tasks on 256 threads at p = 6: four passes
+            // instead of two per direction) and written after one barrier: flux
+            // derivatives over the consumed flux values, auxiliary residuals over
+            // S, and each direction's velocity-divergence term n_dd du_d/dxi_d
+            // over the velocity u_d, which no task reads any more; the final pass
+            // sums the three terms in direction order.
+            constexpr int NTD = EMAX * 6 * NF;
+            constexpr int TPT = (3 * NTD + NT - 1) / NT;
+            const int ntd = nel * 6 * NF;
+            const T *gD = ops + OL::Dt;   // uniform operator entries
+            const T *gL = ops + OL::gl;
+            const T *gR = ops + OL::gr;
+            // task t -> direction, element, field, line; first point and stride of the line
+            auto decode = [&](unsigned t, unsigned &d, unsigned &el, unsigned &f, unsigned &L,
+                              unsigned &base, unsigned &str) {
+                d = t / ntd;
+                const unsigned r0 = t - d * ntd;
+                el = r0 / (6 * NF);
+                const unsigned r = r0 - el * (6 * NF);
+                f = r / NF;
+                L = r - f * NF;
+                const unsigned a = L % M, bb = L / M;
+                str = d == 0 ? 1u : (d == 1 ? (unsigned)M : (unsigned)(M * M));
+                base = d == 0 ? M * L : (d == 1 ? a + M * M * bb : L);
+            };
+            T outv[TPT][M];
+#pragma unroll
+            for (int u = 0; u < TPT; ++u) {
+                const unsigned t = tid + u * NT;
+                if ((int)t < 3 * ntd) {
+                    unsigned d, el, f, L, base, str;
+                    decode(t, d, el, f, L, base, str);
+                    const T *fld = f < 3 ? sU + (el * NV + 1 + f) * NS
+                                         : sF + (el * 9 + 3 * d + f - 3) * NS;
+                    const unsigned comp = f < 3 ? 4 + f : f - 2;
+                    const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + comp * NF + L;
+                    const T fm = FIm[0], fpl = FIm[EMAX * CHP];
+                    T in[M];
+#pragma unroll
+                    for (int l = 0; l < M; ++l) in[l] = fld[base + l * str];
+#pragma unroll
+                    for (int i = 0; i < M; ++i) {
+                        T v = T(0);
+#pragma unroll
+                        for (int l = 0; l < M; ++l) v = fma(gD[i * M + l], in[l], v);
+                        outv[u][i] = fma(gL[i], fm, fma(gR[i], fpl, v));
+                    }
+                }
+            }
+            __syncthreads();  // every read of the velocities and flux values is done
+#pragma unroll
+            for (int u = 0; u < TPT; ++u) {
+                const unsigned t = tid + u * NT;
+                if ((int)t < 3 * ntd) {
+                    unsigned d, el, f, L, base, str;
+                    decode(t, d, el, f, L, base, str);
+                    T *Ue = sU + el * NV * NS;
+                    if (f < 3) {
+                        // g[3f+d] = n_dd (corrected d u_f / d xi_d); aux residual (f, d)
+                        const T ndd = d == 0 ? c.nvec[0][0] : (d == 1 ? c.nvec[1][1] : c.nvec[2][2]);
+#pragma unroll
+                        for (int i = 0; i < M; ++i) {
+                            const unsigned q = base + i * str;
+                            const T gv = outv[u][i] * ndd;
+                            T *sq = Ue + (4 + 3 * f + d) * NS + q;
+                            *sq = c.invT * fma(c.inv_det, gv, -*sq);
+                            if (f == d) Ue[(1 + d) * NS + q] = gv;
+                        }
+                    } else {
+                        T *Fq = sF + (el * 9 + 3 * d + f - 3) * NS + base;
+#pragma unroll
+                        for (int i = 0; i < M; ++i) Fq[i * str] = outv[u][i];
+                    }
+                }
+            }
+            __syncthreads();
+            for (unsigned t = tid; t < (unsigned)nel * NS; t += NT) {
+                const unsigned el = t / NS, q = t - el * NS;
+                const unsigned qi = q % M, qj = (q / M) % M, qk = q / (M * M);
+                const T *Ue = sU + el * NV * NS;
+                const T *Fe = sF + el * 9 * NS;
+                T dissP = T(0);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const unsigned id = d == 0 ? qi : (d == 1 ? qj : qk);
+                    const unsigned fp = d == 0 ? qj + M * qk : (d == 1 ? qi + M * qk : qi + M * qj);
+                    const T *FIm = sFI + ((2 * d) * EMAX + el) * CHP + fp;
+                    dissP = fma(gl[id], FIm[0], fma(gr[id], FIm[EMAX * CHP], dissP));
+                }
+                const T divV = (Ue[NS + q] + Ue[2 * NS + q]) + Ue[3 * NS + q];
+                const T rP = -c.inv_det * fma(c.zeta, divV, dissP);
                 T rm[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
@@ -913,9 +1054,9 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 // ---------------------------------------------------------------------------
 // launch
 // ---------------------------------------------------------------------------
-template <int P, typename T, bool DIAG>
+template <int P, typename T, bool DIAG, bool MF>
 int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, T *TR,
-               const T *ops, const Consts<T> &c, hipStream_t s)
+               const T *ops, const Consts<T> &c, hipStream_t s, bool prof)
 {
     constexpr int M = P + 1, NS = M * M * M;
     constexpr int CHP = TraceLayout<M, T>::CHP;
@@ -940,6 +1081,10 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
     const void *kfu = (const void *)k_fused<P, T, DIAG, false>;
     if constexpr (STG_OK)
         if (sp) kfu = (const void *)k_fused<P, T, DIAG, true>;
+    if constexpr (MF) {
+        if (sp) return set_error(FR_EUNSUPPORTED, "matrix-core variant: no stage epilogue");
+        kfu = (const void *)k_fused<P, T, DIAG, false, true>;
+    }
     // persistent grid: every workgroup that fits on the device at once
     auto persistent_grid = [&](const void *fn, int nt, size_t lds, int &grid) -> int {
         if (grid) return FR_OK;
@@ -960,24 +1105,27 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
         return FR_OK;
     };
     int &grid_tr = pl->fused_grid[0][P][sizeof(T) == 8][DIAG];
-    int &grid_fu = pl->fused_grid[sp ? 2 : 1][P][sizeof(T) == 8][DIAG];
+    int &grid_fu = pl->fused_grid[MF ? 3 : (sp ? 2 : 1)][P][sizeof(T) == 8][DIAG];
     if (int rc = persistent_grid(ktr, TNT, lds_tr, grid_tr)) return rc;
     if (int rc = persistent_grid(kfu, NT, lds_fu, grid_fu)) return rc;
     const unsigned gtr = (unsigned)min(nbatch_tr, grid_tr);
     const unsigned gfu = (unsigned)min(min(nbatch, grid_fu), sp ? MAX_PARTIALS : grid_fu);
     {
-        ProfScope ps(pl, FR_K_TRACE, s);
+        ProfScope ps(prof ? pl : nullptr, FR_K_TRACE, s);
         hipLaunchKernelGGL((k_trace<P, T, DIAG>), dim3(gtr), dim3(TNT), lds_tr, s, U, TR, ops, c,
                            pl->nx, pl->ny, pl->nz, TE, nbatch_tr);
     }
     {
-        ProfScope ps(pl, FR_K_FUSED, s);
+        ProfScope ps(prof ? pl : nullptr, FR_K_FUSED, s);
         if (sp) {
             if constexpr (STG_OK) {
                 if (nparts) *nparts = (int)gfu;
                 hipLaunchKernelGGL((k_fused<P, T, DIAG, true>), dim3(gfu), dim3(NT), lds_fu, s, U,
                                    TR, (T *)nullptr, ops, c, ne, E, nbatch, *sp);
             }
+        } else if constexpr (MF) {
+            hipLaunchKernelGGL((k_fused<P, T, DIAG, false, true>), dim3(gfu), dim3(NT), lds_fu, s, U,
+                               TR, R, ops, c, ne, E, nbatch, StageSpec{});
         } else {
             hipLaunchKernelGGL((k_fused<P, T, DIAG, false>), dim3(gfu), dim3(NT), lds_fu, s, U, TR,
                                R, ops, c, ne, E, nbatch, StageSpec{});
@@ -986,15 +1134,15 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
     return check_hip(hipGetLastError(), "fused residual launch");
 }
 
-template <typename T>
+template <typename T, bool MF = false>
 int dispatch_fused(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, T *TR,
-                   const T *ops, const Consts<T> &c, hipStream_t s)
+                   const T *ops, const Consts<T> &c, hipStream_t s, bool prof)
 {
     const bool dg = c.diag != 0;
 #define FR_CASE(PP)                                                                        \
     case PP:                                                                               \
-        return dg ? fused_impl<PP, T, true>(pl, U, R, sp, nparts, TR, ops, c, s)           \
-                  : fused_impl<PP, T, false>(pl, U, R, sp, nparts, TR, ops, c, s);
+        return dg ? fused_impl<PP, T, true, MF>(pl, U, R, sp, nparts, TR, ops, c, s, prof) \
+                  : fused_impl<PP, T, false, MF>(pl, U, R, sp, nparts, TR, ops, c, s, prof);
     switch (pl->p) {
         FR_CASE(1)
         FR_CASE(2)
@@ -1007,22 +1155,40 @@ int dispatch_fused(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *npar
     return set_error(FR_EINVAL, "order %d", pl->p);
 }
 
-int fused_any(fr_plan *pl, const void *U, void *R, const StageSpec *sp, int *nparts,
-              hipStream_t s)
+// Bytes of the face-trace array of the fused path.
+size_t trace_bytes(const fr_plan *pl)
 {
     const int m = pl->m;
     const size_t esz = pl->precision == FR_F64 ? 8 : 4;
     const size_t w = 16 / esz;
     const size_t chp = (NTR * m * m + w - 1) / w * w;
-    const size_t tr_bytes = (size_t)6 * pl->ne * chp * esz;
-    if (int rc = ensure_scratch(pl->traces, tr_bytes)) return rc;
+    return (size_t)6 * pl->ne * chp * esz;
+}
+
+// The fused residual (or stage) with its face traces in TR: the plan's own
+// scratch (allocated on first use) when TR is null.  prof = false skips the
+// per-kernel event timing.
+int fused_any(fr_plan *pl, const void *U, void *R, const StageSpec *sp, int *nparts,
+              hipStream_t s, void *TR = nullptr, bool prof = true, bool mf = false)
+{
+    if (!TR) {
+        if (int rc = ensure_scratch(pl->traces, trace_bytes(pl))) return rc;
+        TR = pl->traces.ptr;
+    }
+    if (mf) {
+        if (pl->precision != FR_F32)
+            return set_error(FR_EUNSUPPORTED,
+                             "the matrix-core variant computes in single precision (FR_F32)");
+        return dispatch_fused<float, true>(pl, (const float *)U, (float *)R, sp, nparts, (float *)TR,
+                                           (const float *)pl->ops32, pl->c32, s, prof);
+    }
     if (pl->precision == FR_F64)
         return dispatch_fused<double>(pl, (const double *)U, (double *)R, sp, nparts,
-                                      (double *)pl->traces.ptr, (const double *)pl->ops64,
-                                      pl->c64, s);
-    return dispatch_fused<float>(pl, (const float *)U, (float *)R, sp, nparts,
-                                 (float *)pl->traces.ptr, (const float *)pl->ops32, pl->c32, s);
+                                      (double *)TR, (const double *)pl->ops64, pl->c64, s, prof);
+    return dispatch_fused<float>(pl, (const float *)U, (float *)R, sp, nparts, (float *)TR,
+                                 (const float *)pl->ops32, pl->c32, s, prof);
 }
+
 
 }  // namespace
 
@@ -1030,6 +1196,12 @@ int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s)
 {
     return fused_any(pl, U, R, nullptr, nullptr, s);
 }
+
+int launch_residual_mfma(fr_plan *pl, const void *U, void *R, hipStream_t s)
+{
+    return fused_any(pl, U, R, nullptr, nullptr, s, nullptr, true, true);
+}
+
 
 bool fused_stage_available(const fr_plan *pl)
 {

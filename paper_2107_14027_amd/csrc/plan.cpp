@@ -366,7 +366,7 @@ int fr_plan_set_int(fr_plan *pl, int key, int value)
             pl->precision = value;
             return FR_OK;
         case FR_OPT_VARIANT:
-            if (value != FR_FUSED && value != FR_UNFUSED)
+            if (value != FR_FUSED && value != FR_UNFUSED && value != FR_MFMA)
                 return set_error(FR_EINVAL, "variant %d", value);
             pl->variant = value;
             return FR_OK;

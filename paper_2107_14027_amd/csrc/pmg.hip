@@ -128,8 +128,7 @@ int pseudo_residual(fr_plan *pl, const double *U, const double *B, const double 
     void *k = (char *)st + n * esz;
     if (!f64)
         if (int rc = launch_to_precision(pl, U, st, n, s)) return rc;
-    const int rc = pl->variant == FR_FUSED ? launch_residual_fused(pl, f64 ? (const void *)U : st, k, s)
-                                           : launch_residual_unfused(pl, f64 ? (const void *)U : st, k, s);
+    const int rc = launch_residual(pl, f64 ? (const void *)U : st, k, s);
     if (rc) return rc;
     if (f64)
         hipLaunchKernelGGL(k_pseudo<double>, dim3(grid_of(n)), dim3(TBP), 0, s, (const double *)k, U,

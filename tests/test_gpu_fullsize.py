@@ -44,7 +44,8 @@ def test_order_sweep_full_size_sampled(p):
     Ro = {B.FR_F64: oracle.residual_elems(p, n, Uh, sel, ZETA, NU, TRELAX),
           B.FR_F32: oracle.residual_elems(p, n, Uh.astype(np.float32).astype(np.float64), sel,
                                           ZETA, NU, TRELAX)}
-    for prec, var in ((B.FR_F64, B.FR_FUSED), (B.FR_F32, B.FR_FUSED), (B.FR_F64, B.FR_UNFUSED)):
+    for prec, var in ((B.FR_F64, B.FR_FUSED), (B.FR_F32, B.FR_FUSED), (B.FR_F64, B.FR_UNFUSED),
+                      (B.FR_F32, B.FR_MFMA)):
         plan = B.Plan(p, n, ZETA, NU, TRELAX, precision=prec, variant=var)
         U = Ud if prec == B.FR_F64 else Ud.float()
         R = torch.empty_like(U)
@@ -71,8 +72,8 @@ def test_manufactured_64cubed_p4_sampled():
           B.FR_F32: oracle.residual_elems(p, n, U.astype(np.float32).astype(np.float64), sel,
                                           ZETA, NU, TRELAX)}
     Ud = torch.from_numpy(U).to("cuda")
-    for prec in (B.FR_F64, B.FR_F32):
-        plan = B.Plan(p, n, ZETA, NU, TRELAX, precision=prec)
+    for prec, var in ((B.FR_F64, B.FR_FUSED), (B.FR_F32, B.FR_FUSED), (B.FR_F32, B.FR_MFMA)):
+        plan = B.Plan(p, n, ZETA, NU, TRELAX, precision=prec, variant=var)
         Ui = Ud if prec == B.FR_F64 else Ud.float()
         R = torch.empty_like(Ui)
         B.fr_residual(plan.handle, Ui, R)
@@ -80,9 +81,9 @@ def test_manufactured_64cubed_p4_sampled():
         Rs = R[torch.from_numpy(sel).to("cuda")].double().cpu().numpy()
         plan.close()
         del R
-        say("  prec=%d rel %.2e" % (prec, rel(Rs, Ro[prec])))
+        say("  prec=%d var=%d rel %.2e" % (prec, var, rel(Rs, Ro[prec])))
         assert rel(Rs, Ro[prec]) <= TOL[prec]
-        check_groups(Rs, Ro[prec], prec, U[sel], what="manufactured prec=%d" % prec)
+        check_groups(Rs, Ro[prec], prec, U[sel], what="manufactured prec=%d var=%d" % (prec, var))
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
