@@ -151,6 +151,22 @@ size_t fr_state_len(const fr_plan *plan);
 int fr_residual(fr_plan *plan, const void *U, void *R, fr_stream_t s);
 
 /*
+ * fr_residual_noalloc -- fr_residual for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and kernels as fr_residual in the
+ * FR_FUSED or FR_MFMA variant, but the face traces go to a fixed array of
+ * 64 MiB that the library holds on every device it runs on (until the process
+ * ends) instead of the plan's scratch; it calls no allocating routine.
+ * Limit: 6 * ne * ceil16(7 (p+1)^2) values of the plan's precision must fit in
+ * 64 MiB (at p = 3: 12,483 elements in FP64, 24,966 in FP32); larger plans get
+ * FR_EINVAL before any work is enqueued, FR_UNFUSED gets FR_EUNSUPPORTED.  All
+ * calls on one device share the array, so calls that overlap in time on one
+ * device (two streams, two threads) race; calls ordered on one stream do not.
+ * Nothing in the array needs clearing: every call writes each trace it reads.
+ */
+int fr_residual_noalloc(fr_plan *plan, const void *U, void *R, fr_stream_t s);
+
+/*
  * fr_rk_step -- nsteps classical fourth-order Runge-Kutta steps of size dt of
  * dU/dtau = R(U) on all 13 variables.  U is a double state array updated in
  * place; the stage accumulators are double; in FR_F32 precision each stage

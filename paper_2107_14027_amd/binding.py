@@ -28,7 +28,7 @@ EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_des
             "fr_pmg_create", "fr_pmg_dual_step", "fr_pmg_destroy", "fr_diagnostics",
             "fr_acm_create", "fr_acm_residual", "fr_acm_gradient", "fr_acm_dual_step",
             "fr_acm_destroy", "fr_lhex_create", "fr_lhex_residual", "fr_lhex_destroy",
-            "fr_launch_shape", "fr_mlp_guess_checked")
+            "fr_launch_shape", "fr_mlp_guess_checked", "fr_residual_noalloc")
 
 
 class FrError(RuntimeError):
@@ -59,6 +59,7 @@ def lib():
         L.fr_state_len.argtypes = [_vp]
         L.fr_state_len.restype = ctypes.c_size_t
         L.fr_residual.argtypes = [_vp, _vp, _vp, _vp]
+        L.fr_residual_noalloc.argtypes = [_vp, _vp, _vp, _vp]
         L.fr_rk_step.argtypes = [_vp, _vp, D, I, _vp]
         L.fr_dual_step.argtypes = [_vp, _vp, _vp, _vp, D, D, D, I, I, ctypes.POINTER(I), _dp, _vp]
         L.fr_guess_extrap.argtypes = [_vp, _vp, _vp, _vp, I, _vp, _vp]
@@ -176,6 +177,14 @@ def fr_residual(plan, U, R, stream=None):
     dt = torch.float64 if fr_plan_get_int(plan, FR_OPT_PRECISION) == FR_F64 else torch.float32
     return _check(lib().fr_residual(plan, _dev(U, dt, n, "U"), _dev(R, dt, n, "R"),
                                     _stream(stream)))
+
+
+def fr_residual_noalloc(plan, U, R, stream=None):
+    import torch
+    n = fr_state_len(plan)
+    dt = torch.float64 if fr_plan_get_int(plan, FR_OPT_PRECISION) == FR_F64 else torch.float32
+    return _check(lib().fr_residual_noalloc(plan, _dev(U, dt, n, "U"), _dev(R, dt, n, "R"),
+                                            _stream(stream)))
 
 
 def fr_rk_step(plan, U, dt, nsteps, stream=None):

@@ -301,6 +301,17 @@ int fr_residual(fr_plan *pl, const void *U, void *R, fr_stream_t s)
     return residual(pl, U, R, (hipStream_t)s);
 }
 
+int fr_residual_noalloc(fr_plan *pl, const void *U, void *R, fr_stream_t s)
+{
+    if (!pl) return set_error(FR_EINVAL, "fr_residual_noalloc: NULL plan");
+    if (int rc = check_array(U, "U")) return rc;
+    if (int rc = check_array(R, "R")) return rc;
+    const size_t bytes = fr_state_len(pl) * esize(pl);
+    if (overlap(U, bytes, R, bytes))
+        return set_error(FR_EINVAL, "fr_residual_noalloc: U and R overlap");
+    return launch_residual_noalloc(pl, U, R, (hipStream_t)s);
+}
+
 int fr_rk_step(fr_plan *pl, double *U, double dt, int nsteps, fr_stream_t sv)
 {
     if (!pl) return set_error(FR_EINVAL, "fr_rk_step: NULL plan");

@@ -155,6 +155,11 @@ void graphs_reset(fr_plan *pl);
 int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s);
 int launch_residual_unfused(fr_plan *pl, const void *U, void *R, hipStream_t s);
 int launch_residual_mfma(fr_plan *pl, const void *U, void *R, hipStream_t s);
+// the fused (or matrix-core) residual with its face traces in the library's
+// fixed per-device array; no allocation.  scratch_setup looks that array's
+// address up on device dev (once per device, with dev current).
+int launch_residual_noalloc(fr_plan *pl, const void *U, void *R, hipStream_t s);
+int scratch_setup(int dev);
 // the residual of the plan's variant (fused, unfused or matrix-core)
 int launch_residual(fr_plan *pl, const void *U, void *R, hipStream_t s);
 // fused residual of U followed by the stage update sp (no residual array);

@@ -17,6 +17,8 @@
 // and prefetch the next batch's global data into registers before computing
 // the current one, so every workgroup keeps a batch of loads in flight while
 // it works on LDS; the grid is sized to the number of co-resident workgroups.
+#include <mutex>
+
 #include "fr_device.h"
 
 namespace fr {
@@ -1200,6 +1202,50 @@ int launch_residual_fused(fr_plan *pl, const void *U, void *R, hipStream_t s)
 int launch_residual_mfma(fr_plan *pl, const void *U, void *R, hipStream_t s)
 {
     return fused_any(pl, U, R, nullptr, nullptr, s, nullptr, true, true);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free residual: the face traces go to a fixed device array of
+// SCRATCH_BYTES instead of the plan's scratch.  Every device holds its own
+// copy of the array; host code never uses the array's name (a host-side
+// stand-in), only the device address looked up once per device.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+static std::mutex scratch_mu;
+static void *scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+int scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return set_error(FR_EUNSUPPORTED, "device %d: at most %d devices", dev, SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_ptr[dev]) return FR_OK;
+    void *ptr = nullptr;
+    if (int rc = check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))
+        return rc;
+    scratch_ptr[dev] = ptr;
+    return FR_OK;
+}
+
+int launch_residual_noalloc(fr_plan *pl, const void *U, void *R, hipStream_t s)
+{
+    if (pl->variant != FR_FUSED && pl->variant != FR_MFMA)
+        return set_error(FR_EUNSUPPORTED, "fr_residual_noalloc: fused or matrix-core variant only");
+    const size_t need = trace_bytes(pl);
+    if (need > SCRATCH_BYTES)
+        return set_error(FR_EINVAL,
+                         "fr_residual_noalloc: the face traces need %zu bytes, the fixed array holds "
+                         "%zu (at most about %zu elements at this order and precision)",
+                         need, SCRATCH_BYTES, (size_t)(SCRATCH_BYTES / (need / pl->ne)));
+    void *ptr = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        if (pl->device >= 0 && pl->device < SCRATCH_MAX_DEVICES) ptr = scratch_ptr[pl->device];
+    }
+    if (!ptr) return set_error(FR_EHIP, "fr_residual_noalloc: no trace array on device %d", pl->device);
+    return fused_any(pl, U, R, nullptr, nullptr, s, ptr, false, pl->variant == FR_MFMA);
 }
 
 

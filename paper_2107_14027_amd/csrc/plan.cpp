@@ -327,7 +327,7 @@ fr_plan *fr_plan_create(int p, int nx, int ny, int nz, const double jac[9], doub
     fill_consts(pl, pl->c64);
     fill_consts(pl, pl->c32);
 
-    if (check_hip(hipGetDevice(&pl->device), "hipGetDevice")) {
+    if (check_hip(hipGetDevice(&pl->device), "hipGetDevice") || fr::scratch_setup(pl->device)) {
         delete pl;
         return nullptr;
     }

@@ -43,6 +43,7 @@ def test_strerror_and_invalid_arguments_fail_before_device_work():
         assert ei.value.code == B.FR_EINVAL
     L = B.lib()
     assert L.fr_residual(None, None, None, None) == B.FR_EINVAL
+    assert L.fr_residual_noalloc(None, None, None, None) == B.FR_EINVAL
     assert L.fr_rk_step(None, None, 1e-3, 1, None) == B.FR_EINVAL
     assert L.fr_state_len(None) == 0
     assert L.fr_plan_set_int(None, 1, 0) == B.FR_EINVAL
