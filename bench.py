@@ -305,6 +305,96 @@ def compare_dual(p=3, N=32, dt=1e-2, dtaus=(2e-3, 8e-3), tol=1e-4, max_iters=400
     return out
 
 
+def sines_operator(p, n):
+    """-div F + S of ACM-HD in closed form for P = u = v = w = f = sin x sin y sin z
+    with exact-gradient auxiliary variables (g = grad f): R_P = -zeta (g_x + g_y + g_z),
+    R_u_i = -2 f (g_x + g_y + g_z) - g_i - 3 nu f (the viscous term's divergence is
+    nu lap f = -3 nu f), R_aux = 0.  Returns (ne, 4, m^3) for P, u, v, w."""
+    import numpy as np
+    from paper_2107_14027_amd import inputs
+    C = inputs.point_coords(p, n)
+    x, y, z = C[:, 0], C[:, 1], C[:, 2]
+    f = np.sin(x) * np.sin(y) * np.sin(z)
+    g = (np.cos(x) * np.sin(y) * np.sin(z), np.sin(x) * np.cos(y) * np.sin(z),
+         np.sin(x) * np.sin(y) * np.cos(z))
+    sg = g[0] + g[1] + g[2]
+    out = np.empty((f.shape[0], 4, f.shape[1]))
+    out[:, 0] = -ZETA * sg
+    for i in range(3):
+        out[:, 1 + i] = -2.0 * f * sg - g[i] - 3.0 * NU * f
+    return out
+
+
+def mfma_config4(p=4, N=64, reps=10):
+    """The matrix-core form (FR_MFMA: the per-direction operator block on
+    v_mfma_f32_16x16x4f32, single-precision operands and accumulation) beside the
+    double- and single-precision VALU fused residual on P = u = v = w =
+    sin x sin y sin z, p = 4, N^3 hexes: time per residual, and the max and RMS
+    error of P, u, v, w against the closed-form operator (the auxiliary residual
+    is exactly zero there), with the same for n = 4, 8, 16, 32 and the observed
+    orders of accuracy."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2107_14027_amd import binding as B
+    from paper_2107_14027_amd import inputs
+    forms = (("f64_valu", B.FR_F64, B.FR_FUSED), ("f32_valu", B.FR_F32, B.FR_FUSED),
+             ("f32_mfma", B.FR_F32, B.FR_MFMA))
+
+    def run(n, timed):
+        U = torch.from_numpy(inputs.sines(p, n)).to("cuda")
+        E = torch.from_numpy(sines_operator(p, n)).to("cuda")
+        out = {}
+        for key, prec, var in forms:
+            plan = B.Plan(p, n, ZETA, NU, TRELAX, precision=prec, variant=var)
+            Ui = U if prec == B.FR_F64 else U.float()
+            R = torch.empty_like(Ui)
+            ms = time_residual(B, torch, plan, Ui, R, reps) if timed else None
+            B.fr_residual(plan.handle, Ui, R)
+            torch.cuda.synchronize()
+            d = R[:, :4].double() - E
+            out[key] = {"max_err": float(d.abs().max()), "rms_err": float(d.pow(2).mean().sqrt()),
+                        "ms": ms, "R": R[:, :4].double() if timed else None}
+            plan.close()
+            del R
+        scale = float(E.abs().max())
+        del U, E
+        torch.cuda.empty_cache()
+        return out, scale
+
+    n = (N, N, N)
+    big, scale = run(n, True)
+    ref = big["f64_valu"]["R"]
+    res = {"workload": "P = u = v = w = sin x sin y sin z, exact-gradient auxiliary variables, "
+                       "p=%d on %d^3 hexes (%d solution points); errors of P, u, v, w against "
+                       "the closed-form operator (max |R| = %.3f)" % (p, N, N ** 3 * (p + 1) ** 3, scale)}
+    npts = N ** 3 * (p + 1) ** 3
+    for key, *_ in forms:
+        r = big[key]
+        res[key] = {"ms": round(r["ms"], 4),
+                    "GDOF_per_s": round(npts * NV / (r["ms"] * 1e-3) / 1e9, 2),
+                    "max_err": float("%.4g" % r["max_err"]), "rms_err": float("%.4g" % r["rms_err"])}
+        if key != "f64_valu":
+            d = r["R"] - ref
+            res[key]["max_diff_vs_f64"] = float("%.4g" % float(d.abs().max()))
+            res[key]["rel_l2_diff_vs_f64"] = float("%.4g" % float(d.norm() / ref.norm()))
+    del big, ref
+    torch.cuda.empty_cache()
+    ns = (4, 8, 16, 32)
+    errs = {key: [] for key, *_ in forms}
+    for nn in ns:
+        o, _ = run((nn, nn, nn), False)
+        for key in errs:
+            errs[key].append(o[key]["max_err"])
+    res["convergence"] = {"n": list(ns)}
+    for key, e in errs.items():
+        res["convergence"][key] = {
+            "max_err": [float("%.4g" % v) for v in e],
+            "order": [round(math.log(e[i] / e[i + 1]) / math.log(ns[i + 1] / ns[i]), 2)
+                      for i in range(len(ns) - 1)]}
+    return res
+
+
 def time_mlp(p=3, N=64, rows=1 << 16, reps=10):
     """The learned guess's kernels on their own: one network guess over every
     point of a p=3, 64^3 FP64 state (three states read, one written: 416 B per
@@ -376,6 +466,8 @@ def main():
     ap.add_argument("--no-acm", action="store_true",
                     help="skip the comparison-system timings: standard ACM (LDG) beside ACM-HD, "
                          "and ACM-HD on linear hexahedra")
+    ap.add_argument("--no-mfma", action="store_true",
+                    help="skip the matrix-core precision form (p=4, 64^3 manufactured solution)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -555,6 +647,11 @@ def main():
         lhex = time_lhex()
         log("linear hexahedra: %s" % lhex)
 
+    mfma = None
+    if not args.no_mfma:
+        mfma = mfma_config4()
+        log("matrix-core precision form: %s" % mfma)
+
     learned = None
     if not args.no_learned:
         from paper_2107_14027_amd import learned as L
@@ -637,6 +734,7 @@ def main():
         "time_step": timestep,
         "standard_acm_ldg": acm,
         "linear_hexahedra": lhex,
+        "mfma_config4": mfma,
         "learned_guess": learned,
         "sweep": sweep,
         "kernel_ms": {str(p): {"trace": round(kstats[p]["trace_ms"], 4),

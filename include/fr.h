@@ -73,7 +73,7 @@ typedef enum fr_option {
                              which keeps the separate kernel); 0: residual kernel + separate
                              stage kernel.  The states are bitwise identical either way; the
                              norm's summation order (per workgroup) differs.                 */
-    FR_OPT_PSEUDO = 8     /* pseudo-time scheme of fr_dual_step and of every fr_pmg level:
+    FR_OPT_PSEUDO = 8,    /* pseudo-time scheme of fr_dual_step and of every fr_pmg level:
                              0 (default) classical RK4 with the fixed step dtau; 1 the RK34
                              embedded pair (Sec. 5; coefficients of Kennedy, Carpenter and
                              Lewis's RK3(2)4[2R+]C) with one pseudo-step per state value,
@@ -81,6 +81,13 @@ typedef enum fr_option {
                              (e the embedded error estimate, tol the call's tolerance) and
                              kept within [dtau/3, 3 dtau].  The step field persists in the
                              plan between calls with the same dtau.                           */
+    FR_OPT_FORM = 9       /* kernel form of the FR_FUSED residual (fr_residual; the stage
+                             epilogue keeps the point form): FR_FORM_AUTO (default) the
+                             line form where the Jacobian is diagonal, else the point form;
+                             FR_FORM_POINT elements staged in LDS, every point contracting
+                             its own lines; FR_FORM_LINES one lane per element line and
+                             direction, state read straight into registers (diagonal
+                             Jacobians only: FR_EUNSUPPORTED otherwise).                     */
 } fr_option;
 
 /* Kernel identifiers for fr_plan_kernel_stats. */
@@ -99,6 +106,7 @@ typedef enum fr_kernel {
 
 enum { FR_F64 = 0, FR_F32 = 1 };
 enum { FR_FUSED = 0, FR_UNFUSED = 1, FR_MFMA = 2 };
+enum { FR_FORM_AUTO = 0, FR_FORM_POINT = 1, FR_FORM_LINES = 2 };
 
 /*
  * fr_plan_create -- build the 1D operators (Sec. 2.1: Gauss-Legendre solution

@@ -12,12 +12,13 @@ LIB_PATH = os.environ.get("FR_LIBRARY", os.path.join(HERE, "libfr.so"))
 
 FR_OK, FR_EINVAL, FR_ENOMEM, FR_EHIP, FR_ENONFINITE, FR_ENOCONV, FR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 (FR_OPT_PRECISION, FR_OPT_VARIANT, FR_OPT_BLOCK, FR_OPT_PROFILE, FR_OPT_GUESS_BASE,
- FR_OPT_GRAPH, FR_OPT_FUSE_STAGE, FR_OPT_PSEUDO) = 1, 2, 3, 4, 5, 6, 7, 8
+ FR_OPT_GRAPH, FR_OPT_FUSE_STAGE, FR_OPT_PSEUDO, FR_OPT_FORM) = 1, 2, 3, 4, 5, 6, 7, 8, 9
 KERNELS = ("trace", "fused", "u_project", "u_flux", "u_div", "u_common", "u_correct",
            "u_negsrc", "stage")
 FR_F64, FR_F32 = 0, 1
 FR_K_TRACE, FR_K_FUSED = 0, 1
 FR_FUSED, FR_UNFUSED, FR_MFMA = 0, 1, 2
+FR_FORM_AUTO, FR_FORM_POINT, FR_FORM_LINES = 0, 1, 2
 NV = 13
 
 EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_destroy",

@@ -178,6 +178,21 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
     const bool epi = stage_in_epilogue(pl) && !D && !rk34;
     void *const bufs[2] = {b.stT, b.k};
     const int o = f64 ? 0 : 1;
+    // face traces ping-pong between two arrays: each stage's epilogue writes
+    // those of the state it produces, so only the call's first stage runs the
+    // trace kernel (stage 0 reads A and writes B, stages 1, 2, 3 alternate)
+    void *trA = nullptr, *trB = nullptr;
+    if (epi)
+        if (int r = stage_trace_buffers(pl, trA, trB)) return r;
+    auto with_traces = [&](StageSpec sp, const void *in, void *out) {
+        sp.tr_in = in;
+        sp.tr_out = out;
+        sp.nx = pl->nx;
+        sp.ny = pl->ny;
+        sp.nz = pl->nz;
+        return sp;
+    };
+    bool chained = false;  // stage 0's input traces come from the previous stage 3
     auto stage0 = [&](hipStream_t st) -> int {
         if (rk34) {
             if (int r = residual(pl, f64 ? (const void *)U : b.stT, b.k, st)) return r;
@@ -185,8 +200,9 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
                                   partial, st);
         }
         if (epi) {
-            const StageSpec sp{U, b.acc, nullptr, f64 ? nullptr : st64, bufs[o], B, partial,
-                               a, w[0], c[1], 1, 0};
+            const StageSpec sp = with_traces(StageSpec{U, b.acc, nullptr, f64 ? nullptr : st64,
+                                                       bufs[o], B, partial, a, w[0], c[1], 1, 0},
+                                             chained ? trA : nullptr, trB);
             return launch_residual_stage(pl, f64 ? (const void *)U : bufs[0], sp, &nparts, st);
         }
         if (int r = residual(pl, f64 ? (const void *)U : b.stT, b.k, st)) return r;
@@ -209,9 +225,11 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
                 const bool last = k == 3;
                 void *in = bufs[(k - 1 + o) % 2];
                 void *out = last ? (f64 ? nullptr : bufs[0]) : bufs[(k + o) % 2];
-                const StageSpec sp{U, b.acc, f64 ? (const double *)in : st64,
-                                   (f64 || last) ? nullptr : st64, out, B, nullptr,
-                                   a, w[k], last ? 0.0 : c[k + 1], 0, last};
+                const StageSpec sp = with_traces(
+                    StageSpec{U, b.acc, f64 ? (const double *)in : st64,
+                              (f64 || last) ? nullptr : st64, out, B, nullptr, a, w[k],
+                              last ? 0.0 : c[k + 1], 0, last},
+                    k % 2 ? trB : trA, k % 2 ? trA : trB);
                 if (int r = launch_residual_stage(pl, in, sp, nullptr, st)) return r;
             }
             return FR_OK;
@@ -248,6 +266,7 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
     // is not wanted); its norm is known when `have`
     bool have = checked(0);
     if (!rc && (max_iters > 0 || have)) rc = stage0(s);
+    chained = true;
     if (!rc && have) rc = readback(s);
     if (!rc && have) rc = wait_norm();
     *converged = 0;
@@ -272,7 +291,8 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
                                       (uint64_t)pl->dual.ptr, (uint64_t)pl->norm.ptr,
                                       (uint64_t)pl->traces.ptr, (uint64_t)pl->unfused.ptr,
                                       config_word(pl), (uint64_t)pl->norm_host,
-                                      (uint64_t)nparts, (uint64_t)pl->rk34.ptr, bits(tol)};
+                                      (uint64_t)nparts, (uint64_t)pl->rk34.ptr, bits(tol),
+                                      (uint64_t)pl->traces2.ptr};
             rc = graph_run(pl, pl->graphs[check ? 0 : 1], key, s, body);
         } else {
             rc = body(s);
@@ -335,14 +355,25 @@ int fr_rk_step(fr_plan *pl, double *U, double dt, int nsteps, fr_stream_t sv)
     const bool epi = stage_in_epilogue(pl);
     void *const bufs[2] = {b.stT, b.k};
     const int o = f64 ? 0 : 1;
+    // face traces ping-pong between two arrays (stage 0 reads A, writes B;
+    // stages 1, 2, 3 alternate): only the call's first stage runs the trace kernel
+    void *trA = nullptr, *trB = nullptr;
+    if (epi)
+        if (int r = stage_trace_buffers(pl, trA, trB)) return r;
+    bool chained = false;
     auto step = [&](hipStream_t st) -> int {
         if (epi) {
             const void *in = f64 ? (const void *)U : bufs[0];
             for (int k = 0; k < 4; ++k) {
                 const bool last = k == 3;
                 void *out = last ? (f64 ? nullptr : bufs[0]) : bufs[(k + o) % 2];
-                const StageSpec sp{U, b.acc, nullptr, nullptr, out, nullptr, nullptr,
-                                   0.0, w[k], last ? 0.0 : c[k + 1], k == 0, last};
+                StageSpec sp{U, b.acc, nullptr, nullptr, out, nullptr, nullptr,
+                             0.0, w[k], last ? 0.0 : c[k + 1], k == 0, last};
+                sp.tr_in = k == 0 ? (chained ? trA : nullptr) : (k % 2 ? trB : trA);
+                sp.tr_out = k % 2 ? trA : trB;
+                sp.nx = pl->nx;
+                sp.ny = pl->ny;
+                sp.nz = pl->nz;
                 if (int r = launch_residual_stage(pl, in, sp, nullptr, st)) return r;
                 in = out;
             }
@@ -361,10 +392,11 @@ int fr_rk_step(fr_plan *pl, double *U, double dt, int nsteps, fr_stream_t sv)
     };
     const bool graphs = pl->use_graphs && !pl->profile;
     for (int it = 0; it < nsteps && !rc; ++it) {
+        chained = it > 0;
         if (graphs && it > 0) {
             const uint64_t key[20] = {2, (uint64_t)U, bits(dt), (uint64_t)pl->rk.ptr,
                                       (uint64_t)pl->traces.ptr, (uint64_t)pl->unfused.ptr,
-                                      config_word(pl)};
+                                      config_word(pl), (uint64_t)pl->traces2.ptr};
             rc = graph_run(pl, pl->graphs[2], key, s, step);
         } else {
             rc = step(s);

@@ -69,6 +69,14 @@ struct StageSpec {
     double *partial;
     double a, b, cnext;
     int first, last;
+    // face traces: tr_in non-null holds those of the input state (written by
+    // the previous stage's epilogue), so the trace kernel is skipped; tr_out
+    // non-null receives those of the state this stage produces (s', or U on
+    // the last stage), in the working precision, as the trace kernel would
+    // compute them from that state.  nx, ny, nz: the lattice (for tr_out).
+    const void *tr_in;
+    void *tr_out;
+    int nx, ny, nz;
 };
 
 // capacity of the per-workgroup partial sums of a fused stage launch
@@ -89,6 +97,7 @@ struct fr_plan {
     int precision;  // FR_F64 / FR_F32
     int variant;    // FR_FUSED / FR_UNFUSED
     int block;      // elements per workgroup override (0 = default)
+    int form = 0;   // FR_FORM_AUTO / FR_FORM_POINT / FR_FORM_LINES (fused plain residual)
     int guess_base = 2;  // extrapolation order the learned guess corrects
     // captured time-integration graphs ([0] pseudo-step with norm read-back,
     // [1] pseudo-step without, [2] RK4 step) and their capture stream
@@ -105,8 +114,9 @@ struct fr_plan {
     fr::GraphCache graphs[3];
     // persistent grid sizes of the fused path on this plan's device, per
     // (order, precision, diagonal Jacobian): [0] trace kernel, [1] fused kernel,
-    // [2] fused kernel with the stage epilogue, [3] its matrix-core form
-    int fused_grid[4][fr::PMAX + 1][2][2] = {};
+    // [2] fused kernel with the stage epilogue, [3] its matrix-core form;
+    // [4] 1 once the line-form kernel's LDS limit is set
+    int fused_grid[5][fr::PMAX + 1][2][2] = {};
     int device;
     // host copies of the operators (double)
     double x[8], w[8], D[64], lm[8], lp[8], gl[8], gr[8], Dt[64];
@@ -116,6 +126,7 @@ struct fr_plan {
     fr::Consts<float> c32;
     // scratch
     fr::Scratch traces;     // [6][ne][7][m^2] of the working precision
+    fr::Scratch traces2;    // second trace array: the stage epilogue's ping-pong
     fr::Scratch unfused;    // stage buffers of the unfused pipeline
     fr::Scratch rk;         // acc (double), stage (T), k (T)
     fr::Scratch dual;       // BDF constant part (double, velocity only)
@@ -167,6 +178,8 @@ int launch_residual(fr_plan *pl, const void *U, void *R, hipStream_t s);
 int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *nparts,
                           hipStream_t s);
 bool fused_stage_available(const fr_plan *pl);
+// the two trace arrays of the stage epilogue's ping-pong (allocated on first use)
+int stage_trace_buffers(fr_plan *pl, void *&a, void *&b);
 
 
 // Up to max_iters classical RK4 pseudo-steps of dU/dtau = R(U) - M_V (a U + B)

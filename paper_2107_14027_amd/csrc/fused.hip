@@ -1025,13 +1025,46 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
                             const double un = fma(sp.b, kv, oa[j]);
                             sp.U[gi] = un;
                             if (sp.s_out) static_cast<T *>(sp.s_out)[gi] = (T)un;
+                            if (sp.tr_out) sU[t] = (T)un;
                         } else {
                             sp.acc[gi] = fma(sp.b, kv, sp.first ? ou[j] : oa[j]);
                             const double sn = fma(sp.cnext, kv, ou[j]);
                             if (sp.s_out64) sp.s_out64[gi] = sn;
                             static_cast<T *>(sp.s_out)[gi] = (T)sn;
+                            if (sp.tr_out) sU[t] = (T)sn;
                         }
                     }
+                }
+            }
+            if (sp.tr_out) {
+                // ---- stage 1 of the next residual: the produced state's face
+                //      traces (k_trace's values and layout) from the tile, written
+                //      to the neighbours' receiving blocks
+                using V = typename V16<T>::type;
+                constexpr int CH = TL::CH, CHV = TL::CHV, W = TL::W;
+                __syncthreads();
+                V *TRo = static_cast<V *>(sp.tr_out);
+                for (unsigned t = tid; t < 6u * EMAX * CHV; t += NT) {
+                    const unsigned f = t / (EMAX * CHV), r = t - f * (EMAX * CHV);
+                    const unsigned el = r / CHV, k = r - el * CHV;
+                    if ((int)el >= nel) continue;
+                    const int d = f >> 1, s = f & 1;
+                    const T nh[3] = {geo[9 + 3 * d], geo[10 + 3 * d], geo[11 + 3 * d]};
+                    const T *lf = sop + (s ? OL::lp : OL::lm);
+                    V x;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const unsigned o = k * W + w;
+                        const unsigned cc = o / NF, fp = o - cc * NF;
+                        const unsigned a = fp % M, bb = fp / M;
+                        const int stride = d == 0 ? 1 : (d == 1 ? M : M * M);
+                        const int base = d == 0 ? M * fp : (d == 1 ? a + M * M * bb : fp);
+                        x[w] = o < (unsigned)CH
+                                   ? trace_value<M, T>(sU + el * NV * NS, d, base, stride, lf, nh, cc, DIAG)
+                                   : T(0);
+                    }
+                    const int64_t nb = neighbour(e0 + el, (int)f, sp.nx, sp.ny, sp.nz);
+                    __builtin_nontemporal_store(x, TRo + ((int64_t)(f ^ 1) * ne + nb) * CHV + k);
                 }
             }
         }
@@ -1049,6 +1082,359 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
                 for (int w = 0; w < NT / 64; ++w) t += red[w];
                 sp.partial[blockIdx.x] = t;
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_lines: stages 2-6 as line tasks (diagonal Jacobian).
+//
+// A workgroup takes LE consecutive elements: it copies their contiguous state
+// block into LDS (16-byte vectors where the element size allows), then runs
+// three groups of LW waves, one group per direction d.  A lane owns one line
+// of direction d of one element (face point L = a + m b of the faces 2d and
+// 2d+1).  It reads the m values of the seven variables the direction needs
+// (P, u, v, w and S_0d, S_1d, S_2d: with a diagonal Jacobian the transformed
+// flux along d involves no other), projects them to both ends of the line (the
+// element's own traces, with k_trace's fma chain, so both sides of a face see
+// the same bits), reads the neighbours' traces, forms the two common fluxes,
+// the transformed flux at the m points and the six partially corrected
+// derivatives (three velocities, three momentum fluxes; Table 1 stages 3 and 5
+// with the operator Dt and the correction derivatives g_L', g_R').  The
+// auxiliary residuals (a, d) are complete at that point and are written out;
+// the P and momentum parts of directions y and z go through LDS to the x lane
+// of the same points, which sums the three directions and writes the rest of R.
+// ---------------------------------------------------------------------------
+#ifndef FR_LE1_D
+#define FR_LE1_D 16
+#endif
+#ifndef FR_LW1_D
+#define FR_LW1_D 1
+#endif
+#ifndef FR_LE2_D
+#define FR_LE2_D 7
+#endif
+#ifndef FR_LW2_D
+#define FR_LW2_D 1
+#endif
+#ifndef FR_LE3_D
+#define FR_LE3_D 4
+#endif
+#ifndef FR_LW3_D
+#define FR_LW3_D 1
+#endif
+#ifndef FR_LE4_D
+#define FR_LE4_D 5
+#endif
+#ifndef FR_LW4_D
+#define FR_LW4_D 2
+#endif
+#ifndef FR_LE5_D
+#define FR_LE5_D 3
+#endif
+#ifndef FR_LW5_D
+#define FR_LW5_D 2
+#endif
+#ifndef FR_LE6_D
+#define FR_LE6_D 1
+#endif
+#ifndef FR_LW6_D
+#define FR_LW6_D 1
+#endif
+#ifndef FR_LE1_F
+#define FR_LE1_F 16
+#endif
+#ifndef FR_LW1_F
+#define FR_LW1_F 1
+#endif
+#ifndef FR_LE2_F
+#define FR_LE2_F 7
+#endif
+#ifndef FR_LW2_F
+#define FR_LW2_F 1
+#endif
+#ifndef FR_LE3_F
+#define FR_LE3_F 4
+#endif
+#ifndef FR_LW3_F
+#define FR_LW3_F 1
+#endif
+#ifndef FR_LE4_F
+#define FR_LE4_F 5
+#endif
+#ifndef FR_LW4_F
+#define FR_LW4_F 2
+#endif
+#ifndef FR_LE5_F
+#define FR_LE5_F 7
+#endif
+#ifndef FR_LW5_F
+#define FR_LW5_F 4
+#endif
+#ifndef FR_LE6_F
+#define FR_LE6_F 1
+#endif
+#ifndef FR_LW6_F
+#define FR_LW6_F 1
+#endif
+// LDS layout of the line form: the batch's elements at a pitch of EP values
+// (13 m^3 padded so that consecutive elements start at bank offsets m^2 apart:
+// lanes of neighbouring elements then read neighbouring banks).
+template <int P, typename T>
+struct LinesLds {
+    static constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    static constexpr int BANKV = sizeof(T) == 8 ? 32 : 64;  // values per bank sweep of a read
+    static constexpr int raw = NV * NS;
+    static constexpr int EP = raw + ((NF - raw % BANKV) % BANKV + BANKV) % BANKV;
+    // whole 16-byte chunks per element, so that the copy can use vectors
+    static constexpr bool VEC = (raw * sizeof(T)) % 16 == 0 && (EP * sizeof(T)) % 16 == 0;
+};
+
+template <int P, typename T> struct LinesShape;
+#define FR_LSHAPE(PP, TT, S)                                                        \
+    template <> struct LinesShape<PP, TT> {                                         \
+        static constexpr int E = FR_LE##PP##_##S, W = FR_LW##PP##_##S, NT = 192 * W; \
+        static_assert(E * (PP + 1) * (PP + 1) <= 64 * W, "one lane per line");       \
+        static_assert(E * LinesLds<PP, TT>::EP * sizeof(TT) <= 160 * 1024, "LDS");    \
+    };
+FR_LSHAPE(1, double, D)
+FR_LSHAPE(2, double, D)
+FR_LSHAPE(3, double, D)
+FR_LSHAPE(4, double, D)
+FR_LSHAPE(5, double, D)
+FR_LSHAPE(6, double, D)
+FR_LSHAPE(1, float, F)
+FR_LSHAPE(2, float, F)
+FR_LSHAPE(3, float, F)
+FR_LSHAPE(4, float, F)
+FR_LSHAPE(5, float, F)
+FR_LSHAPE(6, float, F)
+#undef FR_LSHAPE
+
+// The m values of one line (first value p, stride STR) into registers; an
+// x-line (STR = 1) is contiguous and is read in 16- or 8-byte vectors where
+// its length and the element size keep them aligned.
+template <int M, int STR, typename T>
+__device__ __forceinline__ void line_load(const T *__restrict__ p, T (&x)[M])
+{
+    if constexpr (STR == 1 && (M * sizeof(T)) % 16 == 0) {
+        using V = typename V16<T>::type;
+        constexpr int W = 16 / sizeof(T);
+#pragma unroll
+        for (int k = 0; k < M / W; ++k) {
+            const V v = reinterpret_cast<const V *>(p)[k];
+#pragma unroll
+            for (int w = 0; w < W; ++w) x[k * W + w] = v[w];
+        }
+    } else if constexpr (STR == 1 && sizeof(T) == 4 && M % 2 == 0) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int k = 0; k < M / 2; ++k) {
+            const f2v v = reinterpret_cast<const f2v *>(p)[k];
+            x[2 * k] = v[0];
+            x[2 * k + 1] = v[1];
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < M; ++l) x[l] = p[l * STR];
+    }
+}
+
+template <int M, int STR, typename T>
+__device__ __forceinline__ void line_store(T *__restrict__ p, const T (&x)[M])
+{
+    if constexpr (STR == 1 && (M * sizeof(T)) % 16 == 0) {
+        using V = typename V16<T>::type;
+        constexpr int W = 16 / sizeof(T);
+#pragma unroll
+        for (int k = 0; k < M / W; ++k) {
+            V v;
+#pragma unroll
+            for (int w = 0; w < W; ++w) v[w] = x[k * W + w];
+            __builtin_nontemporal_store(v, reinterpret_cast<V *>(p) + k);
+        }
+    } else if constexpr (STR == 1 && sizeof(T) == 4 && M % 2 == 0) {
+        typedef float f2v __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int k = 0; k < M / 2; ++k) {
+            f2v v;
+            v[0] = x[2 * k];
+            v[1] = x[2 * k + 1];
+            __builtin_nontemporal_store(v, reinterpret_cast<f2v *>(p) + k);
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < M; ++l) __builtin_nontemporal_store(x[l], p + l * STR);
+    }
+}
+
+
+// One direction's line task on the element tile Ue (LDS).  On return ctb[0][r]
+// holds the P part zeta n_dd du_d/dxi_d + dissipation and ctb[1 + i][r] the
+// corrected derivative of the transformed momentum flux i at the line's point r.
+template <int P, typename T, int D>
+__device__ __forceinline__ void line_task(const T *__restrict__ Ut, const T *__restrict__ TR,
+                                          T *__restrict__ R, const T *__restrict__ ops,
+                                          const Consts<T> &c, int ne, int64_t e, int L,
+                                          T (&ctb)[4][P + 1])
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    constexpr int STR = D == 0 ? 1 : (D == 1 ? M : M * M);
+    using TL = TraceLayout<M, T>;
+    using OL = OpsLayout<M>;
+    const int a = L % M, b = L / M;
+    const int base = D == 0 ? M * L : (D == 1 ? a + M * M * b : L);
+    // the neighbours' traces on this line's two face points (issued first)
+    const T *tm = TR + ((int64_t)(2 * D) * ne + e) * TL::CHP + L;
+    const T *tp = TR + ((int64_t)(2 * D + 1) * ne + e) * TL::CHP + L;
+    T othm[NTR], othp[NTR];
+#pragma unroll
+    for (int cc = 0; cc < NTR; ++cc) {
+        othm[cc] = __builtin_nontemporal_load(tm + cc * NF);
+        othp[cc] = __builtin_nontemporal_load(tp + cc * NF);
+    }
+    // P, u, v, w, S_0D, S_1D, S_2D along the line
+    const T *Ue = Ut + base;
+    T X[7][M];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) line_load<M, STR>(Ue + v * NS, X[v]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) line_load<M, STR>(Ue + (4 + 3 * i + D) * NS, X[4 + i]);
+    // own traces (k_trace's chain) and the two common fluxes
+    T FIm[NTR], FIp[NTR];
+    {
+        T ownm[NTR], ownp[NTR];
+#pragma unroll
+        for (int cc = 0; cc < NTR; ++cc) {
+            T am = T(0), ap = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                am = fma(ops[OL::lm + l], X[cc][l], am);
+                ap = fma(ops[OL::lp + l], X[cc][l], ap);
+            }
+            ownm[cc] = am;
+            ownp[cc] = ap;
+        }
+        const T nh[3] = {c.nhat[D][0], c.nhat[D][1], c.nhat[D][2]};
+        common_flux_sided<T>(ownm, othm, false, nh, c.nmag[D], c.zeta, c.nu, FIm);
+        common_flux_sided<T>(ownp, othp, true, nh, c.nmag[D], c.zeta, c.nu, FIp);
+    }
+    const T ndd = c.nvec[D][D];
+    // velocity derivatives: auxiliary residuals (a, D) and the P part
+#pragma unroll
+    for (int va = 0; va < 3; ++va) {
+        T aux[M];
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            T s = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) s = fma(ops[OL::Dt + r * M + l], X[1 + va][l], s);
+            const T cd = fma(ops[OL::gl + r], FIm[4 + va], fma(ops[OL::gr + r], FIp[4 + va], s));
+            const T gv = cd * ndd;
+            aux[r] = c.invT * fma(c.inv_det, gv, -X[4 + va][r]);
+            if (va == D)
+                ctb[0][r] = fma(c.zeta, gv, fma(ops[OL::gl + r], FIm[0], ops[OL::gr + r] * FIp[0]));
+        }
+        line_store<M, STR>(R + e * (NV * NS) + (4 + 3 * va + D) * NS + base, aux);
+    }
+    // transformed momentum fluxes F_D,i = n_DD (u_i u_D + P delta_iD - nu S_iD)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        T F[M];
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            const T vn = X[1 + D][l] * ndd;
+            const T sn = X[4 + i][l] * ndd;
+            F[l] = i == D ? fma(X[1 + i][l], vn, fma(X[0][l], ndd, -c.nu * sn))
+                          : fma(X[1 + i][l], vn, -c.nu * sn);
+        }
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+            T s = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) s = fma(ops[OL::Dt + r * M + l], F[l], s);
+            ctb[1 + i][r] = fma(ops[OL::gl + r], FIm[1 + i], fma(ops[OL::gr + r], FIp[1 + i], s));
+        }
+    }
+}
+
+template <int P, typename T>
+__global__ void __launch_bounds__((LinesShape<P, T>::NT))
+    k_lines(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
+            const T *__restrict__ ops, Consts<T> c, int ne)
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    constexpr int E = LinesShape<P, T>::E, W = LinesShape<P, T>::W, NT = LinesShape<P, T>::NT;
+    using LL = LinesLds<P, T>;
+    constexpr int EP = LL::EP, RAW = LL::raw;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sU = reinterpret_cast<T *>(smem_raw);  // [E][EP]
+    const int64_t e0 = (int64_t)blockIdx.x * E;
+    const int nel = (int)min((int64_t)E, (int64_t)ne - e0);
+    // the batch's state block into LDS
+    {
+        const T *src = U + e0 * RAW;
+        if constexpr (LL::VEC) {
+            using V = typename V16<T>::type;
+            constexpr int VW = 16 / sizeof(T), CPE = RAW / VW;  // chunks per element
+            const int nch = nel * CPE;
+            const V *sv = reinterpret_cast<const V *>(src);
+#pragma unroll 4
+            for (int k = threadIdx.x; k < nch; k += NT) {
+                const int el = k / CPE, o = k - el * CPE;
+                reinterpret_cast<V *>(sU + el * EP)[o] = __builtin_nontemporal_load(sv + k);
+            }
+        } else {
+            const int nv = nel * RAW;
+#pragma unroll 4
+            for (int k = threadIdx.x; k < nv; k += NT) {
+                const int el = k / RAW, o = k - el * RAW;
+                sU[el * EP + o] = __builtin_nontemporal_load(src + k);
+            }
+        }
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int d = wave / W;
+    const int t = (wave - d * W) * 64 + (threadIdx.x & 63);
+    const int el = t / NF, L = t - el * NF;
+    const bool act = el < nel;
+    const int64_t e = e0 + el;
+    T *Ut = sU + el * EP;
+    T ctb[4][M];
+    if (act) {
+        if (d == 0) line_task<P, T, 0>(Ut, TR, R, ops, c, ne, e, L, ctb);
+        else if (d == 1) line_task<P, T, 1>(Ut, TR, R, ops, c, ne, e, L, ctb);
+        else line_task<P, T, 2>(Ut, TR, R, ops, c, ne, e, L, ctb);
+    }
+    // every read of the state tile is done: the P and momentum parts of
+    // directions y (slots 0-3) and z (slots 4-7) go over it
+    __syncthreads();
+    if (act && d == 1) {
+        const int a = L % M, b = L / M;
+        T *dst = Ut + a + M * M * b;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int r = 0; r < M; ++r) dst[k * NS + r * M] = ctb[k][r];
+    } else if (act && d == 2) {
+        T *dst = Ut + 4 * NS + L;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int r = 0; r < M; ++r) dst[k * NS + r * NF] = ctb[k][r];
+    }
+    __syncthreads();
+    if (act && d == 0) {
+        const T *cy = Ut + M * L;
+        const T *cz = Ut + 4 * NS + M * L;
+        T *Re = R + e * (NV * NS) + M * L;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            T o[M];
+#pragma unroll
+            for (int r = 0; r < M; ++r) o[r] = -c.inv_det * ((ctb[k][r] + cy[k * NS + r]) + cz[k * NS + r]);
+            line_store<M, 1>(Re + k * NS, o);
         }
     }
 }
@@ -1087,6 +1473,10 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
         if (sp) return set_error(FR_EUNSUPPORTED, "matrix-core variant: no stage epilogue");
         kfu = (const void *)k_fused<P, T, DIAG, false, true>;
     }
+    // line-task form of the plain residual (diagonal Jacobian)
+    const bool lines = !MF && !sp && DIAG && pl->form == FR_FORM_LINES;
+    if (!MF && !sp && !DIAG && pl->form == FR_FORM_LINES)
+        return set_error(FR_EUNSUPPORTED, "line-task form: diagonal Jacobians only");
     // persistent grid: every workgroup that fits on the device at once
     auto persistent_grid = [&](const void *fn, int nt, size_t lds, int &grid) -> int {
         if (grid) return FR_OK;
@@ -1109,13 +1499,35 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
     int &grid_tr = pl->fused_grid[0][P][sizeof(T) == 8][DIAG];
     int &grid_fu = pl->fused_grid[MF ? 3 : (sp ? 2 : 1)][P][sizeof(T) == 8][DIAG];
     if (int rc = persistent_grid(ktr, TNT, lds_tr, grid_tr)) return rc;
-    if (int rc = persistent_grid(kfu, NT, lds_fu, grid_fu)) return rc;
+    if (!lines)
+        if (int rc = persistent_grid(kfu, NT, lds_fu, grid_fu)) return rc;
     const unsigned gtr = (unsigned)min(nbatch_tr, grid_tr);
     const unsigned gfu = (unsigned)min(min(nbatch, grid_fu), sp ? MAX_PARTIALS : grid_fu);
-    {
+    if (sp && sp->tr_in) {
+        TR = static_cast<T *>(const_cast<void *>(sp->tr_in));
+    } else {
         ProfScope ps(prof ? pl : nullptr, FR_K_TRACE, s);
         hipLaunchKernelGGL((k_trace<P, T, DIAG>), dim3(gtr), dim3(TNT), lds_tr, s, U, TR, ops, c,
                            pl->nx, pl->ny, pl->nz, TE, nbatch_tr);
+    }
+    if (lines) {
+        constexpr int LE = LinesShape<P, T>::E, LNT = LinesShape<P, T>::NT;
+        const size_t lds_li = (size_t)LE * LinesLds<P, T>::EP * sizeof(T);
+        const int64_t nb = ((int64_t)ne + LE - 1) / LE;
+        int &set = pl->fused_grid[4][P][sizeof(T) == 8][DIAG];
+        if (!set) {
+            if (int rc = check_hip(hipFuncSetAttribute((const void *)k_lines<P, T>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)lds_li),
+                                   "hipFuncSetAttribute"))
+                return rc;
+            set = 1;
+        }
+        ProfScope ps(prof ? pl : nullptr, FR_K_FUSED, s);
+        if constexpr (DIAG)
+            hipLaunchKernelGGL((k_lines<P, T>), dim3((unsigned)nb), dim3(LNT), lds_li, s, U, TR, R, ops,
+                               c, ne);
+        return check_hip(hipGetLastError(), "fused residual launch");
     }
     {
         ProfScope ps(prof ? pl : nullptr, FR_K_FUSED, s);
@@ -1272,6 +1684,15 @@ int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *
                           hipStream_t s)
 {
     return fused_any(pl, U, nullptr, &sp, nparts, s);
+}
+
+int stage_trace_buffers(fr_plan *pl, void *&a, void *&b)
+{
+    if (int rc = ensure_scratch(pl->traces, trace_bytes(pl))) return rc;
+    if (int rc = ensure_scratch(pl->traces2, trace_bytes(pl))) return rc;
+    a = pl->traces.ptr;
+    b = pl->traces2.ptr;
+    return FR_OK;
 }
 
 // Launch shape of the fused path's kernels (host only): elements per batch,

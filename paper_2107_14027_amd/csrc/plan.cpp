@@ -360,6 +360,8 @@ int fr_plan_set_int(fr_plan *pl, int key, int value)
             if (value != pl->precision) {
                 hipDeviceSynchronize();
                 free_scratch(pl->traces);
+    free_scratch(pl->traces2);
+                free_scratch(pl->traces2);
                 free_scratch(pl->unfused);
                 free_scratch(pl->rk);
             }
@@ -394,6 +396,11 @@ int fr_plan_set_int(fr_plan *pl, int key, int value)
             if (value != 0 && value != 1) return set_error(FR_EINVAL, "pseudo-time scheme %d", value);
             pl->pseudo = value;
             return FR_OK;
+        case FR_OPT_FORM:
+            if (value != FR_FORM_AUTO && value != FR_FORM_POINT && value != FR_FORM_LINES)
+                return set_error(FR_EINVAL, "form %d", value);
+            pl->form = value;
+            return FR_OK;
         default:
             return set_error(FR_EINVAL, "unknown option %d", key);
     }
@@ -411,6 +418,7 @@ int fr_plan_get_int(const fr_plan *pl, int key, int *value)
         case FR_OPT_GRAPH: *value = pl->use_graphs; return FR_OK;
         case FR_OPT_FUSE_STAGE: *value = pl->fuse_stage; return FR_OK;
         case FR_OPT_PSEUDO: *value = pl->pseudo; return FR_OK;
+        case FR_OPT_FORM: *value = pl->form; return FR_OK;
         default: return set_error(FR_EINVAL, "unknown option %d", key);
     }
 }

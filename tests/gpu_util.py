@@ -61,11 +61,12 @@ def check_groups(R, Ro, precision, U=None, zeta=ZETA, T=T_CFG, what=""):
 
 
 def gpu_residual(p, n, U, zeta=ZETA, nu=NU, T=T_CFG, jac=None, precision=B.FR_F64,
-                 variant=B.FR_FUSED, block=0, plan=None):
+                 variant=B.FR_FUSED, block=0, plan=None, form=B.FR_FORM_AUTO):
     import torch
     own = plan is None
     if own:
         plan = B.Plan(p, n, zeta, nu, T, jac, precision, variant, block)
+        plan.set(B.FR_OPT_FORM, form)
     dt = torch.float64 if precision == B.FR_F64 else torch.float32
     Ud = torch.from_numpy(np.ascontiguousarray(U)).to("cuda").to(dt)
     Rd = torch.empty_like(Ud)

@@ -61,6 +61,29 @@ def test_orders_ragged(p, n, prec, var, jac):
     check_groups(R, Ro, prec, U, what="p=%d jac=%s" % (p, jac))
 
 
+FORMS = [B.FR_FORM_POINT, B.FR_FORM_LINES]
+
+
+@pytest.mark.parametrize("p,n", CASES)
+@pytest.mark.parametrize("prec", PREC)
+@pytest.mark.parametrize("form", FORMS)
+def test_forms_ragged(p, n, prec, form):
+    """Both kernel forms of the fused residual against the oracle (diagonal
+    Jacobian: the periodic box)."""
+    U = rand_U(p, n, seed=300 + p)
+    say("forms p=%d n=%s prec=%d form=%d" % (p, n, prec, form))
+    R = gpu_residual(p, n, U, precision=prec, form=form)
+    Ro = oracle.residual(p, n, U, ZETA, NU, T_CFG)
+    assert rel(R, Ro) <= TOL[prec], rel(R, Ro)
+    check_groups(R, Ro, prec, U, what="p=%d form=%d" % (p, form))
+
+
+def test_line_form_needs_diagonal_jacobian():
+    with pytest.raises(B.FrError) as ei:
+        gpu_residual(2, (2, 2, 2), rand_U(2, (2, 2, 2), 1), jac=SKEW, form=B.FR_FORM_LINES)
+    assert ei.value.code == B.FR_EUNSUPPORTED
+
+
 @pytest.mark.parametrize("n", [(1, 1, 1), (1, 2, 1), (2, 1, 1)])
 @pytest.mark.parametrize("prec", PREC)
 def test_degenerate_lattices(n, prec):
@@ -68,8 +91,9 @@ def test_degenerate_lattices(n, prec):
     p = 3
     U = rand_U(p, n, seed=7)
     say("degenerate n=%s prec=%d" % (n, prec))
-    for var in VAR:
-        R = gpu_residual(p, n, U, precision=prec, variant=var)
+    for var, form in ((B.FR_FUSED, B.FR_FORM_POINT), (B.FR_FUSED, B.FR_FORM_LINES),
+                      (B.FR_UNFUSED, B.FR_FORM_AUTO)):
+        R = gpu_residual(p, n, U, precision=prec, variant=var, form=form)
         Ro = oracle.residual(p, n, U, ZETA, NU, T_CFG)
         assert rel(R, Ro) <= TOL[prec]
         check_groups(R, Ro, prec, U, what="degenerate")
@@ -97,12 +121,16 @@ def test_block_size_invariance_and_determinism(p):
     n = (4, 3, 3) if p < 5 else (2, 2, 3)
     U = rand_U(p, n, seed=11)
     say("block invariance p=%d" % p)
-    ref = gpu_residual(p, n, U)
-    again = gpu_residual(p, n, U)
+    pt = B.FR_FORM_POINT
+    ref = gpu_residual(p, n, U, form=pt)
+    again = gpu_residual(p, n, U, form=pt)
     assert np.array_equal(ref, again)
-    emax = fused_emax(p, "D")   # largest batch the fused kernel accepts
+    emax = fused_emax(p, "D")   # largest batch the point-form kernel accepts
     for E in (1, 2, 3):
         if E <= emax:
-            assert np.array_equal(gpu_residual(p, n, U, block=E), ref), E
+            assert np.array_equal(gpu_residual(p, n, U, block=E, form=pt), ref), E
     with pytest.raises(B.FrError):
-        gpu_residual(p, n, U, block=emax + 1)
+        gpu_residual(p, n, U, block=emax + 1, form=pt)
+    lines = gpu_residual(p, n, U, form=B.FR_FORM_LINES)
+    assert np.array_equal(lines, gpu_residual(p, n, U, form=B.FR_FORM_LINES))
+    assert rel(lines, ref) <= 1e-13

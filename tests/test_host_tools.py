@@ -95,3 +95,17 @@ def test_new_entry_points_validate_arguments():
     assert L.fr_lhex_create(None) is None
     L.fr_lhex_destroy(None)
     assert L.fr_lhex_residual(None, None, None, None, None) == B.FR_EINVAL
+
+
+def test_bench_closed_form_manufactured_operator():
+    """bench.py's closed form of -div F + S for P = u = v = w = sin x sin y sin z
+    (the matrix-core precision study's error reference) equals the symbolic
+    differentiation of the flux."""
+    import numpy as np
+    import bench
+    from test_oracle_residual import sines_exact_residual
+    for p, n in ((2, (2, 3, 2)), (4, (2, 2, 2))):
+        E = sines_exact_residual(p, n)
+        C = bench.sines_operator(p, n)
+        assert np.max(np.abs(C - E[:, :4])) <= 1e-13
+        assert np.max(np.abs(E[:, 4:])) <= 1e-13
