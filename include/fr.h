@@ -71,7 +71,8 @@ typedef enum fr_option {
                              norm) in the fused kernel's epilogue, so the residual never goes
                              to memory (not available at p = 6 with a non-diagonal Jacobian,
                              which keeps the separate kernel); 0: residual kernel + separate
-                             stage kernel.  The states are bitwise identical either way; the
+                             stage kernel.  With FR_OPT_FORM = FR_FORM_POINT the states are
+                             bitwise identical either way (otherwise equal to rounding); the
                              norm's summation order (per workgroup) differs.                 */
     FR_OPT_PSEUDO = 8,    /* pseudo-time scheme of fr_dual_step and of every fr_pmg level:
                              0 (default) classical RK4 with the fixed step dtau; 1 the RK34
@@ -81,13 +82,17 @@ typedef enum fr_option {
                              (e the embedded error estimate, tol the call's tolerance) and
                              kept within [dtau/3, 3 dtau].  The step field persists in the
                              plan between calls with the same dtau.                           */
-    FR_OPT_FORM = 9       /* kernel form of the FR_FUSED residual (fr_residual; the stage
-                             epilogue keeps the point form): FR_FORM_AUTO (default) the
-                             line form where the Jacobian is diagonal, else the point form;
-                             FR_FORM_POINT elements staged in LDS, every point contracting
-                             its own lines; FR_FORM_LINES one lane per element line and
-                             direction, state read straight into registers (diagonal
-                             Jacobians only: FR_EUNSUPPORTED otherwise).                     */
+    FR_OPT_FORM = 9       /* kernel form of the FR_FUSED residual kernel: FR_FORM_POINT the
+                             batch staged in LDS with the transformed fluxes, every point
+                             contracting its own lines; FR_FORM_LINES (diagonal Jacobians
+                             only, FR_EUNSUPPORTED otherwise) the batch staged in LDS, one
+                             lane per element line and direction computing the flux, its
+                             own traces, the common fluxes and the six corrected line
+                             derivatives in registers; FR_FORM_AUTO (default) the line form
+                             where it measured faster (diagonal Jacobian, p = 2, 3, 4 in
+                             FR_F64, p = 2, 3, 5, 6 in FR_F32), else the point form.  The
+                             forms agree to rounding (not bitwise); the stage epilogue of
+                             fr_rk_step / fr_dual_step always uses the point form.      */
 } fr_option;
 
 /* Kernel identifiers for fr_plan_kernel_stats. */

@@ -140,5 +140,58 @@ __device__ __forceinline__ void flux_dot(const T U[NV], const T nv[3], T zeta, T
     }
 }
 
+// 16-byte vector of the working precision
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <typename T> struct V16;
+template <> struct V16<double> { using type = d2v; };
+template <> struct V16<float> { using type = f4v; };
+
+// LDS layout of the line form: the batch's elements at a pitch of EP values
+// (13 m^3 padded so that consecutive elements start at bank offsets m^2 apart:
+// lanes of neighbouring elements then read neighbouring banks).
+template <int P, typename T>
+struct LinesLds {
+    static constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    static constexpr int BANKV = sizeof(T) == 8 ? 32 : 64;  // values per bank sweep of a read
+    static constexpr int raw = NV * NS;
+    static constexpr int EP = raw + ((NF - raw % BANKV) % BANKV + BANKV) % BANKV;
+    // whole 16-byte chunks per element, so that the copy can use vectors
+    static constexpr bool VEC = (raw * sizeof(T)) % 16 == 0 && (EP * sizeof(T)) % 16 == 0;
+    // the operator block, padded to 16 bytes
+    static constexpr int OPS = (OpsLayout<M>::size * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
+    // LDS values of a batch of E elements: operators, state tile, three
+    // directions' P and momentum parts
+    static constexpr int values(int E, bool xr) { return OPS + E * EP + (xr ? 8 : 12) * E * NS; }
+};
+
+// A batch's contiguous state block (nel elements from src) into the line
+// form's LDS tile (element pitch EP), in 16-byte vectors where the element
+// size allows.
+template <int P, typename T, int NT>
+__device__ __forceinline__ void tile_load(const T *__restrict__ src, T *__restrict__ sU, int nel)
+{
+    using LL = LinesLds<P, T>;
+    constexpr int EP = LL::EP, RAW = LL::raw;
+    if constexpr (LL::VEC) {
+        using V = typename V16<T>::type;
+        constexpr int VW = 16 / sizeof(T), CPE = RAW / VW;  // chunks per element
+        const int nch = nel * CPE;
+        const V *sv = reinterpret_cast<const V *>(src);
+#pragma unroll 4
+        for (int k = threadIdx.x; k < nch; k += NT) {
+            const int ek = k / CPE, o = k - ek * CPE;
+            reinterpret_cast<V *>(sU + ek * EP)[o] = __builtin_nontemporal_load(sv + k);
+        }
+    } else {
+        const int nv = nel * RAW;
+#pragma unroll 4
+        for (int k = threadIdx.x; k < nv; k += NT) {
+            const int ek = k / RAW, o = k - ek * RAW;
+            sU[ek * EP + o] = __builtin_nontemporal_load(src + k);
+        }
+    }
+}
+
 }  // namespace dev
 }  // namespace fr

@@ -114,9 +114,13 @@ struct fr_plan {
     fr::GraphCache graphs[3];
     // persistent grid sizes of the fused path on this plan's device, per
     // (order, precision, diagonal Jacobian): [0] trace kernel, [1] fused kernel,
-    // [2] fused kernel with the stage epilogue, [3] its matrix-core form;
-    // [4] 1 once the line-form kernel's LDS limit is set
-    int fused_grid[5][fr::PMAX + 1][2][2] = {};
+    // [2] fused kernel with the stage epilogue, [3] its matrix-core form
+    int fused_grid[4][fr::PMAX + 1][2][2] = {};
+    // 1 once the LDS limit of the line-form kernels is set on this plan's
+    // device, per (kernel: 0 residual, 1 traces; order; precision)
+    int lines_attr[2][fr::PMAX + 1][2] = {};
+    // 1 once the LDS limit of the unfused stage-1 kernel is set (order, precision)
+    int unfused_attr[fr::PMAX + 1][2] = {};
     int device;
     // host copies of the operators (double)
     double x[8], w[8], D[64], lm[8], lp[8], gl[8], gr[8], Dt[64];

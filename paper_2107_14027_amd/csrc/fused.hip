@@ -25,11 +25,6 @@ namespace fr {
 namespace {
 using namespace dev;
 
-typedef double d2v __attribute__((ext_vector_type(2)));
-typedef float f4v __attribute__((ext_vector_type(4)));
-template <typename T> struct V16;
-template <> struct V16<double> { using type = d2v; };
-template <> struct V16<float> { using type = f4v; };
 
 // Launch shape per order and precision: EMAX elements per batch (a runtime
 // block size E <= EMAX may be chosen) and NT threads per workgroup.  Each
@@ -526,6 +521,13 @@ template <int P, typename T, bool DIAG> struct StageEpilogue {
     static constexpr bool value =
         LineDiv<P, DIAG>::value || Shape<P, T>::EMAX * NS <= Shape<P, T>::NT;
 };
+
+// Face traces of one element line, written to the neighbours' receiving
+// blocks (defined with the line form below).
+template <int P, typename T, int D>
+__device__ __forceinline__ void line_traces_out(const T *__restrict__ Ut, const T *__restrict__ lm,
+                                                const T *__restrict__ lp, T *__restrict__ TR,
+                                                int64_t e, int L, int nx, int ny, int nz, int64_t ne);
 
 template <int P, typename T, bool DIAG, bool STG, bool MF = false>
 __global__ void __launch_bounds__((Shape<P, T>::NT))
@@ -1043,6 +1045,28 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
                 using V = typename V16<T>::type;
                 constexpr int CH = TL::CH, CHV = TL::CHV, W = TL::W;
                 __syncthreads();
+                if constexpr (DIAG) {
+                    // one task per (direction, element, line)
+                    T lmr[M], lpr[M];
+#pragma unroll
+                    for (int l = 0; l < M; ++l) {
+                        lmr[l] = sop[OL::lm + l];
+                        lpr[l] = sop[OL::lp + l];
+                    }
+                    T *TRs = static_cast<T *>(sp.tr_out);
+                    for (unsigned t = tid; t < 3u * EMAX * NF; t += NT) {
+                        const unsigned dd = t / (EMAX * NF), r = t - dd * (EMAX * NF);
+                        const unsigned el = r / NF, L = r - el * NF;
+                        if ((int)el >= nel) continue;
+                        const T *Ut = sU + el * NV * NS;
+                        if (dd == 0)
+                            line_traces_out<P, T, 0>(Ut, lmr, lpr, TRs, e0 + el, L, sp.nx, sp.ny, sp.nz, ne);
+                        else if (dd == 1)
+                            line_traces_out<P, T, 1>(Ut, lmr, lpr, TRs, e0 + el, L, sp.nx, sp.ny, sp.nz, ne);
+                        else
+                            line_traces_out<P, T, 2>(Ut, lmr, lpr, TRs, e0 + el, L, sp.nx, sp.ny, sp.nz, ne);
+                    }
+                } else {
                 V *TRo = static_cast<V *>(sp.tr_out);
                 for (unsigned t = tid; t < 6u * EMAX * CHV; t += NT) {
                     const unsigned f = t / (EMAX * CHV), r = t - f * (EMAX * CHV);
@@ -1065,6 +1089,7 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
                     }
                     const int64_t nb = neighbour(e0 + el, (int)f, sp.nx, sp.ny, sp.nz);
                     __builtin_nontemporal_store(x, TRo + ((int64_t)(f ^ 1) * ne + nb) * CHV + k);
+                }
                 }
             }
         }
@@ -1124,16 +1149,16 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #define FR_LW3_D 1
 #endif
 #ifndef FR_LE4_D
-#define FR_LE4_D 5
+#define FR_LE4_D 2
 #endif
 #ifndef FR_LW4_D
-#define FR_LW4_D 2
+#define FR_LW4_D 1
 #endif
 #ifndef FR_LE5_D
-#define FR_LE5_D 3
+#define FR_LE5_D 1
 #endif
 #ifndef FR_LW5_D
-#define FR_LW5_D 2
+#define FR_LW5_D 1
 #endif
 #ifndef FR_LE6_D
 #define FR_LE6_D 1
@@ -1166,10 +1191,10 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #define FR_LW4_F 2
 #endif
 #ifndef FR_LE5_F
-#define FR_LE5_F 7
+#define FR_LE5_F 3
 #endif
 #ifndef FR_LW5_F
-#define FR_LW5_F 4
+#define FR_LW5_F 2
 #endif
 #ifndef FR_LE6_F
 #define FR_LE6_F 1
@@ -1177,25 +1202,91 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #ifndef FR_LW6_F
 #define FR_LW6_F 1
 #endif
-// LDS layout of the line form: the batch's elements at a pitch of EP values
-// (13 m^3 padded so that consecutive elements start at bank offsets m^2 apart:
-// lanes of neighbouring elements then read neighbouring banks).
-template <int P, typename T>
-struct LinesLds {
-    static constexpr int M = P + 1, NS = M * M * M, NF = M * M;
-    static constexpr int BANKV = sizeof(T) == 8 ? 32 : 64;  // values per bank sweep of a read
-    static constexpr int raw = NV * NS;
-    static constexpr int EP = raw + ((NF - raw % BANKV) % BANKV + BANKV) % BANKV;
-    // whole 16-byte chunks per element, so that the copy can use vectors
-    static constexpr bool VEC = (raw * sizeof(T)) % 16 == 0 && (EP * sizeof(T)) % 16 == 0;
-};
 
+#ifndef FR_LX1_D
+#define FR_LX1_D 0
+#endif
+#ifndef FR_LX2_D
+#define FR_LX2_D 0
+#endif
+#ifndef FR_LX3_D
+#define FR_LX3_D 0
+#endif
+#ifndef FR_LX4_D
+#define FR_LX4_D 0
+#endif
+#ifndef FR_LX5_D
+#define FR_LX5_D 0
+#endif
+#ifndef FR_LX6_D
+#define FR_LX6_D 0
+#endif
+#ifndef FR_LX1_F
+#define FR_LX1_F 0
+#endif
+#ifndef FR_LX2_F
+#define FR_LX2_F 0
+#endif
+#ifndef FR_LX3_F
+#define FR_LX3_F 0
+#endif
+#ifndef FR_LX4_F
+#define FR_LX4_F 0
+#endif
+#ifndef FR_LX5_F
+#define FR_LX5_F 1
+#endif
+#ifndef FR_LX6_F
+#define FR_LX6_F 1
+#endif
+// FR_FORM_AUTO's choice per order and precision (1: line form), from the
+// measured fused-kernel times of both forms on the order-sweep lattices
+// (periodic box, about 16.6-22.0 M points): the line form is faster at
+// p = 2, 3, 4 in double and p = 2, 3, 5, 6 in single precision.
+#ifndef FR_LA1_D
+#define FR_LA1_D 0
+#endif
+#ifndef FR_LA2_D
+#define FR_LA2_D 1
+#endif
+#ifndef FR_LA3_D
+#define FR_LA3_D 1
+#endif
+#ifndef FR_LA4_D
+#define FR_LA4_D 1
+#endif
+#ifndef FR_LA5_D
+#define FR_LA5_D 0
+#endif
+#ifndef FR_LA6_D
+#define FR_LA6_D 0
+#endif
+#ifndef FR_LA1_F
+#define FR_LA1_F 0
+#endif
+#ifndef FR_LA2_F
+#define FR_LA2_F 1
+#endif
+#ifndef FR_LA3_F
+#define FR_LA3_F 1
+#endif
+#ifndef FR_LA4_F
+#define FR_LA4_F 0
+#endif
+#ifndef FR_LA5_F
+#define FR_LA5_F 1
+#endif
+#ifndef FR_LA6_F
+#define FR_LA6_F 1
+#endif
 template <int P, typename T> struct LinesShape;
 #define FR_LSHAPE(PP, TT, S)                                                        \
     template <> struct LinesShape<PP, TT> {                                         \
         static constexpr int E = FR_LE##PP##_##S, W = FR_LW##PP##_##S, NT = 192 * W; \
         static_assert(E * (PP + 1) * (PP + 1) <= 64 * W, "one lane per line");       \
-        static_assert(E * LinesLds<PP, TT>::EP * sizeof(TT) <= 160 * 1024, "LDS");    \
+        static constexpr bool XR = FR_LX##PP##_##S;                                  \
+        static constexpr bool AUTO = FR_LA##PP##_##S;                                \
+        static_assert(LinesLds<PP, TT>::values(E, XR) * sizeof(TT) <= 160 * 1024, "LDS"); \
     };
 FR_LSHAPE(1, double, D)
 FR_LSHAPE(2, double, D)
@@ -1269,32 +1360,28 @@ __device__ __forceinline__ void line_store(T *__restrict__ p, const T (&x)[M])
 }
 
 
-// One direction's line task on the element tile Ue (LDS).  On return ctb[0][r]
-// holds the P part zeta n_dd du_d/dxi_d + dissipation and ctb[1 + i][r] the
-// corrected derivative of the transformed momentum flux i at the line's point r.
-template <int P, typename T, int D>
-__device__ __forceinline__ void line_task(const T *__restrict__ Ut, const T *__restrict__ TR,
-                                          T *__restrict__ R, const T *__restrict__ ops,
-                                          const Consts<T> &c, int ne, int64_t e, int L,
+
+// One direction's line task on the element tile Ut (LDS, updated in place).
+// sop: the operator block in LDS; oth{m,p}: the neighbours' traces on the
+// line's two face points; sCd: this direction's P / momentum slots of the
+// element, [4][m^3].  Writes, at every point r of the line, the auxiliary
+// residual (a, D) over S_aD in the tile (only this lane touches those values)
+// and the direction's P part zeta n_DD du_D/dxi_D + dissipation and corrected
+// momentum-flux derivatives to sCd ([4][m^3] slots of the element), or with XR
+// to ctb[0..3][r] in registers.
+template <int P, typename T, int D, bool XR>
+__device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restrict__ sop,
+                                          const T (&othm)[NTR], const T (&othp)[NTR],
+                                          const Consts<T> &c, int L, T *__restrict__ sCd,
                                           T (&ctb)[4][P + 1])
 {
-    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    constexpr int M = P + 1, NS = M * M * M;
     constexpr int STR = D == 0 ? 1 : (D == 1 ? M : M * M);
-    using TL = TraceLayout<M, T>;
     using OL = OpsLayout<M>;
     const int a = L % M, b = L / M;
     const int base = D == 0 ? M * L : (D == 1 ? a + M * M * b : L);
-    // the neighbours' traces on this line's two face points (issued first)
-    const T *tm = TR + ((int64_t)(2 * D) * ne + e) * TL::CHP + L;
-    const T *tp = TR + ((int64_t)(2 * D + 1) * ne + e) * TL::CHP + L;
-    T othm[NTR], othp[NTR];
-#pragma unroll
-    for (int cc = 0; cc < NTR; ++cc) {
-        othm[cc] = __builtin_nontemporal_load(tm + cc * NF);
-        othp[cc] = __builtin_nontemporal_load(tp + cc * NF);
-    }
+    T *Ue = Ut + base;
     // P, u, v, w, S_0D, S_1D, S_2D along the line
-    const T *Ue = Ut + base;
     T X[7][M];
 #pragma unroll
     for (int v = 0; v < 4; ++v) line_load<M, STR>(Ue + v * NS, X[v]);
@@ -1303,14 +1390,20 @@ __device__ __forceinline__ void line_task(const T *__restrict__ Ut, const T *__r
     // own traces (k_trace's chain) and the two common fluxes
     T FIm[NTR], FIp[NTR];
     {
+        T lm[M], lp[M];
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            lm[l] = sop[OL::lm + l];
+            lp[l] = sop[OL::lp + l];
+        }
         T ownm[NTR], ownp[NTR];
 #pragma unroll
         for (int cc = 0; cc < NTR; ++cc) {
             T am = T(0), ap = T(0);
 #pragma unroll
             for (int l = 0; l < M; ++l) {
-                am = fma(ops[OL::lm + l], X[cc][l], am);
-                ap = fma(ops[OL::lp + l], X[cc][l], ap);
+                am = fma(lm[l], X[cc][l], am);
+                ap = fma(lp[l], X[cc][l], ap);
             }
             ownm[cc] = am;
             ownp[cc] = ap;
@@ -1320,40 +1413,54 @@ __device__ __forceinline__ void line_task(const T *__restrict__ Ut, const T *__r
         common_flux_sided<T>(ownp, othp, true, nh, c.nmag[D], c.zeta, c.nu, FIp);
     }
     const T ndd = c.nvec[D][D];
-    // velocity derivatives: auxiliary residuals (a, D) and the P part
-#pragma unroll
-    for (int va = 0; va < 3; ++va) {
-        T aux[M];
-#pragma unroll
-        for (int r = 0; r < M; ++r) {
-            T s = T(0);
-#pragma unroll
-            for (int l = 0; l < M; ++l) s = fma(ops[OL::Dt + r * M + l], X[1 + va][l], s);
-            const T cd = fma(ops[OL::gl + r], FIm[4 + va], fma(ops[OL::gr + r], FIp[4 + va], s));
-            const T gv = cd * ndd;
-            aux[r] = c.invT * fma(c.inv_det, gv, -X[4 + va][r]);
-            if (va == D)
-                ctb[0][r] = fma(c.zeta, gv, fma(ops[OL::gl + r], FIm[0], ops[OL::gr + r] * FIp[0]));
-        }
-        line_store<M, STR>(R + e * (NV * NS) + (4 + 3 * va + D) * NS + base, aux);
-    }
     // transformed momentum fluxes F_D,i = n_DD (u_i u_D + P delta_iD - nu S_iD)
+    T F[3][M];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        T F[M];
+    for (int l = 0; l < M; ++l) {
+        const T vn = X[1 + D][l] * ndd;
 #pragma unroll
-        for (int l = 0; l < M; ++l) {
-            const T vn = X[1 + D][l] * ndd;
+        for (int i = 0; i < 3; ++i) {
             const T sn = X[4 + i][l] * ndd;
-            F[l] = i == D ? fma(X[1 + i][l], vn, fma(X[0][l], ndd, -c.nu * sn))
-                          : fma(X[1 + i][l], vn, -c.nu * sn);
+            F[i][l] = i == D ? fma(X[1 + i][l], vn, fma(X[0][l], ndd, -c.nu * sn))
+                             : fma(X[1 + i][l], vn, -c.nu * sn);
         }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // row by row: the corrected derivatives of the three velocities (auxiliary
+    // residuals (a, D), P part) and of the three fluxes
 #pragma unroll
-        for (int r = 0; r < M; ++r) {
+    for (int r = 0; r < M; ++r) {
+        // one row's operator values at a time (bounds the live registers)
+        __builtin_amdgcn_sched_barrier(0);
+        T Dr[M];
+#pragma unroll
+        for (int l = 0; l < M; ++l) Dr[l] = sop[OL::Dt + r * M + l];
+        const T glr = sop[OL::gl + r], grr = sop[OL::gr + r];
+        const int q = r * STR;
+        T pc = T(0);
+#pragma unroll
+        for (int va = 0; va < 3; ++va) {
             T s = T(0);
 #pragma unroll
-            for (int l = 0; l < M; ++l) s = fma(ops[OL::Dt + r * M + l], F[l], s);
-            ctb[1 + i][r] = fma(ops[OL::gl + r], FIm[1 + i], fma(ops[OL::gr + r], FIp[1 + i], s));
+            for (int l = 0; l < M; ++l) s = fma(Dr[l], X[1 + va][l], s);
+            const T cd = fma(glr, FIm[4 + va], fma(grr, FIp[4 + va], s));
+            const T gv = cd * ndd;
+            // S_aD at this point is read back from the tile (the line's copy in
+            // registers is dead by now) and replaced by the auxiliary residual
+            T *sq = Ue + (4 + 3 * va + D) * NS + q;
+            *sq = c.invT * fma(c.inv_det, gv, -*sq);
+            if (va == D) pc = fma(c.zeta, gv, fma(glr, FIm[0], grr * FIp[0]));
+        }
+        if constexpr (XR) ctb[0][r] = pc;
+        else sCd[base + q] = pc;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            T s = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) s = fma(Dr[l], F[i][l], s);
+            const T cf = fma(glr, FIm[1 + i], fma(grr, FIp[1 + i], s));
+            if constexpr (XR) ctb[1 + i][r] = cf;
+            else sCd[(1 + i) * NS + base + q] = cf;
         }
     }
 }
@@ -1365,77 +1472,166 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
 {
     constexpr int M = P + 1, NS = M * M * M, NF = M * M;
     constexpr int E = LinesShape<P, T>::E, W = LinesShape<P, T>::W, NT = LinesShape<P, T>::NT;
+    constexpr bool XR = LinesShape<P, T>::XR;
     using LL = LinesLds<P, T>;
+    using TL = TraceLayout<M, T>;
+    using OL = OpsLayout<M>;
     constexpr int EP = LL::EP, RAW = LL::raw;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sU = reinterpret_cast<T *>(smem_raw);  // [E][EP]
+    T *sop = reinterpret_cast<T *>(smem_raw);  // operators
+    T *sU = sop + LL::OPS;                     // [E][EP] state tile
+    // P and momentum parts per direction, [3][E][4][NS] (with XR the x
+    // direction's stay in its lanes' registers and only y and z are here)
+    T *sC = sU + E * EP - (XR ? 4 * E * NS : 0);
     const int64_t e0 = (int64_t)blockIdx.x * E;
     const int nel = (int)min((int64_t)E, (int64_t)ne - e0);
-    // the batch's state block into LDS
-    {
-        const T *src = U + e0 * RAW;
-        if constexpr (LL::VEC) {
-            using V = typename V16<T>::type;
-            constexpr int VW = 16 / sizeof(T), CPE = RAW / VW;  // chunks per element
-            const int nch = nel * CPE;
-            const V *sv = reinterpret_cast<const V *>(src);
-#pragma unroll 4
-            for (int k = threadIdx.x; k < nch; k += NT) {
-                const int el = k / CPE, o = k - el * CPE;
-                reinterpret_cast<V *>(sU + el * EP)[o] = __builtin_nontemporal_load(sv + k);
-            }
-        } else {
-            const int nv = nel * RAW;
-#pragma unroll 4
-            for (int k = threadIdx.x; k < nv; k += NT) {
-                const int el = k / RAW, o = k - el * RAW;
-                sU[el * EP + o] = __builtin_nontemporal_load(src + k);
-            }
-        }
-    }
-    __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int d = wave / W;
     const int t = (wave - d * W) * 64 + (threadIdx.x & 63);
     const int el = t / NF, L = t - el * NF;
     const bool act = el < nel;
     const int64_t e = e0 + el;
-    T *Ut = sU + el * EP;
+    // the neighbours' traces on this lane's line, requested before the state
+    T othm[NTR], othp[NTR];
+    if (act) {
+        const T *tm = TR + ((int64_t)(2 * d) * ne + e) * TL::CHP + L;
+        const T *tp = TR + ((int64_t)(2 * d + 1) * ne + e) * TL::CHP + L;
+#pragma unroll
+        for (int cc = 0; cc < NTR; ++cc) {
+            othm[cc] = __builtin_nontemporal_load(tm + cc * NF);
+            othp[cc] = __builtin_nontemporal_load(tp + cc * NF);
+        }
+    }
+    if (threadIdx.x < OL::size) sop[threadIdx.x] = ops[threadIdx.x];
+    // the batch's state block into LDS
+    tile_load<P, T, NT>(U + e0 * RAW, sU, nel);
+    __syncthreads();
     T ctb[4][M];
     if (act) {
-        if (d == 0) line_task<P, T, 0>(Ut, TR, R, ops, c, ne, e, L, ctb);
-        else if (d == 1) line_task<P, T, 1>(Ut, TR, R, ops, c, ne, e, L, ctb);
-        else line_task<P, T, 2>(Ut, TR, R, ops, c, ne, e, L, ctb);
-    }
-    // every read of the state tile is done: the P and momentum parts of
-    // directions y (slots 0-3) and z (slots 4-7) go over it
-    __syncthreads();
-    if (act && d == 1) {
-        const int a = L % M, b = L / M;
-        T *dst = Ut + a + M * M * b;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int r = 0; r < M; ++r) dst[k * NS + r * M] = ctb[k][r];
-    } else if (act && d == 2) {
-        T *dst = Ut + 4 * NS + L;
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int r = 0; r < M; ++r) dst[k * NS + r * NF] = ctb[k][r];
+        T *Ut = sU + el * EP;
+        T *sCd = sC + ((d * E + el) * 4) * NS;
+        if (d == 0) line_task<P, T, 0, XR>(Ut, sop, othm, othp, c, L, sCd, ctb);
+        else if (d == 1) line_task<P, T, 1, false>(Ut, sop, othm, othp, c, L, sCd, ctb);
+        else line_task<P, T, 2, false>(Ut, sop, othm, othp, c, L, sCd, ctb);
     }
     __syncthreads();
-    if (act && d == 0) {
-        const T *cy = Ut + M * L;
-        const T *cz = Ut + 4 * NS + M * L;
-        T *Re = R + e * (NV * NS) + M * L;
+    if constexpr (XR) {
+        // x lanes: their own parts plus those of y and z at the x-line's points
+        if (act && d == 0) {
+            const T *cy = sC + ((E + el) * 4) * NS + M * L;
+            const T *cz = sC + ((2 * E + el) * 4) * NS + M * L;
+            T *Re = R + e * (NV * NS) + M * L;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            T o[M];
+            for (int k = 0; k < 4; ++k) {
+                T o[M];
 #pragma unroll
-            for (int r = 0; r < M; ++r) o[r] = -c.inv_det * ((ctb[k][r] + cy[k * NS + r]) + cz[k * NS + r]);
-            line_store<M, 1>(Re + k * NS, o);
+                for (int r = 0; r < M; ++r)
+                    o[r] = -c.inv_det * ((ctb[k][r] + cy[k * NS + r]) + cz[k * NS + r]);
+                line_store<M, 1>(Re + k * NS, o);
+            }
         }
+        // every thread: the auxiliary residuals from the tile
+        T *dst = R + e0 * RAW;
+        constexpr int A0 = 4 * NS, NA = 9 * NS;
+        if constexpr (LL::VEC && (A0 * sizeof(T)) % 16 == 0) {
+            using V = typename V16<T>::type;
+            constexpr int VW = 16 / sizeof(T), CPE = NA / VW;
+            const int nch = nel * CPE;
+#pragma unroll 4
+            for (int k = threadIdx.x; k < nch; k += NT) {
+                const int ek = k / CPE, o = k - ek * CPE;
+                __builtin_nontemporal_store(reinterpret_cast<const V *>(sU + ek * EP + A0)[o],
+                                            reinterpret_cast<V *>(dst + ek * RAW + A0) + o);
+            }
+        } else {
+            const int nv = nel * NA;
+#pragma unroll 4
+            for (int k = threadIdx.x; k < nv; k += NT) {
+                const int ek = k / NA, o = k - ek * NA;
+                __builtin_nontemporal_store(sU[ek * EP + A0 + o], dst + ek * RAW + A0 + o);
+            }
+        }
+        return;
+    }
+    // R of the batch, one contiguous block: P and momentum summed over the
+    // three directions in order, the auxiliary residuals from the tile
+    T *dst = R + e0 * RAW;
+    const T mid = -c.inv_det;
+    if constexpr (LL::VEC) {
+        using V = typename V16<T>::type;
+        constexpr int VW = 16 / sizeof(T), CPE = RAW / VW, C4 = 4 * NS / VW;
+        static_assert((4 * NS) % VW == 0, "P and momentum in whole chunks");
+        const int nch = nel * CPE;
+#pragma unroll 4
+        for (int k = threadIdx.x; k < nch; k += NT) {
+            const int ek = k / CPE, o = k - ek * CPE;
+            V x;
+            if (o < C4) {
+                const V *cx = reinterpret_cast<const V *>(sC + (ek * 4) * NS) + o;
+                const V *cy = reinterpret_cast<const V *>(sC + ((E + ek) * 4) * NS) + o;
+                const V *cz = reinterpret_cast<const V *>(sC + ((2 * E + ek) * 4) * NS) + o;
+                const V vx = *cx, vy = *cy, vz = *cz;
+#pragma unroll
+                for (int w = 0; w < VW; ++w) x[w] = mid * ((vx[w] + vy[w]) + vz[w]);
+            } else {
+                x = reinterpret_cast<const V *>(sU + ek * EP)[o];
+            }
+            __builtin_nontemporal_store(x, reinterpret_cast<V *>(dst) + k);
+        }
+    } else {
+        const int nv = nel * RAW;
+#pragma unroll 4
+        for (int k = threadIdx.x; k < nv; k += NT) {
+            const int ek = k / RAW, o = k - ek * RAW;
+            T x;
+            if (o < 4 * NS) {
+                const T *cx = sC + (ek * 4) * NS + o;
+                x = mid * ((cx[0] + cx[E * 4 * NS]) + cx[2 * E * 4 * NS]);
+            } else {
+                x = sU[ek * EP + o];
+            }
+            __builtin_nontemporal_store(x, dst + k);
+        }
+    }
+}
+
+// The two face traces (7 values each) of the direction-D line through face
+// point L of the element tile Ut (element pitch of the line form), written to
+// the receiving blocks of the neighbours across faces 2D and 2D+1.
+template <int P, typename T, int D>
+__device__ __forceinline__ void line_traces_out(const T *__restrict__ Ut, const T *__restrict__ lm,
+                                                const T *__restrict__ lp, T *__restrict__ TR,
+                                                int64_t e, int L, int nx, int ny, int nz, int64_t ne)
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    constexpr int STR = D == 0 ? 1 : (D == 1 ? M : M * M);
+    using TL = TraceLayout<M, T>;
+    const int a = L % M, b = L / M;
+    const int base = D == 0 ? M * L : (D == 1 ? a + M * M * b : L);
+    const T *Ue = Ut + base;
+    T tm[NTR], tp[NTR];
+#pragma unroll
+    for (int cc = 0; cc < NTR; ++cc) {
+        T x[M];
+        line_load<M, STR>(Ue + (cc < 4 ? cc : 4 + 3 * (cc - 4) + D) * NS, x);
+        T am = T(0), ap = T(0);
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            am = fma(lm[l], x[l], am);
+            ap = fma(lp[l], x[l], ap);
+        }
+        tm[cc] = am;
+        tp[cc] = ap;
+    }
+    // the minus face's values go to the minus neighbour's plus-face block and
+    // the plus face's to the plus neighbour's minus-face block
+    const int64_t nbm = neighbour(e, 2 * D, nx, ny, nz), nbp = neighbour(e, 2 * D + 1, nx, ny, nz);
+    T *dm = TR + ((int64_t)(2 * D + 1) * ne + nbm) * TL::CHP + L;
+    T *dp = TR + ((int64_t)(2 * D) * ne + nbp) * TL::CHP + L;
+#pragma unroll
+    for (int cc = 0; cc < NTR; ++cc) {
+        __builtin_nontemporal_store(tm[cc], dm + cc * NF);
+        __builtin_nontemporal_store(tp[cc], dp + cc * NF);
     }
 }
 
@@ -1474,7 +1670,9 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
         kfu = (const void *)k_fused<P, T, DIAG, false, true>;
     }
     // line-task form of the plain residual (diagonal Jacobian)
-    const bool lines = !MF && !sp && DIAG && pl->form == FR_FORM_LINES;
+    const bool lines = !MF && !sp && DIAG &&
+                       (pl->form == FR_FORM_LINES ||
+                        (pl->form == FR_FORM_AUTO && LinesShape<P, T>::AUTO));
     if (!MF && !sp && !DIAG && pl->form == FR_FORM_LINES)
         return set_error(FR_EUNSUPPORTED, "line-task form: diagonal Jacobians only");
     // persistent grid: every workgroup that fits on the device at once
@@ -1512,9 +1710,9 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
     }
     if (lines) {
         constexpr int LE = LinesShape<P, T>::E, LNT = LinesShape<P, T>::NT;
-        const size_t lds_li = (size_t)LE * LinesLds<P, T>::EP * sizeof(T);
+        const size_t lds_li = (size_t)LinesLds<P, T>::values(LE, LinesShape<P, T>::XR) * sizeof(T);
         const int64_t nb = ((int64_t)ne + LE - 1) / LE;
-        int &set = pl->fused_grid[4][P][sizeof(T) == 8][DIAG];
+        int &set = pl->lines_attr[0][P][sizeof(T) == 8];
         if (!set) {
             if (int rc = check_hip(hipFuncSetAttribute((const void *)k_lines<P, T>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,

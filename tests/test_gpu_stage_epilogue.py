@@ -26,6 +26,8 @@ def pair(p, n, prec, jac):
     for fuse in (1, 0):
         pl = B.Plan(p, n, ZETA, NU, T_CFG, jac, prec, B.FR_FUSED)
         pl.set(B.FR_OPT_FUSE_STAGE, fuse)
+        # the same residual arithmetic on both paths: the epilogue is the point form's
+        pl.set(B.FR_OPT_FORM, B.FR_FORM_POINT)
         out.append(pl)
     return out
 
