@@ -466,6 +466,9 @@ def main():
     ap.add_argument("--no-acm", action="store_true",
                     help="skip the comparison-system timings: standard ACM (LDG) beside ACM-HD, "
                          "and ACM-HD on linear hexahedra")
+    ap.add_argument("--learned64", default="5,2",
+                    help="TRAIN,EVAL physical steps of the learned-guess study on the 64^3 lattice "
+                         "(p=3, dt 1e-2, dtau 1e-3, tol 1e-6, P-multigrid); 0,0 skips it")
     ap.add_argument("--no-mfma", action="store_true",
                     help="skip the matrix-core precision form (p=4, 64^3 manufactured solution)")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -556,7 +559,8 @@ def main():
     nedom = ndom[0] * ndom[1] * ndom[2]
     dom_bytes = floor_bytes(pdom, nedom, 8)
     achieved = dom_bytes / kstats[pdom]["fused_ms"] / 1e6
-    kname = "k_fused_p%d_f64" % pdom
+    form = B.fr_plan_get_int(next(w[2] for w in work if w[0] == pdom).handle, B.FR_INFO_RESIDUAL_FORM)
+    kname = "%s_p%d_f64" % ("k_lines" if form == B.FR_FORM_LINES else "k_fused", pdom)
     traffic = read_traffic(kname)
     design = fused_bytes(pdom, nedom, 8)
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
@@ -703,6 +707,28 @@ def main():
                 "checked_vs_linear": rnd4(rp["checked_vs_linear_iters"]),
                 "seconds": round(time.perf_counter() - t1, 1)},
             "kernels": kern}
+        tr64, ev64 = (int(x) for x in args.learned64.split(","))
+        if tr64 > 0 and ev64 > 0:
+            t2 = time.perf_counter()
+            r6 = L.run(p=3, N=64, dt=1e-2, dtau=1e-3, tol=1e-6, solver="pmg", max_cycles=400,
+                       train_steps=tr64, eval_steps=ev64, guess_base=1, samples_per_step=1 << 16,
+                       modes=("extrap", "extrap1", "mlp"), progress_every=1)
+            m6 = r6["modes"]
+            learned["lattice_64"] = {
+                "unit": "P-multigrid cycles per physical step (mean over the evaluation steps)",
+                "workload": "dual time stepping BDF2 + P-multigrid RK4 pseudo-steps, Taylor-Green Re 1600, "
+                            "p=3, 64^3 hexes, dt=0.01, dtau=0.001, tol 1e-06, cap 400 cycles; %d training "
+                            "steps (65536 sampled points each), %d evaluation steps from the identical "
+                            "state" % (tr64, ev64),
+                "learned": round(m6["mlp"]["iters_mean"], 2),
+                "quadratic_extrap": round(m6["extrap"]["iters_mean"], 2),
+                "linear_extrap": round(m6["extrap1"]["iters_mean"], 2),
+                "capped": {k: m6[v]["capped"] for k, v in (("learned", "mlp"), ("quadratic_extrap", "extrap"),
+                                                           ("linear_extrap", "extrap1"))},
+                "learned_vs_quadratic": rnd4(r6["mlp_vs_quadratic_iters"]),
+                "learned_vs_linear": rnd4(r6["mlp_vs_linear_iters"]),
+                "training_loss": r6["loss_curve"][-1][1],
+                "seconds": round(time.perf_counter() - t2, 1)}
         log("learned guess: %s" % learned)
 
     out = {

@@ -136,6 +136,10 @@ fr_plan *fr_plan_create(int p, int nx, int ny, int nz, const double jac[9], doub
  * that no longer applies.  FR_EINVAL for an unknown key or value. */
 int fr_plan_set_int(fr_plan *plan, int key, int value);
 int fr_plan_get_int(const fr_plan *plan, int key, int *value);
+/* Read-only key of fr_plan_get_int: the kernel form fr_residual runs with the
+ * plan's current settings (FR_FORM_POINT or FR_FORM_LINES; 0 for FR_UNFUSED
+ * and FR_MFMA). */
+enum { FR_INFO_RESIDUAL_FORM = 100 };
 
 /* Release the plan and all device memory it owns (waits for the device). */
 void fr_plan_destroy(fr_plan *plan);

@@ -19,6 +19,7 @@ FR_F64, FR_F32 = 0, 1
 FR_K_TRACE, FR_K_FUSED = 0, 1
 FR_FUSED, FR_UNFUSED, FR_MFMA = 0, 1, 2
 FR_FORM_AUTO, FR_FORM_POINT, FR_FORM_LINES = 0, 1, 2
+FR_INFO_RESIDUAL_FORM = 100
 NV = 13
 
 EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_destroy",

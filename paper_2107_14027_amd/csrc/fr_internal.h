@@ -182,6 +182,9 @@ int launch_residual(fr_plan *pl, const void *U, void *R, hipStream_t s);
 int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *nparts,
                           hipStream_t s);
 bool fused_stage_available(const fr_plan *pl);
+// kernel form fr_residual runs on this plan (FR_FORM_POINT or FR_FORM_LINES;
+// 0 for the unfused and matrix-core variants)
+int residual_form(const fr_plan *pl);
 // the two trace arrays of the stage epilogue's ping-pong (allocated on first use)
 int stage_trace_buffers(fr_plan *pl, void *&a, void *&b);
 

@@ -1361,6 +1361,15 @@ __device__ __forceinline__ void line_store(T *__restrict__ p, const T (&x)[M])
 
 
 
+// Whether the line task's row loop stays rolled (per order and precision;
+// fewer live registers against loop overhead).
+#ifndef FR_LROLL
+#define FR_LROLL 1
+#endif
+template <int P, typename T> struct LinesRolled {
+    static constexpr bool value = FR_LROLL != 0;
+};
+
 // One direction's line task on the element tile Ut (LDS, updated in place).
 // sop: the operator block in LDS; oth{m,p}: the neighbours' traces on the
 // line's two face points; sCd: this direction's P / momentum slots of the
@@ -1381,13 +1390,8 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
     const int a = L % M, b = L / M;
     const int base = D == 0 ? M * L : (D == 1 ? a + M * M * b : L);
     T *Ue = Ut + base;
-    // P, u, v, w, S_0D, S_1D, S_2D along the line
-    T X[7][M];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) line_load<M, STR>(Ue + v * NS, X[v]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) line_load<M, STR>(Ue + (4 + 3 * i + D) * NS, X[4 + i]);
-    // own traces (k_trace's chain) and the two common fluxes
+    // own traces (k_trace's chain), one variable's line at a time, and the two
+    // common fluxes
     T FIm[NTR], FIp[NTR];
     {
         T lm[M], lp[M];
@@ -1399,11 +1403,13 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
         T ownm[NTR], ownp[NTR];
 #pragma unroll
         for (int cc = 0; cc < NTR; ++cc) {
+            T x[M];
+            line_load<M, STR>(Ue + (cc < 4 ? cc : 4 + 3 * (cc - 4) + D) * NS, x);
             T am = T(0), ap = T(0);
 #pragma unroll
             for (int l = 0; l < M; ++l) {
-                am = fma(lm[l], X[cc][l], am);
-                ap = fma(lp[l], X[cc][l], ap);
+                am = fma(lm[l], x[l], am);
+                ap = fma(lp[l], x[l], ap);
             }
             ownm[cc] = am;
             ownp[cc] = ap;
@@ -1412,24 +1418,37 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
         common_flux_sided<T>(ownm, othm, false, nh, c.nmag[D], c.zeta, c.nu, FIm);
         common_flux_sided<T>(ownp, othp, true, nh, c.nmag[D], c.zeta, c.nu, FIp);
     }
+    // the lines are read again below rather than kept live through the
+    // common-flux arithmetic (the barrier stops the compiler from reusing the
+    // first reads)
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
     const T ndd = c.nvec[D][D];
-    // transformed momentum fluxes F_D,i = n_DD (u_i u_D + P delta_iD - nu S_iD)
-    T F[3][M];
+    // the velocities along the line and the transformed momentum fluxes
+    // F_D,i = n_DD (u_i u_D + P delta_iD - nu S_iD) (P and S read once more)
+    T X[3][M], F[3][M];
 #pragma unroll
-    for (int l = 0; l < M; ++l) {
-        const T vn = X[1 + D][l] * ndd;
+    for (int ia = 0; ia < 3; ++ia) line_load<M, STR>(Ue + (1 + ia) * NS, X[ia]);
+    {
+        T Pl[M];
+        line_load<M, STR>(Ue, Pl);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-            const T sn = X[4 + i][l] * ndd;
-            F[i][l] = i == D ? fma(X[1 + i][l], vn, fma(X[0][l], ndd, -c.nu * sn))
-                             : fma(X[1 + i][l], vn, -c.nu * sn);
+            T Sl[M];
+            line_load<M, STR>(Ue + (4 + 3 * i + D) * NS, Sl);
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                const T vn = X[D][l] * ndd;
+                const T sn = Sl[l] * ndd;
+                F[i][l] = i == D ? fma(X[i][l], vn, fma(Pl[l], ndd, -c.nu * sn))
+                                 : fma(X[i][l], vn, -c.nu * sn);
+            }
         }
     }
     __builtin_amdgcn_sched_barrier(0);
     // row by row: the corrected derivatives of the three velocities (auxiliary
     // residuals (a, D), P part) and of the three fluxes
-#pragma unroll
-    for (int r = 0; r < M; ++r) {
+    auto row = [&](int r) {
         // one row's operator values at a time (bounds the live registers)
         __builtin_amdgcn_sched_barrier(0);
         T Dr[M];
@@ -1442,7 +1461,7 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
         for (int va = 0; va < 3; ++va) {
             T s = T(0);
 #pragma unroll
-            for (int l = 0; l < M; ++l) s = fma(Dr[l], X[1 + va][l], s);
+            for (int l = 0; l < M; ++l) s = fma(Dr[l], X[va][l], s);
             const T cd = fma(glr, FIm[4 + va], fma(grr, FIp[4 + va], s));
             const T gv = cd * ndd;
             // S_aD at this point is read back from the tile (the line's copy in
@@ -1462,6 +1481,15 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
             if constexpr (XR) ctb[1 + i][r] = cf;
             else sCd[(1 + i) * NS + base + q] = cf;
         }
+    };
+    // with XR the row index selects registers, so the loop is unrolled;
+    // otherwise it stays rolled (fewer live registers)
+    if constexpr (XR || !LinesRolled<P, T>::value) {
+#pragma unroll
+        for (int r = 0; r < M; ++r) row(r);
+    } else {
+#pragma unroll 1
+        for (int r = 0; r < M; ++r) row(r);
     }
 }
 
@@ -1636,6 +1664,185 @@ __device__ __forceinline__ void line_traces_out(const T *__restrict__ Ut, const 
 }
 
 // ---------------------------------------------------------------------------
+// k_trace_lines: stage 1 for a diagonal Jacobian.  A workgroup copies a batch
+// of TLE consecutive elements into LDS (the line form's tile); one task per
+// (direction d, element, line) projects the seven trace variables (P, u, v, w,
+// S_0d, S_1d, S_2d) to both ends of its line with k_trace's fma chain and puts
+// them in an LDS copy of the batch's outgoing blocks; the workgroup then writes
+// every block to its receiving slot (the neighbour across the face) in
+// 16-byte vectors, as k_trace does.
+// ---------------------------------------------------------------------------
+#ifndef FR_TLE1_D
+#define FR_TLE1_D 16
+#endif
+#ifndef FR_TLE2_D
+#define FR_TLE2_D 7
+#endif
+#ifndef FR_TLE3_D
+#define FR_TLE3_D 4
+#endif
+#ifndef FR_TLE4_D
+#define FR_TLE4_D 2
+#endif
+#ifndef FR_TLE5_D
+#define FR_TLE5_D 1
+#endif
+#ifndef FR_TLE6_D
+#define FR_TLE6_D 1
+#endif
+#ifndef FR_TLE1_F
+#define FR_TLE1_F 32
+#endif
+#ifndef FR_TLE2_F
+#define FR_TLE2_F 14
+#endif
+#ifndef FR_TLE3_F
+#define FR_TLE3_F 8
+#endif
+#ifndef FR_TLE4_F
+#define FR_TLE4_F 4
+#endif
+#ifndef FR_TLE5_F
+#define FR_TLE5_F 2
+#endif
+#ifndef FR_TLE6_F
+#define FR_TLE6_F 1
+#endif
+#ifndef FR_TLNT
+#define FR_TLNT 256
+#endif
+#ifndef FR_TLU1_D
+#define FR_TLU1_D 0
+#endif
+#ifndef FR_TLU2_D
+#define FR_TLU2_D 0
+#endif
+#ifndef FR_TLU3_D
+#define FR_TLU3_D 0
+#endif
+#ifndef FR_TLU4_D
+#define FR_TLU4_D 0
+#endif
+#ifndef FR_TLU5_D
+#define FR_TLU5_D 1
+#endif
+#ifndef FR_TLU6_D
+#define FR_TLU6_D 0
+#endif
+#ifndef FR_TLU1_F
+#define FR_TLU1_F 0
+#endif
+#ifndef FR_TLU2_F
+#define FR_TLU2_F 0
+#endif
+#ifndef FR_TLU3_F
+#define FR_TLU3_F 0
+#endif
+#ifndef FR_TLU4_F
+#define FR_TLU4_F 0
+#endif
+#ifndef FR_TLU5_F
+#define FR_TLU5_F 1
+#endif
+#ifndef FR_TLU6_F
+#define FR_TLU6_F 1
+#endif
+// Whether stage 1 runs as k_trace_lines (1) or k_trace (0) for a diagonal
+// Jacobian, per order and precision, from the measured times of both on the
+// order-sweep lattices (both write the same bits).
+template <int P, typename T> struct TraceLinesShape;
+#define FR_TLSHAPE(PP, TT, S)                                                                  \
+    template <> struct TraceLinesShape<PP, TT> {                                               \
+        static constexpr int E = FR_TLE##PP##_##S, NT = FR_TLNT;                               \
+        static constexpr bool USE = FR_TLU##PP##_##S;                                          \
+        static constexpr int OUT = 6 * E * TraceLayout<PP + 1, TT>::CHP;                       \
+        static constexpr int values = LinesLds<PP, TT>::OPS + E * LinesLds<PP, TT>::EP + OUT;  \
+        static_assert(values * sizeof(TT) <= 160 * 1024, "LDS");                               \
+    };
+FR_TLSHAPE(1, double, D)
+FR_TLSHAPE(2, double, D)
+FR_TLSHAPE(3, double, D)
+FR_TLSHAPE(4, double, D)
+FR_TLSHAPE(5, double, D)
+FR_TLSHAPE(6, double, D)
+FR_TLSHAPE(1, float, F)
+FR_TLSHAPE(2, float, F)
+FR_TLSHAPE(3, float, F)
+FR_TLSHAPE(4, float, F)
+FR_TLSHAPE(5, float, F)
+FR_TLSHAPE(6, float, F)
+#undef FR_TLSHAPE
+
+template <int P, typename T>
+__global__ void __launch_bounds__(FR_TLNT)
+    k_trace_lines(const T *__restrict__ U, T *__restrict__ TR, const T *__restrict__ ops, int nx,
+                  int ny, int nz)
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
+    constexpr int E = TraceLinesShape<P, T>::E, NT = TraceLinesShape<P, T>::NT;
+    using LL = LinesLds<P, T>;
+    using OL = OpsLayout<M>;
+    using TL = TraceLayout<M, T>;
+    using V = typename V16<T>::type;
+    constexpr int EP = LL::EP, RAW = LL::raw, CH = TL::CH, CHP = TL::CHP, CHV = TL::CHV;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sop = reinterpret_cast<T *>(smem_raw);
+    T *sU = sop + LL::OPS;       // [E][EP]
+    T *sO = sU + E * EP;         // [6][E][CHP] outgoing blocks, by own face
+    const int64_t ne = (int64_t)nx * ny * nz;
+    const int64_t e0 = (int64_t)blockIdx.x * E;
+    const int nel = (int)min((int64_t)E, ne - e0);
+    if (threadIdx.x < 2 * M) sop[OL::lm + threadIdx.x] = ops[OL::lm + threadIdx.x];
+    // the padding of every outgoing block is written as zeros
+    if constexpr (CHP > CH)
+        for (int k = threadIdx.x; k < 6 * E * (CHP - CH); k += NT)
+            sO[(k / (CHP - CH)) * CHP + CH + k % (CHP - CH)] = T(0);
+    tile_load<P, T, NT>(U + e0 * RAW, sU, nel);
+    __syncthreads();
+    T lm[M], lp[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        lm[l] = sop[OL::lm + l];
+        lp[l] = sop[OL::lp + l];
+    }
+    for (int t = threadIdx.x; t < 3 * E * NF; t += NT) {
+        const int d = t / (E * NF), r = t - d * (E * NF);
+        const int el = r / NF, L = r - el * NF;
+        if (el >= nel) continue;
+        const int a = L % M, b = L / M;
+        const int str = d == 0 ? 1 : (d == 1 ? M : M * M);
+        const int base = d == 0 ? M * L : (d == 1 ? a + M * M * b : L);
+        const T *Ue = sU + el * EP + base;
+        T *om = sO + ((2 * d) * E + el) * CHP + L;
+        T *op = om + E * CHP;
+#pragma unroll
+        for (int cc = 0; cc < NTR; ++cc) {
+            const T *X = Ue + (cc < 4 ? cc : 4 + 3 * (cc - 4) + d) * NS;
+            T am = T(0), ap = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                const T x = X[l * str];
+                am = fma(lm[l], x, am);
+                ap = fma(lp[l], x, ap);
+            }
+            om[cc * NF] = am;
+            op[cc * NF] = ap;
+        }
+    }
+    __syncthreads();
+    // block (f, el) goes to the receiving block (f ^ 1, neighbour across f)
+    V *TRv = reinterpret_cast<V *>(TR);
+    const V *sOv = reinterpret_cast<const V *>(sO);
+    for (int t = threadIdx.x; t < 6 * E * CHV; t += NT) {
+        const int fe = t / CHV, k = t - fe * CHV;
+        const int f = fe / E, el = fe - f * E;
+        if (el >= nel) continue;
+        const int64_t nb = neighbour(e0 + el, f, nx, ny, nz);
+        __builtin_nontemporal_store(sOv[t], TRv + ((int64_t)(f ^ 1) * ne + nb) * CHV + k);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launch
 // ---------------------------------------------------------------------------
 template <int P, typename T, bool DIAG, bool MF>
@@ -1703,6 +1910,21 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
     const unsigned gfu = (unsigned)min(min(nbatch, grid_fu), sp ? MAX_PARTIALS : grid_fu);
     if (sp && sp->tr_in) {
         TR = static_cast<T *>(const_cast<void *>(sp->tr_in));
+    } else if (DIAG && TraceLinesShape<P, T>::USE) {
+        using TLS = TraceLinesShape<P, T>;
+        const size_t lds_tl = (size_t)TLS::values * sizeof(T);
+        int &set = pl->lines_attr[1][P][sizeof(T) == 8];
+        if (!set) {
+            if (int rc = check_hip(hipFuncSetAttribute((const void *)k_trace_lines<P, T>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)lds_tl),
+                                   "hipFuncSetAttribute"))
+                return rc;
+            set = 1;
+        }
+        ProfScope ps(prof ? pl : nullptr, FR_K_TRACE, s);
+        hipLaunchKernelGGL((k_trace_lines<P, T>), dim3((unsigned)((ne + TLS::E - 1) / TLS::E)),
+                           dim3(TLS::NT), lds_tl, s, U, TR, ops, pl->nx, pl->ny, pl->nz);
     } else {
         ProfScope ps(prof ? pl : nullptr, FR_K_TRACE, s);
         hipLaunchKernelGGL((k_trace<P, T, DIAG>), dim3(gtr), dim3(TNT), lds_tr, s, U, TR, ops, c,
@@ -1858,6 +2080,28 @@ int launch_residual_noalloc(fr_plan *pl, const void *U, void *R, hipStream_t s)
     return fused_any(pl, U, R, nullptr, nullptr, s, ptr, false, pl->variant == FR_MFMA);
 }
 
+
+int residual_form(const fr_plan *pl)
+{
+    if (pl->variant != FR_FUSED) return 0;
+    if (pl->c64.diag == 0 || pl->form == FR_FORM_POINT) return FR_FORM_POINT;
+    if (pl->form == FR_FORM_LINES) return FR_FORM_LINES;
+    const bool f64 = pl->precision == FR_F64;
+    auto pick = [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        return (f64 ? LinesShape<P, double>::AUTO : LinesShape<P, float>::AUTO) ? FR_FORM_LINES
+                                                                                : FR_FORM_POINT;
+    };
+    switch (pl->p) {
+        case 1: return pick(Dir<1>{});
+        case 2: return pick(Dir<2>{});
+        case 3: return pick(Dir<3>{});
+        case 4: return pick(Dir<4>{});
+        case 5: return pick(Dir<5>{});
+        case 6: return pick(Dir<6>{});
+    }
+    return FR_FORM_POINT;
+}
 
 bool fused_stage_available(const fr_plan *pl)
 {

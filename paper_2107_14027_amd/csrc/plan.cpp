@@ -419,6 +419,7 @@ int fr_plan_get_int(const fr_plan *pl, int key, int *value)
         case FR_OPT_FUSE_STAGE: *value = pl->fuse_stage; return FR_OK;
         case FR_OPT_PSEUDO: *value = pl->pseudo; return FR_OK;
         case FR_OPT_FORM: *value = pl->form; return FR_OK;
+        case FR_INFO_RESIDUAL_FORM: *value = fr::residual_form(pl); return FR_OK;
         default: return set_error(FR_EINVAL, "unknown option %d", key);
     }
 }

@@ -5,9 +5,10 @@
 //                      values), line tasks on an LDS-staged batch
 //   k_u_flux     stage 2  F_s  = transformed flux at the points (3 x 13 values)
 //   k_u_div_lds  stage 3  partially corrected divergence of F_s, staged in LDS
-//                         one variable at a time
-//   k_u_common   stage 4  common interface flux, one per unique face
-//   k_u_correct  stage 5  correction with the common fluxes
+//                         one direction at a time
+//   k_u_common_lds   stage 4  common interface flux, one per unique face,
+//                            face blocks staged in LDS
+//   k_u_correct_lds  stage 5  correction with the common fluxes, staged in LDS
 //   k_u_negsrc   stage 6  negate, scale by 1/det J, add the source
 #include "fr_device.h"
 
@@ -39,73 +40,6 @@ __global__ void __launch_bounds__(256) k_u_flux(const T *__restrict__ U, T *__re
         flux_dot<T>(u, nv, c.zeta, c.nu, c.invT, f);
 #pragma unroll
         for (int v = 0; v < NV; ++v) Fs[(((int64_t)d * ne + e) * NV + v) * NS + q] = f[v];
-    }
-}
-
-// Common flux for the plus face of every element (one per unique face),
-// all 13 variables, transformed by |n_d|.
-template <int P, typename T>
-__global__ void __launch_bounds__(256) k_u_common(const T *__restrict__ Uf, T *__restrict__ FI,
-                                                  Consts<T> c, int nx, int ny, int nz)
-{
-    constexpr int M = P + 1, NF = M * M;
-    const int64_t ne = (int64_t)nx * ny * nz;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ne * 3 * NF) return;
-    const int fp = (int)(t % NF);
-    const int64_t r = t / NF;
-    const int64_t e = r % ne;
-    const int d = (int)(r / ne);
-    const int64_t nb = neighbour(e, 2 * d + 1, nx, ny, nz);
-    T L[NV], Rr[NV];
-    for (int v = 0; v < NV; ++v) {
-        L[v] = Uf[(((int64_t)(2 * d + 1) * ne + e) * NV + v) * NF + fp];
-        Rr[v] = Uf[(((int64_t)(2 * d) * ne + nb) * NV + v) * NF + fp];
-    }
-    T nh[3] = {c.nhat[d][0], c.nhat[d][1], c.nhat[d][2]};
-    T fl[NV], fr[NV];
-    flux_dot<T>(L, nh, c.zeta, c.nu, c.invT, fl);
-    flux_dot<T>(Rr, nh, c.zeta, c.nu, c.invT, fr);
-    T vnl = L[1] * nh[0] + L[2] * nh[1] + L[3] * nh[2];
-    T vnr = Rr[1] * nh[0] + Rr[2] * nh[1] + Rr[3] * nh[2];
-    const T al = fabs(vnl) + sqrt(vnl * vnl + c.zeta);
-    const T ar = fabs(vnr) + sqrt(vnr * vnr + c.zeta);
-    const T lam = al > ar ? al : ar;
-    T *dst = FI + (((int64_t)d * ne + e) * NV) * NF + fp;
-    for (int v = 0; v < NV; ++v) {
-        T f = T(0.5) * (fl[v] + fr[v]);
-        if (v < 4) f -= T(0.5) * lam * (Rr[v] - L[v]);
-        dst[v * NF] = c.nmag[d] * f;
-    }
-}
-
-template <int P, typename T>
-__global__ void __launch_bounds__(256) k_u_correct(T *__restrict__ Dv, const T *__restrict__ FI,
-                                                   const T *__restrict__ ops, int nx, int ny,
-                                                   int nz)
-{
-    constexpr int M = P + 1, NS = M * M * M, NF = M * M;
-    using OL = OpsLayout<M>;
-    const int64_t ne = (int64_t)nx * ny * nz;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ne * NS) return;
-    const int64_t e = t / NS;
-    const int q = (int)(t - e * NS);
-    const int idx[3] = {q % M, (q / M) % M, q / (M * M)};
-    const int fa[3] = {idx[1], idx[0], idx[0]}, fb[3] = {idx[2], idx[2], idx[1]};
-    int64_t lo[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) lo[d] = neighbour(e, 2 * d, nx, ny, nz);
-    for (int v = 0; v < NV; ++v) {
-        T acc = Dv[(e * NV + v) * NS + q];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const int fp = fa[d] + M * fb[d];
-            const T fm = FI[(((int64_t)d * ne + lo[d]) * NV + v) * NF + fp];
-            const T fpl = FI[(((int64_t)d * ne + e) * NV + v) * NF + fp];
-            acc = fma(ops[OL::gl + idx[d]], fm, fma(ops[OL::gr + idx[d]], fpl, acc));
-        }
-        Dv[(e * NV + v) * NS + q] = acc;
     }
 }
 
@@ -178,47 +112,224 @@ __global__ void __launch_bounds__((ProjectShape<P, T>::NT))
     }
 }
 
-// Stage 3 with the element's flux staged in LDS one variable at a time: a
-// workgroup takes E elements; per variable it copies the three directions'
-// transformed flux of its elements (contiguous runs of m^3 values) into LDS and
-// every thread contracts its points' three lines.
+// Copy of n contiguous values from global src to LDS dst (16-byte vectors
+// when both ends and the count allow).
+template <typename T, int NT>
+__device__ __forceinline__ void block_copy_in(const T *__restrict__ src, T *__restrict__ dst, int n)
+{
+    using V = typename V16<T>::type;
+    constexpr int VW = 16 / sizeof(T);
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0 && n % VW == 0) {
+        for (int k = threadIdx.x; k < n / VW; k += NT)
+            reinterpret_cast<V *>(dst)[k] = __builtin_nontemporal_load(reinterpret_cast<const V *>(src) + k);
+    } else {
+        for (int k = threadIdx.x; k < n; k += NT) dst[k] = __builtin_nontemporal_load(src + k);
+    }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void block_copy_out(const T *__restrict__ src, T *__restrict__ dst, int n)
+{
+    using V = typename V16<T>::type;
+    constexpr int VW = 16 / sizeof(T);
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0 && n % VW == 0) {
+        for (int k = threadIdx.x; k < n / VW; k += NT)
+            __builtin_nontemporal_store(reinterpret_cast<const V *>(src)[k], reinterpret_cast<V *>(dst) + k);
+    } else {
+        for (int k = threadIdx.x; k < n; k += NT) __builtin_nontemporal_store(src[k], dst + k);
+    }
+}
+
+// Gather of nel blocks of BL contiguous values, block el from src + nb[el] * BL,
+// into consecutive LDS blocks (16-byte vectors when BL allows).
+template <typename T, int NT, int BL>
+__device__ __forceinline__ void copy_blocks(const T *__restrict__ src, const int64_t *nb,
+                                            T *__restrict__ dst, int nel)
+{
+    using V = typename V16<T>::type;
+    constexpr int VW = 16 / sizeof(T);
+    if constexpr ((BL * sizeof(T)) % 16 == 0) {
+        constexpr int CB = BL / VW;
+        for (int k = threadIdx.x; k < nel * CB; k += NT) {
+            const int el = k / CB, o = k - el * CB;
+            reinterpret_cast<V *>(dst)[k] =
+                __builtin_nontemporal_load(reinterpret_cast<const V *>(src + nb[el] * BL) + o);
+        }
+    } else {
+        for (int k = threadIdx.x; k < nel * BL; k += NT) {
+            const int el = k / BL, o = k - el * BL;
+            dst[k] = __builtin_nontemporal_load(src + nb[el] * BL + o);
+        }
+    }
+}
+
+// Stage 3 with the batch's transformed flux staged in LDS one direction at a
+// time (a contiguous block of E elements x 13 variables per direction); each
+// thread accumulates its point's 13 divergences over the three directions in
+// registers, in the order d = 0, 1, 2.
 template <int P, typename T>
 struct DivShape {
     static constexpr int M = P + 1, NS = M * M * M;
     static constexpr int E = NS >= 256 ? 1 : 256 / NS;
-    static constexpr int NT = E * NS < 256 ? (E * NS + 63) / 64 * 64 : 256;
+    static constexpr int NT = 256;
+    static constexpr int KP = (E * NS + NT - 1) / NT;   // points per thread
 };
 
 template <int P, typename T>
-__global__ void __launch_bounds__((DivShape<P, T>::NT))
+__global__ void __launch_bounds__(256)
     k_u_div_lds(const T *__restrict__ Fs, T *__restrict__ Dv, const T *__restrict__ ops, int64_t ne)
 {
     constexpr int M = P + 1, NS = M * M * M;
-    constexpr int E = DivShape<P, T>::E, NT = DivShape<P, T>::NT;
+    constexpr int E = DivShape<P, T>::E, NT = DivShape<P, T>::NT, KP = DivShape<P, T>::KP;
     using OL = OpsLayout<M>;
-    __shared__ T sF[3][E][NS];
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sF = reinterpret_cast<T *>(smem_raw);   // [E][13][NS] of one direction
     const int64_t e0 = (int64_t)blockIdx.x * E;
     const int nel = (int)min((int64_t)E, ne - e0);
-    for (int v = 0; v < NV; ++v) {
-        if (v) __syncthreads();
-        for (int k = threadIdx.x; k < 3 * nel * NS; k += NT) {
-            const int dd = k / (nel * NS), r = k - dd * (nel * NS);
-            const int el = r / NS, q = r - el * NS;
-            sF[dd][el][q] = Fs[(((int64_t)dd * ne + e0 + el) * NV + v) * NS + q];
-        }
+    T acc[KP][NV];
+#pragma unroll
+    for (int u = 0; u < KP; ++u)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[u][v] = T(0);
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+        if (dd) __syncthreads();
+        block_copy_in<T, NT>(Fs + ((int64_t)dd * ne + e0) * NV * NS, sF, nel * NV * NS);
         __syncthreads();
-        for (int k = threadIdx.x; k < nel * NS; k += NT) {
+        const int str = dd == 0 ? 1 : (dd == 1 ? M : M * M);
+#pragma unroll
+        for (int u = 0; u < KP; ++u) {
+            const int k = threadIdx.x + u * NT;
+            if (k >= nel * NS) continue;
             const int el = k / NS, q = k - el * NS;
-            const int i = q % M, j = (q / M) % M, kk = q / (M * M);
-            T acc = T(0);
+            const int id = dd == 0 ? q % M : (dd == 1 ? (q / M) % M : q / (M * M));
+            const T *Fe = sF + el * NV * NS + q - id * str;
 #pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(ops[OL::Dt + i * M + l], sF[0][el][q - i + l], acc);
+            for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int l = 0; l < M; ++l) acc = fma(ops[OL::Dt + j * M + l], sF[1][el][q + (l - j) * M], acc);
+                for (int l = 0; l < M; ++l)
+                    acc[u][v] = fma(ops[OL::Dt + id * M + l], Fe[v * NS + l * str], acc[u][v]);
+        }
+    }
 #pragma unroll
-            for (int l = 0; l < M; ++l)
-                acc = fma(ops[OL::Dt + kk * M + l], sF[2][el][q + (l - kk) * M * M], acc);
-            Dv[((e0 + el) * NV + v) * NS + q] = acc;
+    for (int u = 0; u < KP; ++u) {
+        const int k = threadIdx.x + u * NT;
+        if (k >= nel * NS) continue;
+        const int el = k / NS, q = k - el * NS;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Dv[((e0 + el) * NV + v) * NS + q] = acc[u][v];
+    }
+}
+
+// Stage 4 with the face blocks staged in LDS: a workgroup takes direction d and
+// E consecutive elements, copies their +d face blocks and the -d face blocks
+// of their +d neighbours (contiguous runs), forms the common flux of every face
+// point into LDS and writes the E output blocks as one contiguous run.
+template <int P, typename T>
+struct CommonShape {
+    static constexpr int M = P + 1, NF = M * M;
+    static constexpr int E = NF >= 64 ? 1 : 64 / NF;
+    static constexpr int NT = 64 * ((E * NF + 63) / 64);
+};
+
+template <int P, typename T>
+__global__ void __launch_bounds__((CommonShape<P, T>::NT))
+    k_u_common_lds(const T *__restrict__ Uf, T *__restrict__ FI, Consts<T> c, int nx, int ny, int nz)
+{
+    constexpr int M = P + 1, NF = M * M, BL = NV * NF;
+    constexpr int E = CommonShape<P, T>::E, NT = CommonShape<P, T>::NT;
+    __shared__ __align__(16) T sL[E * BL], sR[E * BL], sO[E * BL];
+    const int64_t ne = (int64_t)nx * ny * nz;
+    const int64_t nb_blocks = (ne + E - 1) / E;
+    const int d = (int)(blockIdx.x / nb_blocks);
+    const int64_t e0 = (int64_t)(blockIdx.x - (int64_t)d * nb_blocks) * E;
+    const int nel = (int)min((int64_t)E, ne - e0);
+    block_copy_in<T, NT>(Uf + ((int64_t)(2 * d + 1) * ne + e0) * BL, sL, nel * BL);
+    // the neighbours' -d blocks, one contiguous block per element
+    __shared__ int64_t sNb[E];
+    if (threadIdx.x < nel) sNb[threadIdx.x] = neighbour(e0 + threadIdx.x, 2 * d + 1, nx, ny, nz);
+    __syncthreads();
+    copy_blocks<T, NT, BL>(Uf + (int64_t)(2 * d) * ne * BL, sNb, sR, nel);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < nel * NF) {
+        const int el = t / NF, fp = t - el * NF;
+        T L[NV], Rr[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            L[v] = sL[el * BL + v * NF + fp];
+            Rr[v] = sR[el * BL + v * NF + fp];
+        }
+        T nh[3] = {c.nhat[d][0], c.nhat[d][1], c.nhat[d][2]};
+        T fl[NV], fr[NV];
+        flux_dot<T>(L, nh, c.zeta, c.nu, c.invT, fl);
+        flux_dot<T>(Rr, nh, c.zeta, c.nu, c.invT, fr);
+        T vnl = L[1] * nh[0] + L[2] * nh[1] + L[3] * nh[2];
+        T vnr = Rr[1] * nh[0] + Rr[2] * nh[1] + Rr[3] * nh[2];
+        const T al = fabs(vnl) + sqrt(vnl * vnl + c.zeta);
+        const T ar = fabs(vnr) + sqrt(vnr * vnr + c.zeta);
+        const T lam = al > ar ? al : ar;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T f = T(0.5) * (fl[v] + fr[v]);
+            if (v < 4) f -= T(0.5) * lam * (Rr[v] - L[v]);
+            sO[el * BL + v * NF + fp] = c.nmag[d] * f;
+        }
+    }
+    __syncthreads();
+    block_copy_out<T, NT>(sO, FI + ((int64_t)d * ne + e0) * BL, nel * BL);
+}
+
+// Stage 5 with the common-flux blocks staged in LDS: a workgroup takes E
+// consecutive elements, copies for each direction their own blocks (+d faces)
+// and their -d neighbours' blocks, and corrects every point's 13 values.
+template <int P, typename T>
+struct CorrectShape {
+    static constexpr int M = P + 1, NS = M * M * M;
+    static constexpr int E = NS >= 256 ? 1 : (256 / NS < 16 ? 256 / NS : 16);
+    static constexpr int NT = 256;
+};
+
+template <int P, typename T>
+__global__ void __launch_bounds__(256)
+    k_u_correct_lds(T *__restrict__ Dv, const T *__restrict__ FI, const T *__restrict__ ops, int nx,
+                    int ny, int nz)
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M, BL = NV * NF;
+    constexpr int E = CorrectShape<P, T>::E, NT = CorrectShape<P, T>::NT;
+    using OL = OpsLayout<M>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sP = reinterpret_cast<T *>(smem_raw);   // [3][E][BL] own (+d) blocks
+    T *sM = sP + 3 * E * BL;                    // [3][E][BL] -d neighbours' blocks
+    const int64_t ne = (int64_t)nx * ny * nz;
+    const int64_t e0 = (int64_t)blockIdx.x * E;
+    const int nel = (int)min((int64_t)E, ne - e0);
+    __shared__ int64_t sNb[3][E];
+    if (threadIdx.x < 3 * nel)
+        sNb[threadIdx.x / nel][threadIdx.x % nel] =
+            neighbour(e0 + threadIdx.x % nel, 2 * (threadIdx.x / nel), nx, ny, nz);
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        block_copy_in<T, NT>(FI + ((int64_t)d * ne + e0) * BL, sP + d * E * BL, nel * BL);
+        copy_blocks<T, NT, BL>(FI + (int64_t)d * ne * BL, sNb[d], sM + d * E * BL, nel);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nel * NS; k += NT) {
+        const int el = k / NS, q = k - el * NS;
+        const int idx[3] = {q % M, (q / M) % M, q / (M * M)};
+        const int fps[3] = {idx[1] + M * idx[2], idx[0] + M * idx[2], idx[0] + M * idx[1]};
+        T *Dq = Dv + ((e0 + el) * NV) * NS + q;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T acc = Dq[v * NS];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T fm = sM[(d * E + el) * BL + v * NF + fps[d]];
+                const T fpl = sP[(d * E + el) * BL + v * NF + fps[d]];
+                acc = fma(ops[OL::gl + idx[d]], fm, fma(ops[OL::gr + idx[d]], fpl, acc));
+            }
+            Dq[v * NS] = acc;
         }
     }
 }
@@ -260,17 +371,20 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
         ProfScope ps(pl, FR_K_U_DIV, s);
         using DS = DivShape<P, T>;
         hipLaunchKernelGGL((k_u_div_lds<P, T>), dim3((unsigned)((ne + DS::E - 1) / DS::E)),
-                           dim3(DS::NT), 0, s, Fs, Dv, ops, ne);
+                           dim3(DS::NT), (size_t)DS::E * NV * NS * sizeof(T), s, Fs, Dv, ops, ne);
     }
     {
         ProfScope ps(pl, FR_K_U_COMMON, s);
-        hipLaunchKernelGGL((k_u_common<P, T>), g(ne * 3 * NF), dim3(nt), 0, s, Uf, FI, c, pl->nx,
-                           pl->ny, pl->nz);
+        using CS = CommonShape<P, T>;
+        hipLaunchKernelGGL((k_u_common_lds<P, T>), dim3((unsigned)(3 * ((ne + CS::E - 1) / CS::E))),
+                           dim3(CS::NT), 0, s, Uf, FI, c, pl->nx, pl->ny, pl->nz);
     }
     {
         ProfScope ps(pl, FR_K_U_CORRECT, s);
-        hipLaunchKernelGGL((k_u_correct<P, T>), g(ne * NS), dim3(nt), 0, s, Dv, FI, ops, pl->nx,
-                           pl->ny, pl->nz);
+        using RS = CorrectShape<P, T>;
+        hipLaunchKernelGGL((k_u_correct_lds<P, T>), dim3((unsigned)((ne + RS::E - 1) / RS::E)),
+                           dim3(RS::NT), (size_t)6 * RS::E * NV * NF * sizeof(T), s, Dv, FI, ops,
+                           pl->nx, pl->ny, pl->nz);
     }
     {
         ProfScope ps(pl, FR_K_U_NEGSRC, s);

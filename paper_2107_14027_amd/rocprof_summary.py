@@ -107,7 +107,7 @@ def traffic(args):
     fs, fcal, fk, fn = res["FETCH_SIZE"]
     ws, wcal, wk, wn = res["WRITE_SIZE"]
     for k in sorted(set(fk) & set(wk)):
-        m = re.match(r"(k_fused|k_trace)<(\d+),(\w+)>", k)
+        m = re.match(r"(k_fused|k_trace|k_lines|k_trace_lines|k_fused_stage)<(\d+),(\w+)>", k)
         if not m:
             continue
         tag = "%s_p%s_%s" % (m.group(1), m.group(2), "f64" if m.group(3) == "double" else "f32")

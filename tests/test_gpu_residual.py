@@ -134,3 +134,25 @@ def test_block_size_invariance_and_determinism(p):
     lines = gpu_residual(p, n, U, form=B.FR_FORM_LINES)
     assert np.array_equal(lines, gpu_residual(p, n, U, form=B.FR_FORM_LINES))
     assert rel(lines, ref) <= 1e-13
+
+
+def test_auto_form_choice_is_reported():
+    """FR_INFO_RESIDUAL_FORM names the kernel form fr_residual runs: the line
+    form at the orders the automatic choice documents (p = 2, 3, 4 in double,
+    p = 2, 3, 5, 6 in single precision, diagonal Jacobian), else the point form;
+    0 for the unfused and matrix-core variants."""
+    lines = {B.FR_F64: {2, 3, 4}, B.FR_F32: {2, 3, 5, 6}}
+    for prec in PREC:
+        for p in range(1, 7):
+            plan = B.Plan(p, (2, 2, 2), ZETA, NU, T_CFG, precision=prec)
+            want = B.FR_FORM_LINES if p in lines[prec] else B.FR_FORM_POINT
+            assert B.fr_plan_get_int(plan.handle, B.FR_INFO_RESIDUAL_FORM) == want, (prec, p)
+            plan.set(B.FR_OPT_FORM, B.FR_FORM_POINT)
+            assert B.fr_plan_get_int(plan.handle, B.FR_INFO_RESIDUAL_FORM) == B.FR_FORM_POINT
+            plan.close()
+            plan = B.Plan(p, (2, 2, 2), ZETA, NU, T_CFG, SKEW, prec)
+            assert B.fr_plan_get_int(plan.handle, B.FR_INFO_RESIDUAL_FORM) == B.FR_FORM_POINT
+            plan.close()
+    plan = B.Plan(3, (2, 2, 2), ZETA, NU, T_CFG, variant=B.FR_UNFUSED)
+    assert B.fr_plan_get_int(plan.handle, B.FR_INFO_RESIDUAL_FORM) == 0
+    plan.close()
