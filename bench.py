@@ -64,6 +64,10 @@ def trace_bytes(p, ne, esz):
     return BM.bytes_per_launch(BM.trace_values(p + 1), ne * (p + 1) ** 3, esz)
 
 
+# residual forms as the library reports them (FR_INFO_RESIDUAL_FORM)
+FORM_NAMES = {1: "point", 2: "lines", 3: "halo"}
+
+
 PAPER_CONTEXT = {
     "kernel_fusion_speedup": "3-4x fused vs unfused flux and divergence kernels, NVIDIA TITAN V, "
                              "CUDA 11.2 (abstract, Sec. 4); bandwidth bound 4x (stages 2+3) and "
@@ -189,7 +193,11 @@ def time_steps(p=3, N=64, steps=5):
         torch.cuda.synchronize()
         du = 1e3 * (time.perf_counter() - t) / max(1, it)
         key = "stage_epilogue" if fuse else "separate_stage_kernel"
-        out[key] = {"rk4_step_ms": round(rk, 3), "pseudo_step_ms": round(du, 3)}
+        out[key] = {"rk4_step_ms": round(rk, 3), "pseudo_step_ms": round(du, 3),
+                    "path": {B.FR_STAGE_SEPARATE: "residual + separate stage kernel",
+                             B.FR_STAGE_POINT: "point-form kernel with the epilogue",
+                             B.FR_STAGE_HALO: "halo-form kernel with the epilogue"}[
+                        B.fr_plan_get_int(plan.handle, B.FR_INFO_STAGE_PATH)]}
         plan.close()
         del V, W
     torch.cuda.empty_cache()
@@ -549,20 +557,26 @@ def main():
         fu_ms, fu_n = B.fr_plan_kernel_stats(plan.handle, 1)
         plan.set(B.FR_OPT_PROFILE, 0)
         fms, tms = fu_ms / max(fu_n, 1), tr_ms / max(tr_n, 1)
-        kstats[p] = dict(trace_ms=tms, fused_ms=fms, fused_total=fu_ms, launches=fu_n,
+        form = B.fr_plan_get_int(plan.handle, B.FR_INFO_RESIDUAL_FORM)
+        halo = form == B.FR_FORM_HALO
+        # the halo form has no trace kernel: its one kernel is the whole residual
+        design = floor_bytes(p, ne, 8) if halo else fused_bytes(p, ne, 8)
+        kstats[p] = dict(trace_ms=tms, fused_ms=fms, fused_total=fu_ms, launches=fu_n, form=form,
+                         design_bytes=design,
                          fused_floor_gbs=floor_bytes(p, ne, 8) / fms / 1e6,
-                         fused_gbs=fused_bytes(p, ne, 8) / fms / 1e6,
-                         trace_gbs=trace_bytes(p, ne, 8) / tms / 1e6,
+                         fused_gbs=design / fms / 1e6,
+                         trace_gbs=trace_bytes(p, ne, 8) / tms / 1e6 if tr_n else None,
                          residual_floor_gbs=floor_bytes(p, ne, 8) / (fms + tms) / 1e6)
     pdom = max(kstats, key=lambda p: kstats[p]["fused_total"])
     ndom = lattices[pdom]
     nedom = ndom[0] * ndom[1] * ndom[2]
     dom_bytes = floor_bytes(pdom, nedom, 8)
     achieved = dom_bytes / kstats[pdom]["fused_ms"] / 1e6
-    form = B.fr_plan_get_int(next(w[2] for w in work if w[0] == pdom).handle, B.FR_INFO_RESIDUAL_FORM)
-    kname = "%s_p%d_f64" % ("k_lines" if form == B.FR_FORM_LINES else "k_fused", pdom)
+    form = kstats[pdom]["form"]
+    kname = "%s_p%d_f64" % ({B.FR_FORM_LINES: "k_lines", B.FR_FORM_HALO: "k_lines_halo"}.get(form, "k_fused"),
+                             pdom)
     traffic = read_traffic(kname)
-    design = fused_bytes(pdom, nedom, 8)
+    design = kstats[pdom]["design_bytes"]
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic,
@@ -583,10 +597,12 @@ def main():
             m = p + 1
             dof = ne * NV * m ** 3
             ks = kstats[p]
-            row = {"fused_f64": dof / (ks["fused_ms"] + ks["trace_ms"]) / 1e6,
+            row = {"form_f64": FORM_NAMES[ks["form"]],
+                   "fused_f64": dof / (ks["fused_ms"] + ks["trace_ms"]) / 1e6,
                    "fused_kernel_f64_floor_frac": ks["fused_floor_gbs"] / HBM_PEAK_GBS,
                    "fused_kernel_f64_design_frac": ks["fused_gbs"] / HBM_PEAK_GBS,
-                   "trace_kernel_f64_hbm_frac": ks["trace_gbs"] / HBM_PEAK_GBS,
+                   "trace_kernel_f64_hbm_frac": (ks["trace_gbs"] / HBM_PEAK_GBS
+                                                 if ks["trace_gbs"] is not None else None),
                    "fused_residual_f64_floor_frac": ks["residual_floor_gbs"] / HBM_PEAK_GBS}
             pu = B.Plan(p, n, ZETA, NU, TRELAX, precision=B.FR_F64, variant=B.FR_UNFUSED)
             pu.set(B.FR_OPT_PROFILE, 1)
@@ -609,11 +625,13 @@ def main():
                 if var == B.FR_FUSED:
                     fu_ms, fu_n = B.fr_plan_kernel_stats(pf.handle, 1)
                     tr_ms, tr_n = B.fr_plan_kernel_stats(pf.handle, 0)
-                    fms, tms = fu_ms / fu_n, tr_ms / tr_n
+                    fms, tms = fu_ms / max(fu_n, 1), tr_ms / max(tr_n, 1)
+                    halo32 = B.fr_plan_get_int(pf.handle, B.FR_INFO_RESIDUAL_FORM) == B.FR_FORM_HALO
+                    d32 = floor_bytes(p, ne, 4) if halo32 else fused_bytes(p, ne, 4)
+                    row["form_f32"] = FORM_NAMES[B.fr_plan_get_int(pf.handle, B.FR_INFO_RESIDUAL_FORM)]
                     row["fused_kernel_f32_floor_frac"] = (floor_bytes(p, ne, 4) / fms / 1e6
                                                           / HBM_PEAK_GBS)
-                    row["fused_kernel_f32_design_frac"] = (fused_bytes(p, ne, 4) / fms / 1e6
-                                                           / HBM_PEAK_GBS)
+                    row["fused_kernel_f32_design_frac"] = d32 / fms / 1e6 / HBM_PEAK_GBS
                     row["fused_residual_f32_floor_frac"] = (floor_bytes(p, ne, 4) / (fms + tms)
                                                             / 1e6 / HBM_PEAK_GBS)
                 pf.close()
@@ -622,8 +640,9 @@ def main():
             row["speedup_fused_vs_unfused_f64"] = row["fused_f64"] / row["unfused_f64"]
             row["speedup_fused_vs_unfused_f32"] = row["fused_f32"] / row["unfused_f32"]
             # the byte-model bound on that speed-up: unfused bytes / fused-residual bytes
-            row["byte_model_speedup_bound"] = (sum(uv.values()) / BM.fused_residual_values(m))
-            sweep[str(p)] = {k: round(v, 4) for k, v in row.items()}
+            row["byte_model_speedup_bound"] = (sum(uv.values()) / BM.fused_residual_values(
+                m, halo=ks["form"] == B.FR_FORM_HALO))
+            sweep[str(p)] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in row.items()}
             log("sweep p=%d: %s" % (p, sweep[str(p)]))
 
     cpu = None

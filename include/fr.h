@@ -71,8 +71,10 @@ typedef enum fr_option {
                              norm) in the fused kernel's epilogue, so the residual never goes
                              to memory (not available at p = 6 with a non-diagonal Jacobian,
                              which keeps the separate kernel); 0: residual kernel + separate
-                             stage kernel.  With FR_OPT_FORM = FR_FORM_POINT the states are
-                             bitwise identical either way (otherwise equal to rounding); the
+                             stage kernel.  The epilogue runs in the residual's own kernel
+                             for the point and halo forms (FR_INFO_RESIDUAL_FORM), and then
+                             the states are bitwise identical either way; with the line form
+                             it runs in the point form's kernel (equal to rounding).  The
                              norm's summation order (per workgroup) differs.                 */
     FR_OPT_PSEUDO = 8,    /* pseudo-time scheme of fr_dual_step and of every fr_pmg level:
                              0 (default) classical RK4 with the fixed step dtau; 1 the RK34
@@ -82,17 +84,23 @@ typedef enum fr_option {
                              (e the embedded error estimate, tol the call's tolerance) and
                              kept within [dtau/3, 3 dtau].  The step field persists in the
                              plan between calls with the same dtau.                           */
-    FR_OPT_FORM = 9       /* kernel form of the FR_FUSED residual kernel: FR_FORM_POINT the
-                             batch staged in LDS with the transformed fluxes, every point
-                             contracting its own lines; FR_FORM_LINES (diagonal Jacobians
-                             only, FR_EUNSUPPORTED otherwise) the batch staged in LDS, one
-                             lane per element line and direction computing the flux, its
-                             own traces, the common fluxes and the six corrected line
-                             derivatives in registers; FR_FORM_AUTO (default) the line form
-                             where it measured faster (diagonal Jacobian, p = 2, 3, 4 in
-                             FR_F64, p = 2, 3, 5, 6 in FR_F32), else the point form.  The
-                             forms agree to rounding (not bitwise); the stage epilogue of
-                             fr_rk_step / fr_dual_step always uses the point form.      */
+    FR_OPT_FORM = 9       /* kernel form of the FR_FUSED residual: FR_FORM_POINT a trace
+                             kernel, then the batch staged in LDS with the transformed
+                             fluxes, every point contracting its own lines; FR_FORM_LINES
+                             (diagonal Jacobians only, FR_EUNSUPPORTED otherwise) a trace
+                             kernel, then the batch staged in LDS and one lane per element
+                             line and direction computing the flux, its own traces, the
+                             common fluxes and the six corrected line derivatives in
+                             registers; FR_FORM_HALO (diagonal Jacobians only) the line form
+                             without a trace kernel: each lane forms the neighbours' traces
+                             from their states (the batch's tile, else global memory) with
+                             the trace kernel's arithmetic, so its results are bitwise those
+                             of FR_FORM_LINES; FR_FORM_AUTO (default) the fastest measured:
+                             the halo form with a diagonal Jacobian, else the point form.
+                             The point and line forms agree to rounding (not bitwise); the
+                             stage epilogue of fr_rk_step /
+                             fr_dual_step uses the halo form's kernel when that is the
+                             residual's form, else the point form's.                       */
 } fr_option;
 
 /* Kernel identifiers for fr_plan_kernel_stats. */
@@ -111,7 +119,7 @@ typedef enum fr_kernel {
 
 enum { FR_F64 = 0, FR_F32 = 1 };
 enum { FR_FUSED = 0, FR_UNFUSED = 1, FR_MFMA = 2 };
-enum { FR_FORM_AUTO = 0, FR_FORM_POINT = 1, FR_FORM_LINES = 2 };
+enum { FR_FORM_AUTO = 0, FR_FORM_POINT = 1, FR_FORM_LINES = 2, FR_FORM_HALO = 3 };
 
 /*
  * fr_plan_create -- build the 1D operators (Sec. 2.1: Gauss-Legendre solution
@@ -136,10 +144,21 @@ fr_plan *fr_plan_create(int p, int nx, int ny, int nz, const double jac[9], doub
  * that no longer applies.  FR_EINVAL for an unknown key or value. */
 int fr_plan_set_int(fr_plan *plan, int key, int value);
 int fr_plan_get_int(const fr_plan *plan, int key, int *value);
-/* Read-only key of fr_plan_get_int: the kernel form fr_residual runs with the
- * plan's current settings (FR_FORM_POINT or FR_FORM_LINES; 0 for FR_UNFUSED
- * and FR_MFMA). */
-enum { FR_INFO_RESIDUAL_FORM = 100 };
+/* Read-only keys of fr_plan_get_int, for the plan's current settings:
+ *   FR_INFO_RESIDUAL_FORM  the kernel form fr_residual runs (FR_FORM_POINT,
+ *                          FR_FORM_LINES or FR_FORM_HALO; 0 for FR_UNFUSED and
+ *                          FR_MFMA)
+ *   FR_INFO_STAGE_PATH     how fr_rk_step and fr_dual_step (RK4 pseudo-steps)
+ *                          apply each stage update: FR_STAGE_SEPARATE (residual
+ *                          kernels, then the separate stage kernel),
+ *                          FR_STAGE_POINT (the point form's kernel with the
+ *                          epilogue), FR_STAGE_HALO (the halo form's kernel with
+ *                          the epilogue).  Explicit FR_OPT_FORM = FR_FORM_POINT or
+ *                          FR_FORM_HALO selects that form's epilogue;
+ *                          FR_FORM_AUTO takes the fastest measured per order and
+ *                          precision; FR_OPT_FUSE_STAGE = 0 the separate kernel. */
+enum { FR_INFO_RESIDUAL_FORM = 100, FR_INFO_STAGE_PATH = 101 };
+enum { FR_STAGE_SEPARATE = 0, FR_STAGE_POINT = 1, FR_STAGE_HALO = 2 };
 
 /* Release the plan and all device memory it owns (waits for the device). */
 void fr_plan_destroy(fr_plan *plan);
@@ -176,7 +195,8 @@ int fr_residual(fr_plan *plan, const void *U, void *R, fr_stream_t s);
  * ends) instead of the plan's scratch; it calls no allocating routine.
  * Limit: 6 * ne * ceil16(7 (p+1)^2) values of the plan's precision must fit in
  * 64 MiB (at p = 3: 12,483 elements in FP64, 24,966 in FP32); larger plans get
- * FR_EINVAL before any work is enqueued, FR_UNFUSED gets FR_EUNSUPPORTED.  All
+ * FR_EINVAL before any work is enqueued, FR_UNFUSED gets FR_EUNSUPPORTED.  The
+ * halo form (FR_OPT_FORM) uses no trace array, so it has no limit.  All
  * calls on one device share the array, so calls that overlap in time on one
  * device (two streams, two threads) race; calls ordered on one stream do not.
  * Nothing in the array needs clearing: every call writes each trace it reads.

@@ -18,8 +18,9 @@ KERNELS = ("trace", "fused", "u_project", "u_flux", "u_div", "u_common", "u_corr
 FR_F64, FR_F32 = 0, 1
 FR_K_TRACE, FR_K_FUSED = 0, 1
 FR_FUSED, FR_UNFUSED, FR_MFMA = 0, 1, 2
-FR_FORM_AUTO, FR_FORM_POINT, FR_FORM_LINES = 0, 1, 2
-FR_INFO_RESIDUAL_FORM = 100
+FR_FORM_AUTO, FR_FORM_POINT, FR_FORM_LINES, FR_FORM_HALO = 0, 1, 2, 3
+FR_INFO_RESIDUAL_FORM, FR_INFO_STAGE_PATH = 100, 101
+FR_STAGE_SEPARATE, FR_STAGE_POINT, FR_STAGE_HALO = 0, 1, 2
 NV = 13
 
 EXPORTED = ("fr_plan_create", "fr_plan_set_int", "fr_plan_get_int", "fr_plan_destroy",

@@ -52,9 +52,11 @@ def fused_values(m):
     return 2 * NV + 6 * NTR / m
 
 
-def fused_residual_values(m):
-    """Both kernels of the fused residual."""
-    return trace_values(m) + fused_values(m)
+def fused_residual_values(m, halo=False):
+    """Both kernels of the fused residual; with halo, the one kernel that
+    recomputes the neighbours' face traces from their states (read through the
+    caches: by design only U and R cross HBM)."""
+    return floor_values() if halo else trace_values(m) + fused_values(m)
 
 
 def unfused_values(m):

@@ -52,7 +52,7 @@ int rk_buffers(fr_plan *pl, RkBufs &b)
 
 bool stage_in_epilogue(const fr_plan *pl)
 {
-    return pl->variant == FR_FUSED && pl->fuse_stage && fused_stage_available(pl);
+    return stage_path(pl) != FR_STAGE_SEPARATE;
 }
 
 // every plan setting that changes the launches of a step
@@ -181,12 +181,14 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
     // face traces ping-pong between two arrays: each stage's epilogue writes
     // those of the state it produces, so only the call's first stage runs the
     // trace kernel (stage 0 reads A and writes B, stages 1, 2, 3 alternate)
+    // (the halo form needs none)
     void *trA = nullptr, *trB = nullptr;
-    if (epi)
+    const bool epi_traces = epi && stage_path(pl) == FR_STAGE_POINT;
+    if (epi_traces)
         if (int r = stage_trace_buffers(pl, trA, trB)) return r;
     auto with_traces = [&](StageSpec sp, const void *in, void *out) {
-        sp.tr_in = in;
-        sp.tr_out = out;
+        sp.tr_in = epi_traces ? in : nullptr;
+        sp.tr_out = epi_traces ? out : nullptr;
         sp.nx = pl->nx;
         sp.ny = pl->ny;
         sp.nz = pl->nz;
@@ -357,8 +359,10 @@ int fr_rk_step(fr_plan *pl, double *U, double dt, int nsteps, fr_stream_t sv)
     const int o = f64 ? 0 : 1;
     // face traces ping-pong between two arrays (stage 0 reads A, writes B;
     // stages 1, 2, 3 alternate): only the call's first stage runs the trace kernel
+    // (the halo form needs none)
     void *trA = nullptr, *trB = nullptr;
-    if (epi)
+    const bool epi_traces = epi && stage_path(pl) == FR_STAGE_POINT;
+    if (epi_traces)
         if (int r = stage_trace_buffers(pl, trA, trB)) return r;
     bool chained = false;
     auto step = [&](hipStream_t st) -> int {
@@ -369,8 +373,10 @@ int fr_rk_step(fr_plan *pl, double *U, double dt, int nsteps, fr_stream_t sv)
                 void *out = last ? (f64 ? nullptr : bufs[0]) : bufs[(k + o) % 2];
                 StageSpec sp{U, b.acc, nullptr, nullptr, out, nullptr, nullptr,
                              0.0, w[k], last ? 0.0 : c[k + 1], k == 0, last};
-                sp.tr_in = k == 0 ? (chained ? trA : nullptr) : (k % 2 ? trB : trA);
-                sp.tr_out = k % 2 ? trA : trB;
+                if (epi_traces) {
+                    sp.tr_in = k == 0 ? (chained ? trA : nullptr) : (k % 2 ? trB : trA);
+                    sp.tr_out = k % 2 ? trA : trB;
+                }
                 sp.nx = pl->nx;
                 sp.ny = pl->ny;
                 sp.nz = pl->nz;

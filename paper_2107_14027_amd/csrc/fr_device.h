@@ -160,9 +160,13 @@ struct LinesLds {
     static constexpr bool VEC = (raw * sizeof(T)) % 16 == 0 && (EP * sizeof(T)) % 16 == 0;
     // the operator block, padded to 16 bytes
     static constexpr int OPS = (OpsLayout<M>::size * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
-    // LDS values of a batch of E elements: operators, state tile, three
-    // directions' P and momentum parts
-    static constexpr int values(int E, bool xr) { return OPS + E * EP + (xr ? 8 : 12) * E * NS; }
+    // LDS values of a batch of E elements: operators, state tile, and the
+    // directions' P and momentum parts that wait in LDS (three directions for
+    // xr = 0, two for xr = 1, none for xr = 2)
+    static constexpr int values(int E, int xr)
+    {
+        return OPS + E * EP + (xr == 2 ? 0 : (xr == 1 ? 8 : 12)) * E * NS;
+    }
 };
 
 // A batch's contiguous state block (nel elements from src) into the line
@@ -189,6 +193,33 @@ __device__ __forceinline__ void tile_load(const T *__restrict__ src, T *__restri
         for (int k = threadIdx.x; k < nv; k += NT) {
             const int ek = k / RAW, o = k - ek * RAW;
             sU[ek * EP + o] = __builtin_nontemporal_load(src + k);
+        }
+    }
+}
+
+// The reverse of tile_load: nel finished elements of the tile (pitch EP) to
+// their contiguous block at dst.
+template <int P, typename T, int NT>
+__device__ __forceinline__ void tile_store(const T *__restrict__ sU, T *__restrict__ dst, int nel)
+{
+    using LL = LinesLds<P, T>;
+    constexpr int EP = LL::EP, RAW = LL::raw;
+    if constexpr (LL::VEC) {
+        using V = typename V16<T>::type;
+        constexpr int VW = 16 / sizeof(T), CPE = RAW / VW;
+        const int nch = nel * CPE;
+        V *dv = reinterpret_cast<V *>(dst);
+#pragma unroll 4
+        for (int k = threadIdx.x; k < nch; k += NT) {
+            const int ek = k / CPE, o = k - ek * CPE;
+            __builtin_nontemporal_store(reinterpret_cast<const V *>(sU + ek * EP)[o], dv + k);
+        }
+    } else {
+        const int nv = nel * RAW;
+#pragma unroll 4
+        for (int k = threadIdx.x; k < nv; k += NT) {
+            const int ek = k / RAW, o = k - ek * RAW;
+            __builtin_nontemporal_store(sU[ek * EP + o], dst + k);
         }
     }
 }

@@ -97,7 +97,7 @@ struct fr_plan {
     int precision;  // FR_F64 / FR_F32
     int variant;    // FR_FUSED / FR_UNFUSED
     int block;      // elements per workgroup override (0 = default)
-    int form = 0;   // FR_FORM_AUTO / FR_FORM_POINT / FR_FORM_LINES (fused plain residual)
+    int form = 0;   // FR_OPT_FORM: FR_FORM_AUTO / _POINT / _LINES / _HALO (fused path)
     int guess_base = 2;  // extrapolation order the learned guess corrects
     // captured time-integration graphs ([0] pseudo-step with norm read-back,
     // [1] pseudo-step without, [2] RK4 step) and their capture stream
@@ -181,7 +181,9 @@ int launch_residual(fr_plan *pl, const void *U, void *R, hipStream_t s);
 // *nparts receives the number of partial sums written when sp.partial is set
 int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *nparts,
                           hipStream_t s);
-bool fused_stage_available(const fr_plan *pl);
+// How fr_rk_step / fr_dual_step apply the RK stage update for this plan's
+// current settings (FR_STAGE_SEPARATE, FR_STAGE_POINT or FR_STAGE_HALO).
+int stage_path(const fr_plan *pl);
 // kernel form fr_residual runs on this plan (FR_FORM_POINT or FR_FORM_LINES;
 // 0 for the unfused and matrix-core variants)
 int residual_form(const fr_plan *pl);

@@ -513,6 +513,68 @@ constexpr int stage_chunk()
 #endif
 }
 
+// The RK stage update of one batch whose residual (working precision) is in
+// LDS: tile(t) is the t-th of the batch's cnt values in global order
+// ([element][variable][point], from element e0).  The double arithmetic of the
+// stand-alone stage kernel (the residual went through LDS, so nothing is
+// contracted into its last operation).  A thread (tid of nt) has at most J
+// values, taken in chunks of C: the global operands of a chunk are requested
+// before the first is used, so that the loads of a wave overlap, with a
+// bounded register cost.  With tr_out the produced state replaces the
+// residual in the tile; ss accumulates the squared velocity pseudo-residual.
+template <int J, int C, int NS, typename T, typename Tile>
+__device__ __forceinline__ void stage_update_batch(const StageSpec &sp, Tile &&tile, unsigned tid,
+                                                   unsigned nt, unsigned cnt, int64_t e0, double &ss)
+{
+    const int64_t g0 = e0 * NV * NS;
+#pragma unroll 1
+    for (int j0 = 0; j0 < J; j0 += C) {
+        double ou[C], oa[C], os[C], ob[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const unsigned t = tid + (j0 + j) * nt;
+            if (t < cnt) {
+                const int64_t gi = g0 + t;
+                if (!sp.last) ou[j] = sp.U[gi];
+                if (!sp.first || sp.last) oa[j] = sp.acc[gi];
+                if (sp.B) {
+                    const unsigned r = t / NS, q = t - r * NS;
+                    const unsigned el = r / NV, v = r - el * NV;
+                    if (v >= 1 && v <= 3) {
+                        os[j] = sp.s_in ? sp.s_in[gi] : sp.U[gi];
+                        ob[j] = sp.B[((int64_t)(e0 + el) * 3 + (v - 1)) * NS + q];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const unsigned t = tid + (j0 + j) * nt;
+            if (t < cnt) {
+                const int64_t gi = g0 + t;
+                const unsigned v = (t / NS) % NV;
+                double kv = (double)tile(t);
+                if (v >= 1 && v <= 3) {
+                    if (sp.B) kv -= fma(sp.a, os[j], ob[j]);
+                    if (sp.partial) ss = fma(kv, kv, ss);
+                }
+                if (sp.last) {
+                    const double un = fma(sp.b, kv, oa[j]);
+                    sp.U[gi] = un;
+                    if (sp.s_out) static_cast<T *>(sp.s_out)[gi] = (T)un;
+                    if (sp.tr_out) tile(t) = (T)un;
+                } else {
+                    sp.acc[gi] = fma(sp.b, kv, sp.first ? ou[j] : oa[j]);
+                    const double sn = fma(sp.cnext, kv, ou[j]);
+                    if (sp.s_out64) sp.s_out64[gi] = sn;
+                    static_cast<T *>(sp.s_out)[gi] = (T)sn;
+                    if (sp.tr_out) tile(t) = (T)sn;
+                }
+            }
+        }
+    }
+}
+
 // The stage epilogue needs the residual of a whole batch in the state tile:
 // the line-task path leaves it there; the point-wise path holds it in
 // registers, which is only done where a thread has a single point.
@@ -990,54 +1052,8 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
             constexpr int J = (EMAX * NV * NS + NT - 1) / NT;
             constexpr int C = stage_chunk<P, T>() < J ? stage_chunk<P, T>() : J;
             __syncthreads();
-            const unsigned cnt = (unsigned)nel * NV * NS;
-            const int64_t g0 = (int64_t)e0 * NV * NS;
-#pragma unroll 1
-            for (int j0 = 0; j0 < J; j0 += C) {
-                double ou[C], oa[C], os[C], ob[C];
-#pragma unroll
-                for (int j = 0; j < C; ++j) {
-                    const unsigned t = tid + (j0 + j) * NT;
-                    if (t < cnt) {
-                        const int64_t gi = g0 + t;
-                        if (!sp.last) ou[j] = sp.U[gi];
-                        if (!sp.first || sp.last) oa[j] = sp.acc[gi];
-                        if (sp.B) {
-                            const unsigned r = t / NS, q = t - r * NS;
-                            const unsigned el = r / NV, v = r - el * NV;
-                            if (v >= 1 && v <= 3) {
-                                os[j] = sp.s_in ? sp.s_in[gi] : sp.U[gi];
-                                ob[j] = sp.B[((int64_t)(e0 + el) * 3 + (v - 1)) * NS + q];
-                            }
-                        }
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < C; ++j) {
-                    const unsigned t = tid + (j0 + j) * NT;
-                    if (t < cnt) {
-                        const int64_t gi = g0 + t;
-                        const unsigned v = (t / NS) % NV;
-                        double kv = (double)sU[t];
-                        if (v >= 1 && v <= 3) {
-                            if (sp.B) kv -= fma(sp.a, os[j], ob[j]);
-                            if (sp.partial) ss = fma(kv, kv, ss);
-                        }
-                        if (sp.last) {
-                            const double un = fma(sp.b, kv, oa[j]);
-                            sp.U[gi] = un;
-                            if (sp.s_out) static_cast<T *>(sp.s_out)[gi] = (T)un;
-                            if (sp.tr_out) sU[t] = (T)un;
-                        } else {
-                            sp.acc[gi] = fma(sp.b, kv, sp.first ? ou[j] : oa[j]);
-                            const double sn = fma(sp.cnext, kv, ou[j]);
-                            if (sp.s_out64) sp.s_out64[gi] = sn;
-                            static_cast<T *>(sp.s_out)[gi] = (T)sn;
-                            if (sp.tr_out) sU[t] = (T)sn;
-                        }
-                    }
-                }
-            }
+            stage_update_batch<J, C, NS, T>(sp, [&](unsigned t) -> T & { return sU[t]; }, tid, NT,
+                                           (unsigned)nel * NV * NS, e0, ss);
             if (sp.tr_out) {
                 // ---- stage 1 of the next residual: the produced state's face
                 //      traces (k_trace's values and layout) from the tile, written
@@ -1126,9 +1142,18 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 // the transformed flux at the m points and the six partially corrected
 // derivatives (three velocities, three momentum fluxes; Table 1 stages 3 and 5
 // with the operator Dt and the correction derivatives g_L', g_R').  The
-// auxiliary residuals (a, d) are complete at that point and are written out;
-// the P and momentum parts of directions y and z go through LDS to the x lane
-// of the same points, which sums the three directions and writes the rest of R.
+// auxiliary residuals (a, d) are complete at that point and replace S_ad in the
+// tile.  The P and momentum parts of the three directions are summed in the
+// order x, y, z; where they wait for the sum is a per-shape choice (XR):
+//   0  each direction's parts in LDS slots of their own ([3][E][4][m^3]); the
+//      final pass sums them while it writes R
+//   1  the x direction's in its lanes' registers, y and z in LDS; the x lanes
+//      sum and write P and momentum, the auxiliary residuals are copied
+//   2  all in registers; after a barrier (the state's P and velocity values are
+//      dead by then) the x lanes store theirs over those values, the y lanes
+//      add theirs, the z lanes add and scale, and the finished tile is R
+// Mode 2 needs no LDS beyond the tile (more workgroups per CU), at the cost of
+// registers and two more barriers.  All three give the same bits.
 // ---------------------------------------------------------------------------
 #ifndef FR_LE1_D
 #define FR_LE1_D 16
@@ -1204,7 +1229,7 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #endif
 
 #ifndef FR_LX1_D
-#define FR_LX1_D 0
+#define FR_LX1_D 2
 #endif
 #ifndef FR_LX2_D
 #define FR_LX2_D 0
@@ -1225,7 +1250,7 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #define FR_LX1_F 0
 #endif
 #ifndef FR_LX2_F
-#define FR_LX2_F 0
+#define FR_LX2_F 2
 #endif
 #ifndef FR_LX3_F
 #define FR_LX3_F 0
@@ -1237,55 +1262,157 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #define FR_LX5_F 1
 #endif
 #ifndef FR_LX6_F
-#define FR_LX6_F 1
+#define FR_LX6_F 2
 #endif
-// FR_FORM_AUTO's choice per order and precision (1: line form), from the
-// measured fused-kernel times of both forms on the order-sweep lattices
-// (periodic box, about 16.6-22.0 M points): the line form is faster at
-// p = 2, 3, 4 in double and p = 2, 3, 5, 6 in single precision.
+// FR_FORM_AUTO's choice per order and precision (0: point form with the trace
+// kernel, 1: line form with the trace kernel, 2: halo form, no trace kernel),
+// from the measured whole-residual times on the order-sweep lattices (periodic
+// box, about 16.6-22.0 M points): the halo form is the fastest everywhere
+// (at p = 5 in single precision the line form is within 3%).
 #ifndef FR_LA1_D
-#define FR_LA1_D 0
+#define FR_LA1_D 2
 #endif
 #ifndef FR_LA2_D
-#define FR_LA2_D 1
+#define FR_LA2_D 2
 #endif
 #ifndef FR_LA3_D
-#define FR_LA3_D 1
+#define FR_LA3_D 2
 #endif
 #ifndef FR_LA4_D
-#define FR_LA4_D 1
+#define FR_LA4_D 2
 #endif
 #ifndef FR_LA5_D
-#define FR_LA5_D 0
+#define FR_LA5_D 2
 #endif
 #ifndef FR_LA6_D
-#define FR_LA6_D 0
+#define FR_LA6_D 2
 #endif
 #ifndef FR_LA1_F
-#define FR_LA1_F 0
+#define FR_LA1_F 2
 #endif
 #ifndef FR_LA2_F
-#define FR_LA2_F 1
+#define FR_LA2_F 2
 #endif
 #ifndef FR_LA3_F
-#define FR_LA3_F 1
+#define FR_LA3_F 2
 #endif
 #ifndef FR_LA4_F
-#define FR_LA4_F 0
+#define FR_LA4_F 2
 #endif
 #ifndef FR_LA5_F
-#define FR_LA5_F 1
+#define FR_LA5_F 2
 #endif
 #ifndef FR_LA6_F
-#define FR_LA6_F 1
+#define FR_LA6_F 2
 #endif
+// Waves per SIMD the register allocation of k_lines aims for (at least).
+#ifndef FR_LV_DEFAULT
+#define FR_LV_DEFAULT 1
+#endif
+#ifndef FR_LV1_D
+#define FR_LV1_D FR_LV_DEFAULT
+#endif
+#ifndef FR_LV2_D
+#define FR_LV2_D FR_LV_DEFAULT
+#endif
+#ifndef FR_LV3_D
+#define FR_LV3_D FR_LV_DEFAULT
+#endif
+#ifndef FR_LV4_D
+#define FR_LV4_D FR_LV_DEFAULT
+#endif
+#ifndef FR_LV5_D
+#define FR_LV5_D FR_LV_DEFAULT
+#endif
+#ifndef FR_LV6_D
+#define FR_LV6_D FR_LV_DEFAULT
+#endif
+#ifndef FR_LV1_F
+#define FR_LV1_F FR_LV_DEFAULT
+#endif
+#ifndef FR_LV2_F
+#define FR_LV2_F FR_LV_DEFAULT
+#endif
+#ifndef FR_LV3_F
+#define FR_LV3_F FR_LV_DEFAULT
+#endif
+#ifndef FR_LV4_F
+#define FR_LV4_F FR_LV_DEFAULT
+#endif
+#ifndef FR_LV5_F
+#define FR_LV5_F FR_LV_DEFAULT
+#endif
+#ifndef FR_LV6_F
+#define FR_LV6_F FR_LV_DEFAULT
+#endif
+// How fr_rk_step and fr_dual_step apply the RK stage update when the plan's
+// residual is the halo form by the automatic choice, per order and precision
+// (FR_STAGE_SEPARATE: the halo-form residual, then the separate stage kernel;
+// FR_STAGE_POINT: the point form's kernel with the epilogue; FR_STAGE_HALO: the
+// halo form's kernel with the epilogue), from the measured RK4 step and dual
+// pseudo-step times on Taylor-Green lattices of 1.8-33.6 M points (the dual
+// pseudo-step decides).
+#ifndef FR_SA1_D
+#define FR_SA1_D FR_STAGE_HALO
+#endif
+#ifndef FR_SA2_D
+#define FR_SA2_D FR_STAGE_HALO
+#endif
+#ifndef FR_SA3_D
+#define FR_SA3_D FR_STAGE_POINT
+#endif
+#ifndef FR_SA4_D
+#define FR_SA4_D FR_STAGE_POINT
+#endif
+#ifndef FR_SA5_D
+#define FR_SA5_D FR_STAGE_POINT
+#endif
+#ifndef FR_SA6_D
+#define FR_SA6_D FR_STAGE_HALO
+#endif
+#ifndef FR_SA1_F
+#define FR_SA1_F FR_STAGE_HALO
+#endif
+#ifndef FR_SA2_F
+#define FR_SA2_F FR_STAGE_HALO
+#endif
+#ifndef FR_SA3_F
+#define FR_SA3_F FR_STAGE_HALO
+#endif
+#ifndef FR_SA4_F
+#define FR_SA4_F FR_STAGE_POINT
+#endif
+#ifndef FR_SA5_F
+#define FR_SA5_F FR_STAGE_POINT
+#endif
+#ifndef FR_SA6_F
+#define FR_SA6_F FR_STAGE_SEPARATE
+#endif
+template <int P, typename T> struct StageAuto;
+#define FR_SAUTO(PP, TT, S) \
+    template <> struct StageAuto<PP, TT> { static constexpr int value = FR_SA##PP##_##S; };
+FR_SAUTO(1, double, D)
+FR_SAUTO(2, double, D)
+FR_SAUTO(3, double, D)
+FR_SAUTO(4, double, D)
+FR_SAUTO(5, double, D)
+FR_SAUTO(6, double, D)
+FR_SAUTO(1, float, F)
+FR_SAUTO(2, float, F)
+FR_SAUTO(3, float, F)
+FR_SAUTO(4, float, F)
+FR_SAUTO(5, float, F)
+FR_SAUTO(6, float, F)
+#undef FR_SAUTO
+
 template <int P, typename T> struct LinesShape;
 #define FR_LSHAPE(PP, TT, S)                                                        \
     template <> struct LinesShape<PP, TT> {                                         \
         static constexpr int E = FR_LE##PP##_##S, W = FR_LW##PP##_##S, NT = 192 * W; \
         static_assert(E * (PP + 1) * (PP + 1) <= 64 * W, "one lane per line");       \
-        static constexpr bool XR = FR_LX##PP##_##S;                                  \
-        static constexpr bool AUTO = FR_LA##PP##_##S;                                \
+        static constexpr int XR = FR_LX##PP##_##S;                                   \
+        static constexpr int AUTO = FR_LA##PP##_##S;                                 \
+        static constexpr int WPE = FR_LV##PP##_##S;                                  \
         static_assert(LinesLds<PP, TT>::values(E, XR) * sizeof(TT) <= 160 * 1024, "LDS"); \
     };
 FR_LSHAPE(1, double, D)
@@ -1361,6 +1488,26 @@ __device__ __forceinline__ void line_store(T *__restrict__ p, const T (&x)[M])
 
 
 
+// The m values of one line into LDS (the layout of line_load).
+template <int M, int STR, typename T>
+__device__ __forceinline__ void line_put(T *__restrict__ p, const T (&x)[M])
+{
+    if constexpr (STR == 1 && (M * sizeof(T)) % 16 == 0) {
+        using V = typename V16<T>::type;
+        constexpr int W = 16 / sizeof(T);
+#pragma unroll
+        for (int k = 0; k < M / W; ++k) {
+            V v;
+#pragma unroll
+            for (int w = 0; w < W; ++w) v[w] = x[k * W + w];
+            reinterpret_cast<V *>(p)[k] = v;
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < M; ++l) p[l * STR] = x[l];
+    }
+}
+
 // Whether the line task's row loop stays rolled (per order and precision;
 // fewer live registers against loop overhead).
 #ifndef FR_LROLL
@@ -1424,13 +1571,13 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
     const T ndd = c.nvec[D][D];
-    // the velocities along the line and the transformed momentum fluxes
-    // F_D,i = n_DD (u_i u_D + P delta_iD - nu S_iD) (P and S read once more)
-    T X[3][M], F[3][M];
-#pragma unroll
-    for (int ia = 0; ia < 3; ++ia) line_load<M, STR>(Ue + (1 + ia) * NS, X[ia]);
+    // the transformed momentum fluxes F_D,i = n_DD (u_i u_D + P delta_iD -
+    // nu S_iD) along the line (S is still the state's here)
+    T F[3][M];
     {
-        T Pl[M];
+        T X[3][M], Pl[M];
+#pragma unroll
+        for (int ia = 0; ia < 3; ++ia) line_load<M, STR>(Ue + (1 + ia) * NS, X[ia]);
         line_load<M, STR>(Ue, Pl);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -1446,10 +1593,29 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
         }
     }
     __builtin_amdgcn_sched_barrier(0);
-    // row by row: the corrected derivatives of the three velocities (auxiliary
-    // residuals (a, D), P part) and of the three fluxes
-    auto row = [&](int r) {
+    // two passes over the rows, so that the fluxes and the velocities are not
+    // live at once: first the corrected derivatives of the three fluxes, then
+    // those of the three velocities (auxiliary residuals (a, D), P part)
+    auto rowF = [&](int r) {
         // one row's operator values at a time (bounds the live registers)
+        __builtin_amdgcn_sched_barrier(0);
+        T Dr[M];
+#pragma unroll
+        for (int l = 0; l < M; ++l) Dr[l] = sop[OL::Dt + r * M + l];
+        const T glr = sop[OL::gl + r], grr = sop[OL::gr + r];
+        const int q = r * STR;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            T s = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) s = fma(Dr[l], F[i][l], s);
+            const T cf = fma(glr, FIm[1 + i], fma(grr, FIp[1 + i], s));
+            if constexpr (XR) ctb[1 + i][r] = cf;
+            else sCd[(1 + i) * NS + base + q] = cf;
+        }
+    };
+    T X[3][M];
+    auto rowV = [&](int r) {
         __builtin_amdgcn_sched_barrier(0);
         T Dr[M];
 #pragma unroll
@@ -1464,43 +1630,87 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
             for (int l = 0; l < M; ++l) s = fma(Dr[l], X[va][l], s);
             const T cd = fma(glr, FIm[4 + va], fma(grr, FIp[4 + va], s));
             const T gv = cd * ndd;
-            // S_aD at this point is read back from the tile (the line's copy in
-            // registers is dead by now) and replaced by the auxiliary residual
+            // S_aD at this point is replaced by the auxiliary residual (only
+            // this lane reads or writes it from here on)
             T *sq = Ue + (4 + 3 * va + D) * NS + q;
             *sq = c.invT * fma(c.inv_det, gv, -*sq);
             if (va == D) pc = fma(c.zeta, gv, fma(glr, FIm[0], grr * FIp[0]));
         }
         if constexpr (XR) ctb[0][r] = pc;
         else sCd[base + q] = pc;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            T s = T(0);
-#pragma unroll
-            for (int l = 0; l < M; ++l) s = fma(Dr[l], F[i][l], s);
-            const T cf = fma(glr, FIm[1 + i], fma(grr, FIp[1 + i], s));
-            if constexpr (XR) ctb[1 + i][r] = cf;
-            else sCd[(1 + i) * NS + base + q] = cf;
-        }
     };
-    // with XR the row index selects registers, so the loop is unrolled;
-    // otherwise it stays rolled (fewer live registers)
+    // with XR the row index selects registers, so the loops are unrolled;
+    // otherwise they stay rolled (fewer live registers)
     if constexpr (XR || !LinesRolled<P, T>::value) {
 #pragma unroll
-        for (int r = 0; r < M; ++r) row(r);
+        for (int r = 0; r < M; ++r) rowF(r);
+        __asm__ volatile("" ::: "memory");  // read the velocities again
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ia = 0; ia < 3; ++ia) line_load<M, STR>(Ue + (1 + ia) * NS, X[ia]);
+#pragma unroll
+        for (int r = 0; r < M; ++r) rowV(r);
     } else {
 #pragma unroll 1
-        for (int r = 0; r < M; ++r) row(r);
+        for (int r = 0; r < M; ++r) rowF(r);
+        __asm__ volatile("" ::: "memory");  // read the velocities again
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ia = 0; ia < 3; ++ia) line_load<M, STR>(Ue + (1 + ia) * NS, X[ia]);
+#pragma unroll 1
+        for (int r = 0; r < M; ++r) rowV(r);
     }
 }
 
-template <int P, typename T>
-__global__ void __launch_bounds__((LinesShape<P, T>::NT))
-    k_lines(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
-            const T *__restrict__ ops, Consts<T> c, int ne)
+// The face trace of a neighbour element, from its state Un (global memory or
+// the tile): its end lf (l(+1) for the minus neighbour, l(-1) for the plus
+// neighbour) of the direction-D line through face point L, for the seven trace
+// variables, with k_trace's fma chain (so the values have the bits k_trace
+// would write).
+template <int P, typename T, int D>
+__device__ __forceinline__ void nbr_trace(const T *__restrict__ Un, int L, const T *__restrict__ lf,
+                                          T (&out)[NTR])
 {
+    constexpr int M = P + 1, NS = M * M * M;
+    constexpr int STR = D == 0 ? 1 : (D == 1 ? M : M * M);
+    const int a = L % M, b = L / M;
+    const T *X = Un + (D == 0 ? M * L : (D == 1 ? a + M * M * b : L));
+#pragma unroll
+    for (int cc = 0; cc < NTR; ++cc) {
+        const T *Xc = X + (cc < 4 ? cc : 4 + 3 * (cc - 4) + D) * NS;
+        T acc = T(0);
+#pragma unroll
+        for (int l = 0; l < M; ++l) acc = fma(lf[l], Xc[l * STR], acc);
+        out[cc] = acc;
+    }
+}
+
+// Values per thread whose global operands the halo form's stage epilogue
+// requests at once, per order and precision (as stage_chunk for the point
+// form; measured: 16 spills, 1 leaves too few loads in flight).
+// FR_LSTG_CHUNK overrides the table.
+template <int P, typename T>
+constexpr int line_stage_chunk()
+{
+#ifdef FR_LSTG_CHUNK
+    return FR_LSTG_CHUNK;
+#else
+    constexpr int d[PMAX + 1] = {0, 8, 8, 8, 8, 8, 8};
+    constexpr int f[PMAX + 1] = {0, 8, 8, 4, 8, 8, 8};
+    return sizeof(T) == 8 ? d[P] : f[P];
+#endif
+}
+
+template <int P, typename T, bool HALO, bool STG>
+__global__ void __launch_bounds__((LinesShape<P, T>::NT))
+    __attribute__((amdgpu_waves_per_eu(LinesShape<P, T>::WPE, 8)))
+    k_lines(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
+            const T *__restrict__ ops, Consts<T> c, int nx, int ny, int nz, StageSpec sp)
+{
+    const int ne = nx * ny * nz;
     constexpr int M = P + 1, NS = M * M * M, NF = M * M;
     constexpr int E = LinesShape<P, T>::E, W = LinesShape<P, T>::W, NT = LinesShape<P, T>::NT;
-    constexpr bool XR = LinesShape<P, T>::XR;
+    constexpr int XR = LinesShape<P, T>::XR;
     using LL = LinesLds<P, T>;
     using TL = TraceLayout<M, T>;
     using OL = OpsLayout<M>;
@@ -1508,42 +1718,123 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sop = reinterpret_cast<T *>(smem_raw);  // operators
     T *sU = sop + LL::OPS;                     // [E][EP] state tile
-    // P and momentum parts per direction, [3][E][4][NS] (with XR the x
-    // direction's stay in its lanes' registers and only y and z are here)
-    T *sC = sU + E * EP - (XR ? 4 * E * NS : 0);
-    const int64_t e0 = (int64_t)blockIdx.x * E;
-    const int nel = (int)min((int64_t)E, (int64_t)ne - e0);
+    // P and momentum parts per direction, [3][E][4][NS] (XR = 1: the x
+    // direction's stay in its lanes' registers and only y and z are here;
+    // XR = 2: none here)
+    T *sC = sU + E * EP - (XR == 1 ? 4 * E * NS : 0);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int d = wave / W;
     const int t = (wave - d * W) * 64 + (threadIdx.x & 63);
     const int el = t / NF, L = t - el * NF;
+    const int64_t nb = ((int64_t)ne + E - 1) / E;
+    if (threadIdx.x < OL::size) sop[threadIdx.x] = ops[threadIdx.x];
+    // with STG: sum of (k*_V)^2 over this workgroup's stage updates
+    double ss = 0.0;
+    auto run_batch = [&](int64_t bt) {
+    const int64_t e0 = bt * E;
+    const int nel = (int)min((int64_t)E, (int64_t)ne - e0);
     const bool act = el < nel;
     const int64_t e = e0 + el;
-    // the neighbours' traces on this lane's line, requested before the state
+    // the neighbours' traces on this lane's line, requested before the state:
+    // from the trace array, or with HALO from the neighbours' own states (from
+    // global memory for a neighbour outside the batch, from the tile after it
+    // is loaded otherwise)
     T othm[NTR], othp[NTR];
+    int64_t nbm = 0, nbp = 0;
+    bool inm = false, inp = false;
     if (act) {
-        const T *tm = TR + ((int64_t)(2 * d) * ne + e) * TL::CHP + L;
-        const T *tp = TR + ((int64_t)(2 * d + 1) * ne + e) * TL::CHP + L;
+        if constexpr (HALO) {
+            nbm = neighbour(e, 2 * d, nx, ny, nz);
+            nbp = neighbour(e, 2 * d + 1, nx, ny, nz);
+            inm = nbm >= e0 && nbm < e0 + nel;
+            inp = nbp >= e0 && nbp < e0 + nel;
+            auto from_global = [&](auto dc) {
+                constexpr int DD = decltype(dc)::value;
+                if (!inm) nbr_trace<P, T, DD>(U + nbm * RAW, L, ops + OL::lp, othm);
+                if (!inp) nbr_trace<P, T, DD>(U + nbp * RAW, L, ops + OL::lm, othp);
+            };
+            if (d == 0) from_global(Dir<0>{});
+            else if (d == 1) from_global(Dir<1>{});
+            else from_global(Dir<2>{});
+        } else {
+            const T *tm = TR + ((int64_t)(2 * d) * ne + e) * TL::CHP + L;
+            const T *tp = TR + ((int64_t)(2 * d + 1) * ne + e) * TL::CHP + L;
 #pragma unroll
-        for (int cc = 0; cc < NTR; ++cc) {
-            othm[cc] = __builtin_nontemporal_load(tm + cc * NF);
-            othp[cc] = __builtin_nontemporal_load(tp + cc * NF);
+            for (int cc = 0; cc < NTR; ++cc) {
+                othm[cc] = __builtin_nontemporal_load(tm + cc * NF);
+                othp[cc] = __builtin_nontemporal_load(tp + cc * NF);
+            }
         }
     }
-    if (threadIdx.x < OL::size) sop[threadIdx.x] = ops[threadIdx.x];
     // the batch's state block into LDS
     tile_load<P, T, NT>(U + e0 * RAW, sU, nel);
     __syncthreads();
+    if constexpr (HALO) {
+        if (act && (inm || inp)) {
+            auto from_tile = [&](auto dc) {
+                constexpr int DD = decltype(dc)::value;
+                if (inm) nbr_trace<P, T, DD>(sU + (nbm - e0) * EP, L, sop + OL::lp, othm);
+                if (inp) nbr_trace<P, T, DD>(sU + (nbp - e0) * EP, L, sop + OL::lm, othp);
+            };
+            if (d == 0) from_tile(Dir<0>{});
+            else if (d == 1) from_tile(Dir<1>{});
+            else from_tile(Dir<2>{});
+        }
+        // a neighbour's S_ad is replaced by its auxiliary residual in the line
+        // task; with several waves per direction that lane may be in another
+        // wave, so every wave finishes these reads first
+        if constexpr (W > 1) __syncthreads();
+    }
     T ctb[4][M];
     if (act) {
         T *Ut = sU + el * EP;
         T *sCd = sC + ((d * E + el) * 4) * NS;
-        if (d == 0) line_task<P, T, 0, XR>(Ut, sop, othm, othp, c, L, sCd, ctb);
-        else if (d == 1) line_task<P, T, 1, false>(Ut, sop, othm, othp, c, L, sCd, ctb);
-        else line_task<P, T, 2, false>(Ut, sop, othm, othp, c, L, sCd, ctb);
+        if (d == 0) line_task<P, T, 0, (XR >= 1)>(Ut, sop, othm, othp, c, L, sCd, ctb);
+        else if (d == 1) line_task<P, T, 1, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
+        else line_task<P, T, 2, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
     }
     __syncthreads();
-    if constexpr (XR) {
+    // R of the batch: P and momentum summed over the three directions in the
+    // order x, y, z and scaled by -1/det J, the auxiliary residuals from the
+    // tile.  Without STG it goes to R; with STG it stays in the tile for the
+    // stage update.
+    const T mid = -c.inv_det;
+    if constexpr (XR == 2) {
+        // summed over the tile's P and velocity values, one direction after
+        // the other
+        auto add_lines = [&](auto dc) {
+            constexpr int DD = decltype(dc)::value;
+            constexpr int STR = DD == 0 ? 1 : (DD == 1 ? M : M * M);
+            const int a = L % M, b = L / M;
+            T *Ue = sU + el * EP + (DD == 0 ? M * L : (DD == 1 ? a + M * M * b : L));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                T o[M];
+                if constexpr (DD == 0) {
+#pragma unroll
+                    for (int r = 0; r < M; ++r) o[r] = ctb[k][r];
+                } else {
+                    line_load<M, STR>(Ue + k * NS, o);
+#pragma unroll
+                    for (int r = 0; r < M; ++r) o[r] = o[r] + ctb[k][r];
+                    if constexpr (DD == 2) {
+#pragma unroll
+                        for (int r = 0; r < M; ++r) o[r] = mid * o[r];
+                    }
+                }
+                line_put<M, STR>(Ue + k * NS, o);
+            }
+        };
+        if (act && d == 0) add_lines(Dir<0>{});
+        __syncthreads();
+        if (act && d == 1) add_lines(Dir<1>{});
+        __syncthreads();
+        if (act && d == 2) add_lines(Dir<2>{});
+        if constexpr (!STG) {
+            __syncthreads();
+            tile_store<P, T, NT>(sU, R + e0 * RAW, nel);
+        }
+    } else if constexpr (XR == 1) {
         // x lanes: their own parts plus those of y and z at the x-line's points
         if (act && d == 0) {
             const T *cy = sC + ((E + el) * 4) * NS + M * L;
@@ -1553,72 +1844,110 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
             for (int k = 0; k < 4; ++k) {
                 T o[M];
 #pragma unroll
-                for (int r = 0; r < M; ++r)
-                    o[r] = -c.inv_det * ((ctb[k][r] + cy[k * NS + r]) + cz[k * NS + r]);
-                line_store<M, 1>(Re + k * NS, o);
+                for (int r = 0; r < M; ++r) o[r] = mid * ((ctb[k][r] + cy[k * NS + r]) + cz[k * NS + r]);
+                if constexpr (STG) line_put<M, 1>(sU + el * EP + M * L + k * NS, o);
+                else line_store<M, 1>(Re + k * NS, o);
             }
         }
-        // every thread: the auxiliary residuals from the tile
+        if constexpr (!STG) {
+            // every thread: the auxiliary residuals from the tile
+            T *dst = R + e0 * RAW;
+            constexpr int A0 = 4 * NS, NA = 9 * NS;
+            if constexpr (LL::VEC && (A0 * sizeof(T)) % 16 == 0) {
+                using V = typename V16<T>::type;
+                constexpr int VW = 16 / sizeof(T), CPE = NA / VW;
+                const int nch = nel * CPE;
+#pragma unroll 4
+                for (int k = threadIdx.x; k < nch; k += NT) {
+                    const int ek = k / CPE, o = k - ek * CPE;
+                    __builtin_nontemporal_store(reinterpret_cast<const V *>(sU + ek * EP + A0)[o],
+                                                reinterpret_cast<V *>(dst + ek * RAW + A0) + o);
+                }
+            } else {
+                const int nv = nel * NA;
+#pragma unroll 4
+                for (int k = threadIdx.x; k < nv; k += NT) {
+                    const int ek = k / NA, o = k - ek * NA;
+                    __builtin_nontemporal_store(sU[ek * EP + A0 + o], dst + ek * RAW + A0 + o);
+                }
+            }
+        }
+    } else {
+        // one pass over the batch: the three directions' parts from their
+        // slots, the auxiliary residuals from the tile
         T *dst = R + e0 * RAW;
-        constexpr int A0 = 4 * NS, NA = 9 * NS;
-        if constexpr (LL::VEC && (A0 * sizeof(T)) % 16 == 0) {
+        if constexpr (LL::VEC) {
             using V = typename V16<T>::type;
-            constexpr int VW = 16 / sizeof(T), CPE = NA / VW;
+            constexpr int VW = 16 / sizeof(T), CPE = RAW / VW, C4 = 4 * NS / VW;
+            static_assert((4 * NS) % VW == 0, "P and momentum in whole chunks");
             const int nch = nel * CPE;
 #pragma unroll 4
             for (int k = threadIdx.x; k < nch; k += NT) {
                 const int ek = k / CPE, o = k - ek * CPE;
-                __builtin_nontemporal_store(reinterpret_cast<const V *>(sU + ek * EP + A0)[o],
-                                            reinterpret_cast<V *>(dst + ek * RAW + A0) + o);
+                V x;
+                if (o < C4) {
+                    const V *cx = reinterpret_cast<const V *>(sC + (ek * 4) * NS) + o;
+                    const V *cy = reinterpret_cast<const V *>(sC + ((E + ek) * 4) * NS) + o;
+                    const V *cz = reinterpret_cast<const V *>(sC + ((2 * E + ek) * 4) * NS) + o;
+                    const V vx = *cx, vy = *cy, vz = *cz;
+#pragma unroll
+                    for (int w = 0; w < VW; ++w) x[w] = mid * ((vx[w] + vy[w]) + vz[w]);
+                    if constexpr (STG) reinterpret_cast<V *>(sU + ek * EP)[o] = x;
+                } else {
+                    x = reinterpret_cast<const V *>(sU + ek * EP)[o];
+                }
+                if constexpr (!STG) __builtin_nontemporal_store(x, reinterpret_cast<V *>(dst) + k);
             }
         } else {
-            const int nv = nel * NA;
+            const int nv = nel * RAW;
 #pragma unroll 4
             for (int k = threadIdx.x; k < nv; k += NT) {
-                const int ek = k / NA, o = k - ek * NA;
-                __builtin_nontemporal_store(sU[ek * EP + A0 + o], dst + ek * RAW + A0 + o);
+                const int ek = k / RAW, o = k - ek * RAW;
+                T x;
+                if (o < 4 * NS) {
+                    const T *cx = sC + (ek * 4) * NS + o;
+                    x = mid * ((cx[0] + cx[E * 4 * NS]) + cx[2 * E * 4 * NS]);
+                    if constexpr (STG) sU[ek * EP + o] = x;
+                } else {
+                    x = sU[ek * EP + o];
+                }
+                if constexpr (!STG) __builtin_nontemporal_store(x, dst + k);
             }
         }
-        return;
     }
-    // R of the batch, one contiguous block: P and momentum summed over the
-    // three directions in order, the auxiliary residuals from the tile
-    T *dst = R + e0 * RAW;
-    const T mid = -c.inv_det;
-    if constexpr (LL::VEC) {
-        using V = typename V16<T>::type;
-        constexpr int VW = 16 / sizeof(T), CPE = RAW / VW, C4 = 4 * NS / VW;
-        static_assert((4 * NS) % VW == 0, "P and momentum in whole chunks");
-        const int nch = nel * CPE;
-#pragma unroll 4
-        for (int k = threadIdx.x; k < nch; k += NT) {
-            const int ek = k / CPE, o = k - ek * CPE;
-            V x;
-            if (o < C4) {
-                const V *cx = reinterpret_cast<const V *>(sC + (ek * 4) * NS) + o;
-                const V *cy = reinterpret_cast<const V *>(sC + ((E + ek) * 4) * NS) + o;
-                const V *cz = reinterpret_cast<const V *>(sC + ((2 * E + ek) * 4) * NS) + o;
-                const V vx = *cx, vy = *cy, vz = *cz;
-#pragma unroll
-                for (int w = 0; w < VW; ++w) x[w] = mid * ((vx[w] + vy[w]) + vz[w]);
-            } else {
-                x = reinterpret_cast<const V *>(sU + ek * EP)[o];
-            }
-            __builtin_nontemporal_store(x, reinterpret_cast<V *>(dst) + k);
+    if constexpr (STG) {
+        // ---- the RK stage update of the batch from its residual in the tile
+        constexpr int J = (E * RAW + NT - 1) / NT;
+        constexpr int C = line_stage_chunk<P, T>() < J ? line_stage_chunk<P, T>() : J;
+        __syncthreads();
+        stage_update_batch<J, C, NS, T>(
+            sp, [&](unsigned q) -> T & { return sU[(q / RAW) * EP + q % RAW]; }, threadIdx.x, NT,
+            (unsigned)nel * RAW, e0, ss);
+    }
+    };
+    if constexpr (STG) {
+        // the stage epilogue's grid is bounded by its partial sums, so a
+        // workgroup may take several batches
+        for (int64_t bt = blockIdx.x; bt < nb; bt += gridDim.x) {
+            if (bt != (int64_t)blockIdx.x) __syncthreads();  // the tile is free again
+            run_batch(bt);
         }
     } else {
-        const int nv = nel * RAW;
-#pragma unroll 4
-        for (int k = threadIdx.x; k < nv; k += NT) {
-            const int ek = k / RAW, o = k - ek * RAW;
-            T x;
-            if (o < 4 * NS) {
-                const T *cx = sC + (ek * 4) * NS + o;
-                x = mid * ((cx[0] + cx[E * 4 * NS]) + cx[2 * E * 4 * NS]);
-            } else {
-                x = sU[ek * EP + o];
+        run_batch(blockIdx.x);
+    }
+    if constexpr (STG) {
+        if (sp.partial) {
+            // fixed-order workgroup sum: wave butterfly, then the waves in order
+            __shared__ double red[NT / 64];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double tsum = 0.0;
+                for (int w = 0; w < NT / 64; ++w) tsum += red[w];
+                sp.partial[blockIdx.x] = tsum;
             }
-            __builtin_nontemporal_store(x, dst + k);
         }
     }
 }
@@ -1867,8 +2196,16 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
         ((size_t)EMAX * (NV + 9) * NS + (size_t)6 * EMAX * CHP + OpsLayout<M>::size + 24) * sizeof(T);
     const void *ktr = (const void *)k_trace<P, T, DIAG>;
     constexpr bool STG_OK = StageEpilogue<P, T, DIAG>::value;
-    if (sp && !STG_OK)
+    // the halo form (line tasks that form the neighbours' traces from their
+    // states: no trace kernel), for the residual and for the stage epilogue
+    const bool halo = !MF && DIAG &&
+                      (sp ? stage_path(pl) == FR_STAGE_HALO
+                          : (pl->form == FR_FORM_HALO ||
+                             (pl->form == FR_FORM_AUTO && LinesShape<P, T>::AUTO == 2)));
+    if (sp && !STG_OK && !halo)
         return set_error(FR_EUNSUPPORTED, "stage epilogue not available at p=%d", P);
+    if (sp && halo && (sp->tr_in || sp->tr_out))
+        return set_error(FR_EINVAL, "halo-form stage epilogue: no face-trace arrays");
     const void *kfu = (const void *)k_fused<P, T, DIAG, false>;
     if constexpr (STG_OK)
         if (sp) kfu = (const void *)k_fused<P, T, DIAG, true>;
@@ -1876,12 +2213,13 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
         if (sp) return set_error(FR_EUNSUPPORTED, "matrix-core variant: no stage epilogue");
         kfu = (const void *)k_fused<P, T, DIAG, false, true>;
     }
-    // line-task form of the plain residual (diagonal Jacobian)
-    const bool lines = !MF && !sp && DIAG &&
-                       (pl->form == FR_FORM_LINES ||
-                        (pl->form == FR_FORM_AUTO && LinesShape<P, T>::AUTO));
-    if (!MF && !sp && !DIAG && pl->form == FR_FORM_LINES)
-        return set_error(FR_EUNSUPPORTED, "line-task form: diagonal Jacobians only");
+    // line-task forms (diagonal Jacobian); the plain line form's stage
+    // epilogue is the point form's
+    const bool lines = halo || (!MF && !sp && DIAG &&
+                                (pl->form == FR_FORM_LINES ||
+                                 (pl->form == FR_FORM_AUTO && LinesShape<P, T>::AUTO == 1)));
+    if (!MF && !sp && !DIAG && (pl->form == FR_FORM_LINES || pl->form == FR_FORM_HALO))
+        return set_error(FR_EUNSUPPORTED, "line-task forms: diagonal Jacobians only");
     // persistent grid: every workgroup that fits on the device at once
     auto persistent_grid = [&](const void *fn, int nt, size_t lds, int &grid) -> int {
         if (grid) return FR_OK;
@@ -1904,11 +2242,15 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
     int &grid_tr = pl->fused_grid[0][P][sizeof(T) == 8][DIAG];
     int &grid_fu = pl->fused_grid[MF ? 3 : (sp ? 2 : 1)][P][sizeof(T) == 8][DIAG];
     if (int rc = persistent_grid(ktr, TNT, lds_tr, grid_tr)) return rc;
-    if (!lines)
+    if (!lines && !halo)
         if (int rc = persistent_grid(kfu, NT, lds_fu, grid_fu)) return rc;
     const unsigned gtr = (unsigned)min(nbatch_tr, grid_tr);
     const unsigned gfu = (unsigned)min(min(nbatch, grid_fu), sp ? MAX_PARTIALS : grid_fu);
-    if (sp && sp->tr_in) {
+    if (!halo && !TR && !(sp && sp->tr_in))
+        return set_error(FR_EINVAL, "fused residual: no face-trace array");
+    if (halo) {
+        // no trace kernel: the line tasks form the neighbours' traces themselves
+    } else if (sp && sp->tr_in) {
         TR = static_cast<T *>(const_cast<void *>(sp->tr_in));
     } else if (DIAG && TraceLinesShape<P, T>::USE) {
         using TLS = TraceLinesShape<P, T>;
@@ -1936,17 +2278,32 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
         const int64_t nb = ((int64_t)ne + LE - 1) / LE;
         int &set = pl->lines_attr[0][P][sizeof(T) == 8];
         if (!set) {
-            if (int rc = check_hip(hipFuncSetAttribute((const void *)k_lines<P, T>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)lds_li),
-                                   "hipFuncSetAttribute"))
-                return rc;
+            for (const void *fn : {(const void *)k_lines<P, T, false, false>,
+                                   (const void *)k_lines<P, T, true, false>,
+                                   (const void *)k_lines<P, T, true, true>})
+                if (int rc = check_hip(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                           (int)lds_li),
+                                       "hipFuncSetAttribute"))
+                    return rc;
             set = 1;
         }
         ProfScope ps(prof ? pl : nullptr, FR_K_FUSED, s);
-        if constexpr (DIAG)
-            hipLaunchKernelGGL((k_lines<P, T>), dim3((unsigned)nb), dim3(LNT), lds_li, s, U, TR, R, ops,
-                               c, ne);
+        if constexpr (DIAG) {
+            if (sp) {
+                // one partial norm sum per workgroup
+                const unsigned g = (unsigned)std::min<int64_t>(nb, MAX_PARTIALS);
+                if (nparts) *nparts = (int)g;
+                hipLaunchKernelGGL((k_lines<P, T, true, true>), dim3(g), dim3(LNT), lds_li, s, U,
+                                   (const T *)nullptr, (T *)nullptr, ops, c, pl->nx, pl->ny, pl->nz,
+                                   *sp);
+            } else if (halo) {
+                hipLaunchKernelGGL((k_lines<P, T, true, false>), dim3((unsigned)nb), dim3(LNT), lds_li,
+                                   s, U, TR, R, ops, c, pl->nx, pl->ny, pl->nz, StageSpec{});
+            } else {
+                hipLaunchKernelGGL((k_lines<P, T, false, false>), dim3((unsigned)nb), dim3(LNT), lds_li,
+                                   s, U, TR, R, ops, c, pl->nx, pl->ny, pl->nz, StageSpec{});
+            }
+        }
         return check_hip(hipGetLastError(), "fused residual launch");
     }
     {
@@ -2005,7 +2362,10 @@ size_t trace_bytes(const fr_plan *pl)
 int fused_any(fr_plan *pl, const void *U, void *R, const StageSpec *sp, int *nparts,
               hipStream_t s, void *TR = nullptr, bool prof = true, bool mf = false)
 {
-    if (!TR) {
+    // the halo form needs no trace array (for a stage, the stage path decides
+    // the form: the point form's epilogue may follow a halo-form residual)
+    const bool halo = !mf && (sp ? stage_path(pl) == FR_STAGE_HALO : residual_form(pl) == FR_FORM_HALO);
+    if (!TR && !halo) {
         if (int rc = ensure_scratch(pl->traces, trace_bytes(pl))) return rc;
         TR = pl->traces.ptr;
     }
@@ -2065,7 +2425,8 @@ int launch_residual_noalloc(fr_plan *pl, const void *U, void *R, hipStream_t s)
 {
     if (pl->variant != FR_FUSED && pl->variant != FR_MFMA)
         return set_error(FR_EUNSUPPORTED, "fr_residual_noalloc: fused or matrix-core variant only");
-    const size_t need = trace_bytes(pl);
+    // the halo form forms the neighbours' traces itself and uses no array
+    const size_t need = residual_form(pl) == FR_FORM_HALO ? 0 : trace_bytes(pl);
     if (need > SCRATCH_BYTES)
         return set_error(FR_EINVAL,
                          "fr_residual_noalloc: the face traces need %zu bytes, the fixed array holds "
@@ -2085,12 +2446,12 @@ int residual_form(const fr_plan *pl)
 {
     if (pl->variant != FR_FUSED) return 0;
     if (pl->c64.diag == 0 || pl->form == FR_FORM_POINT) return FR_FORM_POINT;
-    if (pl->form == FR_FORM_LINES) return FR_FORM_LINES;
+    if (pl->form == FR_FORM_LINES || pl->form == FR_FORM_HALO) return pl->form;
     const bool f64 = pl->precision == FR_F64;
     auto pick = [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        return (f64 ? LinesShape<P, double>::AUTO : LinesShape<P, float>::AUTO) ? FR_FORM_LINES
-                                                                                : FR_FORM_POINT;
+        const int a = f64 ? LinesShape<P, double>::AUTO : LinesShape<P, float>::AUTO;
+        return a == 2 ? FR_FORM_HALO : (a == 1 ? FR_FORM_LINES : FR_FORM_POINT);
     };
     switch (pl->p) {
         case 1: return pick(Dir<1>{});
@@ -2103,7 +2464,8 @@ int residual_form(const fr_plan *pl)
     return FR_FORM_POINT;
 }
 
-bool fused_stage_available(const fr_plan *pl)
+// Whether the point form's kernel has a stage epilogue for this plan.
+static bool point_stage_available(const fr_plan *pl)
 {
     const bool dg = pl->c64.diag != 0, f64 = pl->precision == FR_F64;
     auto pick = [&](auto pc) {
@@ -2120,6 +2482,29 @@ bool fused_stage_available(const fr_plan *pl)
         case 6: return pick(Dir<6>{});
     }
     return false;
+}
+
+int stage_path(const fr_plan *pl)
+{
+    if (pl->variant != FR_FUSED || !pl->fuse_stage) return FR_STAGE_SEPARATE;
+    const int point = point_stage_available(pl) ? FR_STAGE_POINT : FR_STAGE_SEPARATE;
+    if (residual_form(pl) != FR_FORM_HALO) return point;
+    if (pl->form == FR_FORM_HALO) return FR_STAGE_HALO;
+    const bool f64 = pl->precision == FR_F64;
+    auto pick = [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        return f64 ? StageAuto<P, double>::value : StageAuto<P, float>::value;
+    };
+    int a = FR_STAGE_HALO;
+    switch (pl->p) {
+        case 1: a = pick(Dir<1>{}); break;
+        case 2: a = pick(Dir<2>{}); break;
+        case 3: a = pick(Dir<3>{}); break;
+        case 4: a = pick(Dir<4>{}); break;
+        case 5: a = pick(Dir<5>{}); break;
+        case 6: a = pick(Dir<6>{}); break;
+    }
+    return a == FR_STAGE_POINT ? point : a;
 }
 
 int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *nparts,

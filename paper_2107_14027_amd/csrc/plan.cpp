@@ -397,7 +397,8 @@ int fr_plan_set_int(fr_plan *pl, int key, int value)
             pl->pseudo = value;
             return FR_OK;
         case FR_OPT_FORM:
-            if (value != FR_FORM_AUTO && value != FR_FORM_POINT && value != FR_FORM_LINES)
+            if (value != FR_FORM_AUTO && value != FR_FORM_POINT && value != FR_FORM_LINES &&
+                value != FR_FORM_HALO)
                 return set_error(FR_EINVAL, "form %d", value);
             pl->form = value;
             return FR_OK;
@@ -420,6 +421,7 @@ int fr_plan_get_int(const fr_plan *pl, int key, int *value)
         case FR_OPT_PSEUDO: *value = pl->pseudo; return FR_OK;
         case FR_OPT_FORM: *value = pl->form; return FR_OK;
         case FR_INFO_RESIDUAL_FORM: *value = fr::residual_form(pl); return FR_OK;
+        case FR_INFO_STAGE_PATH: *value = fr::stage_path(pl); return FR_OK;
         default: return set_error(FR_EINVAL, "unknown option %d", key);
     }
 }

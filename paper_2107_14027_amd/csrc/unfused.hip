@@ -21,25 +21,46 @@ using namespace dev;
 // Buffers: Uf[6][ne][13][NF], Fs[3][ne][13][NS], Dv[ne][13][NS], FI[3][ne][13][NF]
 // ---------------------------------------------------------------------------
 
+// Stage 2: VW consecutive points of one element per thread (VW = 1 unless
+// m^3 is a multiple of the 16-byte vector width), every value read and
+// written in coalesced (vector) accesses.
+template <int P, typename T>
+struct FluxShape {
+    static constexpr int NS = (P + 1) * (P + 1) * (P + 1), W16 = 16 / (int)sizeof(T);
+    static constexpr int VW = NS % W16 == 0 ? W16 : 1;
+};
+
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_u_flux(const T *__restrict__ U, T *__restrict__ Fs,
                                                 Consts<T> c, int64_t ne)
 {
-    constexpr int M = P + 1, NS = M * M * M;
+    constexpr int M = P + 1, NS = M * M * M, VW = FluxShape<P, T>::VW;
+    typedef T Vw __attribute__((ext_vector_type(VW)));
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ne * NS) return;
-    const int64_t e = t / NS;
-    const int q = (int)(t - e * NS);
-    T u[NV];
+    if (t >= ne * NS / VW) return;
+    const int64_t e = t * VW / NS;
+    const int q = (int)(t * VW - e * NS);
+    Vw u[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u[v] = U[(e * NV + v) * NS + q];
+    for (int v = 0; v < NV; ++v)
+        u[v] = __builtin_nontemporal_load(reinterpret_cast<const Vw *>(U + (e * NV + v) * NS + q));
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         T nv[3] = {c.nvec[d][0], c.nvec[d][1], c.nvec[d][2]};
-        T f[NV];
-        flux_dot<T>(u, nv, c.zeta, c.nu, c.invT, f);
+        Vw f[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Fs[(((int64_t)d * ne + e) * NV + v) * NS + q] = f[v];
+        for (int w = 0; w < VW; ++w) {
+            T uw[NV], fw[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) uw[v] = u[v][w];
+            flux_dot<T>(uw, nv, c.zeta, c.nu, c.invT, fw);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) f[v][w] = fw[v];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            __builtin_nontemporal_store(
+                f[v], reinterpret_cast<Vw *>(Fs + (((int64_t)d * ne + e) * NV + v) * NS + q));
     }
 }
 
@@ -228,7 +249,9 @@ __global__ void __launch_bounds__(256)
 template <int P, typename T>
 struct CommonShape {
     static constexpr int M = P + 1, NF = M * M;
-    static constexpr int E = NF >= 64 ? 1 : 64 / NF;
+    // as many elements as keep the three face-block buffers within 48 KB
+    static constexpr int EMAX = (48 * 1024) / (3 * NV * NF * (int)sizeof(T));
+    static constexpr int E = EMAX < 32 ? EMAX : 32;
     static constexpr int NT = 64 * ((E * NF + 63) / 64);
 };
 
@@ -365,7 +388,8 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
     }
     {
         ProfScope ps(pl, FR_K_U_FLUX, s);
-        hipLaunchKernelGGL((k_u_flux<P, T>), g(ne * NS), dim3(nt), 0, s, U, Fs, c, ne);
+        hipLaunchKernelGGL((k_u_flux<P, T>), g(ne * NS / FluxShape<P, T>::VW), dim3(nt), 0, s, U, Fs,
+                           c, ne);
     }
     {
         ProfScope ps(pl, FR_K_U_DIV, s);

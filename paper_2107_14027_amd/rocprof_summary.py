@@ -36,9 +36,13 @@ def short(name):
     m = re.search(r"(k_\w+)<(\d+), (\w+)((?:, \w+)*)>", name)
     if m:
         kern, p, t, extra = m.groups()
-        # the fused kernel's last template argument selects the stage epilogue
-        if kern == "k_fused" and extra.endswith("true") and extra.count(",") == 2:
+        # k_fused<P, T, DIAG, STG[, MF]>: STG selects the stage epilogue;
+        # k_lines<P, T, HALO>: HALO forms the neighbour traces from their states
+        args = [a.strip() for a in extra.split(",") if a.strip()]
+        if kern == "k_fused" and len(args) >= 2 and args[1] == "true":
             kern = "k_fused_stage"
+        if kern == "k_lines" and args and args[0] == "true":
+            kern = "k_lines_halo"
         return "%s<%s,%s>" % (kern, p, t)
     m = re.search(r"(k_\w+)<([^>]*)>", name)
     if m:
@@ -107,7 +111,7 @@ def traffic(args):
     fs, fcal, fk, fn = res["FETCH_SIZE"]
     ws, wcal, wk, wn = res["WRITE_SIZE"]
     for k in sorted(set(fk) & set(wk)):
-        m = re.match(r"(k_fused|k_trace|k_lines|k_trace_lines|k_fused_stage)<(\d+),(\w+)>", k)
+        m = re.match(r"(k_fused|k_trace|k_lines|k_lines_halo|k_trace_lines|k_fused_stage)<(\d+),(\w+)>", k)
         if not m:
             continue
         tag = "%s_p%s_%s" % (m.group(1), m.group(2), "f64" if m.group(3) == "double" else "f32")

@@ -29,6 +29,22 @@ def test_library_exports_every_declared_function():
     assert set(names) == set(B.EXPORTED)
 
 
+def test_binding_constants_match_header():
+    """Every FR_ constant the binding defines has the value include/fr.h gives
+    it (enumerators with an explicit value)."""
+    src = open(os.path.join(ROOT, "include", "fr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    header = {k: int(v) for k, v in re.findall(r"\b(FR_\w+)\s*=\s*(-?\d+)", src)}
+    checked = 0
+    for name in dir(B):
+        if name.startswith("FR_") and isinstance(getattr(B, name), int) and name in header:
+            assert getattr(B, name) == header[name], name
+            checked += 1
+    assert checked >= 30
+    for name in ("FR_INFO_RESIDUAL_FORM", "FR_INFO_STAGE_PATH", "FR_STAGE_HALO", "FR_FORM_HALO"):
+        assert name in header and hasattr(B, name), name
+
+
 def test_strerror_and_invalid_arguments_fail_before_device_work():
     assert B.lib().fr_strerror(B.FR_ENOCONV).decode().startswith("pseudo-time")
     for args in [(0, 4, 4, 4, None, 4.0, (1e-3, 1.0)),      # order out of range

@@ -61,7 +61,7 @@ def test_orders_ragged(p, n, prec, var, jac):
     check_groups(R, Ro, prec, U, what="p=%d jac=%s" % (p, jac))
 
 
-FORMS = [B.FR_FORM_POINT, B.FR_FORM_LINES]
+FORMS = [B.FR_FORM_POINT, B.FR_FORM_LINES, B.FR_FORM_HALO]
 
 
 @pytest.mark.parametrize("p,n", CASES)
@@ -78,9 +78,10 @@ def test_forms_ragged(p, n, prec, form):
     check_groups(R, Ro, prec, U, what="p=%d form=%d" % (p, form))
 
 
-def test_line_form_needs_diagonal_jacobian():
+@pytest.mark.parametrize("form", [B.FR_FORM_LINES, B.FR_FORM_HALO])
+def test_line_forms_need_diagonal_jacobian(form):
     with pytest.raises(B.FrError) as ei:
-        gpu_residual(2, (2, 2, 2), rand_U(2, (2, 2, 2), 1), jac=SKEW, form=B.FR_FORM_LINES)
+        gpu_residual(2, (2, 2, 2), rand_U(2, (2, 2, 2), 1), jac=SKEW, form=form)
     assert ei.value.code == B.FR_EUNSUPPORTED
 
 
@@ -92,7 +93,7 @@ def test_degenerate_lattices(n, prec):
     U = rand_U(p, n, seed=7)
     say("degenerate n=%s prec=%d" % (n, prec))
     for var, form in ((B.FR_FUSED, B.FR_FORM_POINT), (B.FR_FUSED, B.FR_FORM_LINES),
-                      (B.FR_UNFUSED, B.FR_FORM_AUTO)):
+                      (B.FR_FUSED, B.FR_FORM_HALO), (B.FR_UNFUSED, B.FR_FORM_AUTO)):
         R = gpu_residual(p, n, U, precision=prec, variant=var, form=form)
         Ro = oracle.residual(p, n, U, ZETA, NU, T_CFG)
         assert rel(R, Ro) <= TOL[prec]
@@ -134,18 +135,21 @@ def test_block_size_invariance_and_determinism(p):
     lines = gpu_residual(p, n, U, form=B.FR_FORM_LINES)
     assert np.array_equal(lines, gpu_residual(p, n, U, form=B.FR_FORM_LINES))
     assert rel(lines, ref) <= 1e-13
+    # the halo form forms the neighbours' traces itself with the trace kernel's
+    # arithmetic: the same bits as the line form
+    assert np.array_equal(gpu_residual(p, n, U, form=B.FR_FORM_HALO), lines)
 
 
 def test_auto_form_choice_is_reported():
-    """FR_INFO_RESIDUAL_FORM names the kernel form fr_residual runs: the line
-    form at the orders the automatic choice documents (p = 2, 3, 4 in double,
-    p = 2, 3, 5, 6 in single precision, diagonal Jacobian), else the point form;
-    0 for the unfused and matrix-core variants."""
-    lines = {B.FR_F64: {2, 3, 4}, B.FR_F32: {2, 3, 5, 6}}
+    """FR_INFO_RESIDUAL_FORM names the kernel form fr_residual runs: the halo
+    form at the orders the automatic choice documents (every order, diagonal
+    Jacobian), else the point form; 0 for the unfused and matrix-core
+    variants."""
+    halo = {B.FR_F64: {1, 2, 3, 4, 5, 6}, B.FR_F32: {1, 2, 3, 4, 5, 6}}
     for prec in PREC:
         for p in range(1, 7):
             plan = B.Plan(p, (2, 2, 2), ZETA, NU, T_CFG, precision=prec)
-            want = B.FR_FORM_LINES if p in lines[prec] else B.FR_FORM_POINT
+            want = B.FR_FORM_HALO if p in halo[prec] else B.FR_FORM_POINT
             assert B.fr_plan_get_int(plan.handle, B.FR_INFO_RESIDUAL_FORM) == want, (prec, p)
             plan.set(B.FR_OPT_FORM, B.FR_FORM_POINT)
             assert B.fr_plan_get_int(plan.handle, B.FR_INFO_RESIDUAL_FORM) == B.FR_FORM_POINT

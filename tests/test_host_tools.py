@@ -18,6 +18,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.mark.parametrize("name,short", [
     ("void fr::(anonymous namespace)::k_fused<3, double, true, false>(double const*)", "k_fused<3,double>"),
     ("void fr::(anonymous namespace)::k_fused<3, double, true, true>(double const*)", "k_fused_stage<3,double>"),
+    ("void fr::(anonymous namespace)::k_fused<3, double, true, true, false>(double const*)",
+     "k_fused_stage<3,double>"),
+    ("void fr::(anonymous namespace)::k_fused<6, double, true, false, false>(double const*)",
+     "k_fused<6,double>"),
+    ("void fr::(anonymous namespace)::k_lines<2, double, true>(double const*)", "k_lines_halo<2,double>"),
+    ("void fr::(anonymous namespace)::k_lines<2, float, false>(float const*)", "k_lines<2,float>"),
     ("void fr::(anonymous namespace)::k_trace<6, float, true>(float const*)", "k_trace<6,float>"),
     ("void fr::(anonymous namespace)::k_stage<double, true, false>(double*)", "k_stage<double,true,false>"),
     ("void fr::(anonymous namespace)::k_final_sum(double const*, int, double*)", "k_final_sum"),
