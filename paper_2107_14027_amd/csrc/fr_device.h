@@ -162,10 +162,10 @@ struct LinesLds {
     static constexpr int OPS = (OpsLayout<M>::size * (int)sizeof(T) + 15) / 16 * 16 / (int)sizeof(T);
     // LDS values of a batch of E elements: operators, state tile, and the
     // directions' P and momentum parts that wait in LDS (three directions for
-    // xr = 0, two for xr = 1, none for xr = 2)
+    // xr = 0, two for xr = 1, none for xr = 2, 3)
     static constexpr int values(int E, int xr)
     {
-        return OPS + E * EP + (xr == 2 ? 0 : (xr == 1 ? 8 : 12)) * E * NS;
+        return OPS + E * EP + (xr >= 2 ? 0 : (xr == 1 ? 8 : 12)) * E * NS;
     }
 };
 

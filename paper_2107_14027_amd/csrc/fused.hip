@@ -1152,8 +1152,13 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 //   2  all in registers; after a barrier (the state's P and velocity values are
 //      dead by then) the x lanes store theirs over those values, the y lanes
 //      add theirs, the z lanes add and scale, and the finished tile is R
-// Mode 2 needs no LDS beyond the tile (more workgroups per CU), at the cost of
-// registers and two more barriers.  All three give the same bits.
+//   3  as 2, but the momentum parts are summed between the line task's two
+//      halves (after every lane has read the tile's P and velocities for the
+//      last time) and the P parts after the second, so that the flux half's
+//      and the velocity half's results are never held in registers together
+// Modes 2 and 3 need no LDS beyond the tile (more workgroups per CU), at the
+// cost of registers and more barriers; mode 3 holds about as many registers
+// as mode 0 and is the default.  All four give the same bits.
 // ---------------------------------------------------------------------------
 #ifndef FR_LE1_D
 #define FR_LE1_D 16
@@ -1229,40 +1234,40 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #endif
 
 #ifndef FR_LX1_D
-#define FR_LX1_D 2
+#define FR_LX1_D 3
 #endif
 #ifndef FR_LX2_D
-#define FR_LX2_D 0
+#define FR_LX2_D 3
 #endif
 #ifndef FR_LX3_D
-#define FR_LX3_D 0
+#define FR_LX3_D 3
 #endif
 #ifndef FR_LX4_D
-#define FR_LX4_D 0
+#define FR_LX4_D 3
 #endif
 #ifndef FR_LX5_D
-#define FR_LX5_D 0
+#define FR_LX5_D 3
 #endif
 #ifndef FR_LX6_D
-#define FR_LX6_D 0
+#define FR_LX6_D 3
 #endif
 #ifndef FR_LX1_F
-#define FR_LX1_F 0
+#define FR_LX1_F 3
 #endif
 #ifndef FR_LX2_F
-#define FR_LX2_F 2
+#define FR_LX2_F 3
 #endif
 #ifndef FR_LX3_F
 #define FR_LX3_F 0
 #endif
 #ifndef FR_LX4_F
-#define FR_LX4_F 0
+#define FR_LX4_F 3
 #endif
 #ifndef FR_LX5_F
-#define FR_LX5_F 1
+#define FR_LX5_F 3
 #endif
 #ifndef FR_LX6_F
-#define FR_LX6_F 2
+#define FR_LX6_F 3
 #endif
 // FR_FORM_AUTO's choice per order and precision (0: point form with the trace
 // kernel, 1: line form with the trace kernel, 2: halo form, no trace kernel),
@@ -1305,7 +1310,11 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #ifndef FR_LA6_F
 #define FR_LA6_F 2
 #endif
-// Waves per SIMD the register allocation of k_lines aims for (at least).
+// Waves per SIMD the register allocation of the line-form residual kernels aims
+// for (at least): 3 at p = 6 in double precision (168 VGPRs with a few values
+// spilled, against 171 VGPRs and two waves without the hint: 1.63 against
+// 2.13 ms per halo residual on 40^3 hexes); the stage-epilogue kernels take no
+// hint.
 #ifndef FR_LV_DEFAULT
 #define FR_LV_DEFAULT 1
 #endif
@@ -1325,7 +1334,7 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #define FR_LV5_D FR_LV_DEFAULT
 #endif
 #ifndef FR_LV6_D
-#define FR_LV6_D FR_LV_DEFAULT
+#define FR_LV6_D 3
 #endif
 #ifndef FR_LV1_F
 #define FR_LV1_F FR_LV_DEFAULT
@@ -1386,7 +1395,7 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #define FR_SA5_F FR_STAGE_POINT
 #endif
 #ifndef FR_SA6_F
-#define FR_SA6_F FR_STAGE_SEPARATE
+#define FR_SA6_F FR_STAGE_HALO
 #endif
 template <int P, typename T> struct StageAuto;
 #define FR_SAUTO(PP, TT, S) \
@@ -1517,29 +1526,38 @@ template <int P, typename T> struct LinesRolled {
     static constexpr bool value = FR_LROLL != 0;
 };
 
-// One direction's line task on the element tile Ut (LDS, updated in place).
+// One direction's line task on the element tile Ut (LDS, updated in place),
+// in three phases that a caller may separate by barriers:
+//   lt_fluxes      the line's own traces (k_trace's chain), the two common
+//                  fluxes FIm / FIp, the transformed momentum fluxes and their
+//                  corrected derivatives (momentum parts)
+//   lt_velocities  the line's velocities (read from the tile)
+//   lt_derivs      their corrected derivatives: the auxiliary residuals (a, D)
+//                  replace S_aD in the tile (only this lane touches those
+//                  values) and the P part zeta n_DD du_D/dxi_D + dissipation
 // sop: the operator block in LDS; oth{m,p}: the neighbours' traces on the
-// line's two face points; sCd: this direction's P / momentum slots of the
-// element, [4][m^3].  Writes, at every point r of the line, the auxiliary
-// residual (a, D) over S_aD in the tile (only this lane touches those values)
-// and the direction's P part zeta n_DD du_D/dxi_D + dissipation and corrected
-// momentum-flux derivatives to sCd ([4][m^3] slots of the element), or with XR
-// to ctb[0..3][r] in registers.
+// line's two face points.  The P and momentum parts go to sCd (this
+// direction's [4][m^3] slots of the element) or, with XR, to ctb[0..3][r] in
+// registers.
+template <int P, typename T, int D>
+__device__ __forceinline__ int lt_base(int L)
+{
+    constexpr int M = P + 1;
+    const int a = L % M, b = L / M;
+    return D == 0 ? M * L : (D == 1 ? a + M * M * b : L);
+}
+
 template <int P, typename T, int D, bool XR>
-__device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restrict__ sop,
+__device__ __forceinline__ void lt_fluxes(T *__restrict__ Ut, const T *__restrict__ sop,
                                           const T (&othm)[NTR], const T (&othp)[NTR],
                                           const Consts<T> &c, int L, T *__restrict__ sCd,
-                                          T (&ctb)[4][P + 1])
+                                          T (&ctb)[4][P + 1], T (&FIm)[NTR], T (&FIp)[NTR])
 {
     constexpr int M = P + 1, NS = M * M * M;
     constexpr int STR = D == 0 ? 1 : (D == 1 ? M : M * M);
     using OL = OpsLayout<M>;
-    const int a = L % M, b = L / M;
-    const int base = D == 0 ? M * L : (D == 1 ? a + M * M * b : L);
+    const int base = lt_base<P, T, D>(L);
     T *Ue = Ut + base;
-    // own traces (k_trace's chain), one variable's line at a time, and the two
-    // common fluxes
-    T FIm[NTR], FIp[NTR];
     {
         T lm[M], lp[M];
 #pragma unroll
@@ -1593,9 +1611,8 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
         }
     }
     __builtin_amdgcn_sched_barrier(0);
-    // two passes over the rows, so that the fluxes and the velocities are not
-    // live at once: first the corrected derivatives of the three fluxes, then
-    // those of the three velocities (auxiliary residuals (a, D), P part)
+    // the corrected derivatives of the three fluxes, row by row (the fluxes
+    // and the velocities are never live at once)
     auto rowF = [&](int r) {
         // one row's operator values at a time (bounds the live registers)
         __builtin_amdgcn_sched_barrier(0);
@@ -1614,7 +1631,41 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
             else sCd[(1 + i) * NS + base + q] = cf;
         }
     };
-    T X[3][M];
+    // with XR the row index selects registers, so the loop is unrolled;
+    // otherwise it stays rolled (fewer live registers)
+    if constexpr (XR || !LinesRolled<P, T>::value) {
+#pragma unroll
+        for (int r = 0; r < M; ++r) rowF(r);
+    } else {
+#pragma unroll 1
+        for (int r = 0; r < M; ++r) rowF(r);
+    }
+}
+
+template <int P, typename T, int D>
+__device__ __forceinline__ void lt_velocities(const T *__restrict__ Ut, int L, T (&X)[3][P + 1])
+{
+    constexpr int M = P + 1, NS = M * M * M;
+    constexpr int STR = D == 0 ? 1 : (D == 1 ? M : M * M);
+    __asm__ volatile("" ::: "memory");  // read the velocities again
+    __builtin_amdgcn_sched_barrier(0);
+    const T *Ue = Ut + lt_base<P, T, D>(L);
+#pragma unroll
+    for (int ia = 0; ia < 3; ++ia) line_load<M, STR>(Ue + (1 + ia) * NS, X[ia]);
+}
+
+template <int P, typename T, int D, bool XR>
+__device__ __forceinline__ void lt_derivs(T *__restrict__ Ut, const T *__restrict__ sop,
+                                          const T (&X)[3][P + 1], const T (&FIm)[NTR],
+                                          const T (&FIp)[NTR], const Consts<T> &c, int L,
+                                          T *__restrict__ sCd, T (&ctb)[4][P + 1])
+{
+    constexpr int M = P + 1, NS = M * M * M;
+    constexpr int STR = D == 0 ? 1 : (D == 1 ? M : M * M);
+    using OL = OpsLayout<M>;
+    const int base = lt_base<P, T, D>(L);
+    T *Ue = Ut + base;
+    const T ndd = c.nvec[D][D];
     auto rowV = [&](int r) {
         __builtin_amdgcn_sched_barrier(0);
         T Dr[M];
@@ -1639,27 +1690,26 @@ __device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restric
         if constexpr (XR) ctb[0][r] = pc;
         else sCd[base + q] = pc;
     };
-    // with XR the row index selects registers, so the loops are unrolled;
-    // otherwise they stay rolled (fewer live registers)
     if constexpr (XR || !LinesRolled<P, T>::value) {
-#pragma unroll
-        for (int r = 0; r < M; ++r) rowF(r);
-        __asm__ volatile("" ::: "memory");  // read the velocities again
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int ia = 0; ia < 3; ++ia) line_load<M, STR>(Ue + (1 + ia) * NS, X[ia]);
 #pragma unroll
         for (int r = 0; r < M; ++r) rowV(r);
     } else {
 #pragma unroll 1
-        for (int r = 0; r < M; ++r) rowF(r);
-        __asm__ volatile("" ::: "memory");  // read the velocities again
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int ia = 0; ia < 3; ++ia) line_load<M, STR>(Ue + (1 + ia) * NS, X[ia]);
-#pragma unroll 1
         for (int r = 0; r < M; ++r) rowV(r);
     }
+}
+
+// The three phases in a row.
+template <int P, typename T, int D, bool XR>
+__device__ __forceinline__ void line_task(T *__restrict__ Ut, const T *__restrict__ sop,
+                                          const T (&othm)[NTR], const T (&othp)[NTR],
+                                          const Consts<T> &c, int L, T *__restrict__ sCd,
+                                          T (&ctb)[4][P + 1])
+{
+    T FIm[NTR], FIp[NTR], X[3][P + 1];
+    lt_fluxes<P, T, D, XR>(Ut, sop, othm, othp, c, L, sCd, ctb, FIm, FIp);
+    lt_velocities<P, T, D>(Ut, L, X);
+    lt_derivs<P, T, D, XR>(Ut, sop, X, FIm, FIp, c, L, sCd, ctb);
 }
 
 // The face trace of a neighbour element, from its state Un (global memory or
@@ -1703,7 +1753,7 @@ constexpr int line_stage_chunk()
 
 template <int P, typename T, bool HALO, bool STG>
 __global__ void __launch_bounds__((LinesShape<P, T>::NT))
-    __attribute__((amdgpu_waves_per_eu(LinesShape<P, T>::WPE, 8)))
+    __attribute__((amdgpu_waves_per_eu(STG ? 1 : LinesShape<P, T>::WPE, 8)))
     k_lines(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
             const T *__restrict__ ops, Consts<T> c, int nx, int ny, int nz, StageSpec sp)
 {
@@ -1786,50 +1836,92 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
         if constexpr (W > 1) __syncthreads();
     }
     T ctb[4][M];
-    if (act) {
+    const T mid = -c.inv_det;
+    // the parts ctb[k0..k1) of this lane's line added over the tile's P and
+    // velocity values (x stores, y adds, z adds and scales by -1/det J)
+    auto add_lines = [&](auto dc, auto k0c, auto k1c) {
+        constexpr int DD = decltype(dc)::value;
+        constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+        constexpr int STR = DD == 0 ? 1 : (DD == 1 ? M : M * M);
+        T *Ue = sU + el * EP + lt_base<P, T, DD>(L);
+#pragma unroll
+        for (int k = K0; k < K1; ++k) {
+            T o[M];
+            if constexpr (DD == 0) {
+#pragma unroll
+                for (int r = 0; r < M; ++r) o[r] = ctb[k][r];
+            } else {
+                line_load<M, STR>(Ue + k * NS, o);
+#pragma unroll
+                for (int r = 0; r < M; ++r) o[r] = o[r] + ctb[k][r];
+                if constexpr (DD == 2) {
+#pragma unroll
+                    for (int r = 0; r < M; ++r) o[r] = mid * o[r];
+                }
+            }
+            line_put<M, STR>(Ue + k * NS, o);
+        }
+    };
+    if constexpr (XR == 3) {
+        // the momentum parts are summed between the two halves of the line
+        // task, once every lane has read the tile's P and velocities, and the
+        // P parts after it: the fluxes' and the velocities' parts are never
+        // held in registers together
+        T FIm[NTR], FIp[NTR], X[3][M];
         T *Ut = sU + el * EP;
-        T *sCd = sC + ((d * E + el) * 4) * NS;
-        if (d == 0) line_task<P, T, 0, (XR >= 1)>(Ut, sop, othm, othp, c, L, sCd, ctb);
-        else if (d == 1) line_task<P, T, 1, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
-        else line_task<P, T, 2, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
+        if (act) {
+            auto ph1 = [&](auto dc) {
+                constexpr int DD = decltype(dc)::value;
+                lt_fluxes<P, T, DD, true>(Ut, sop, othm, othp, c, L, nullptr, ctb, FIm, FIp);
+                lt_velocities<P, T, DD>(Ut, L, X);
+            };
+            if (d == 0) ph1(Dir<0>{});
+            else if (d == 1) ph1(Dir<1>{});
+            else ph1(Dir<2>{});
+        }
+        __syncthreads();
+        if (act && d == 0) add_lines(Dir<0>{}, Dir<1>{}, Dir<4>{});
+        __syncthreads();
+        if (act && d == 1) add_lines(Dir<1>{}, Dir<1>{}, Dir<4>{});
+        __syncthreads();
+        if (act && d == 2) add_lines(Dir<2>{}, Dir<1>{}, Dir<4>{});
+        if (act) {
+            if (d == 0) lt_derivs<P, T, 0, true>(Ut, sop, X, FIm, FIp, c, L, nullptr, ctb);
+            else if (d == 1) lt_derivs<P, T, 1, true>(Ut, sop, X, FIm, FIp, c, L, nullptr, ctb);
+            else lt_derivs<P, T, 2, true>(Ut, sop, X, FIm, FIp, c, L, nullptr, ctb);
+        }
+        if (act && d == 0) add_lines(Dir<0>{}, Dir<0>{}, Dir<1>{});
+        __syncthreads();
+        if (act && d == 1) add_lines(Dir<1>{}, Dir<0>{}, Dir<1>{});
+        __syncthreads();
+        if (act && d == 2) add_lines(Dir<2>{}, Dir<0>{}, Dir<1>{});
+    } else {
+        if (act) {
+            T *Ut = sU + el * EP;
+            T *sCd = sC + ((d * E + el) * 4) * NS;
+            if (d == 0) line_task<P, T, 0, (XR >= 1)>(Ut, sop, othm, othp, c, L, sCd, ctb);
+            else if (d == 1) line_task<P, T, 1, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
+            else line_task<P, T, 2, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // R of the batch: P and momentum summed over the three directions in the
     // order x, y, z and scaled by -1/det J, the auxiliary residuals from the
     // tile.  Without STG it goes to R; with STG it stays in the tile for the
     // stage update.
-    const T mid = -c.inv_det;
-    if constexpr (XR == 2) {
+    if constexpr (XR == 3) {
+        if constexpr (!STG) {
+            __syncthreads();
+            tile_store<P, T, NT>(sU, R + e0 * RAW, nel);
+        }
+    } else if constexpr (XR == 2) {
         // summed over the tile's P and velocity values, one direction after
         // the other
-        auto add_lines = [&](auto dc) {
-            constexpr int DD = decltype(dc)::value;
-            constexpr int STR = DD == 0 ? 1 : (DD == 1 ? M : M * M);
-            const int a = L % M, b = L / M;
-            T *Ue = sU + el * EP + (DD == 0 ? M * L : (DD == 1 ? a + M * M * b : L));
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                T o[M];
-                if constexpr (DD == 0) {
-#pragma unroll
-                    for (int r = 0; r < M; ++r) o[r] = ctb[k][r];
-                } else {
-                    line_load<M, STR>(Ue + k * NS, o);
-#pragma unroll
-                    for (int r = 0; r < M; ++r) o[r] = o[r] + ctb[k][r];
-                    if constexpr (DD == 2) {
-#pragma unroll
-                        for (int r = 0; r < M; ++r) o[r] = mid * o[r];
-                    }
-                }
-                line_put<M, STR>(Ue + k * NS, o);
-            }
-        };
-        if (act && d == 0) add_lines(Dir<0>{});
+        if (act && d == 0) add_lines(Dir<0>{}, Dir<0>{}, Dir<4>{});
         __syncthreads();
-        if (act && d == 1) add_lines(Dir<1>{});
+        if (act && d == 1) add_lines(Dir<1>{}, Dir<0>{}, Dir<4>{});
         __syncthreads();
-        if (act && d == 2) add_lines(Dir<2>{});
+        if (act && d == 2) add_lines(Dir<2>{}, Dir<0>{}, Dir<4>{});
         if constexpr (!STG) {
             __syncthreads();
             tile_store<P, T, NT>(sU, R + e0 * RAW, nel);

@@ -64,6 +64,96 @@ __global__ void __launch_bounds__(256) k_u_flux(const T *__restrict__ U, T *__re
     }
 }
 
+// Which stage-2 kernel runs, per order and precision (measured).
+#ifndef FR_UFLUX_LDS
+#define FR_UFLUX_LDS 1
+#endif
+template <int P, typename T>
+constexpr bool unfused_flux_lds()
+{
+    return FR_UFLUX_LDS != 0;
+}
+
+// Stage 2 with contiguous writes: a workgroup copies a batch of E consecutive
+// elements' states into LDS (one contiguous block), then writes the batch's
+// block of F_s for each direction as one contiguous stream, every output value
+// formed from the staged state with flux_dot's arithmetic for that component.
+template <int P, typename T>
+struct FluxLdsShape {
+    static constexpr int NS = (P + 1) * (P + 1) * (P + 1), RAW = NV * NS, NT = 256;
+    // about 24 KB of state per workgroup (one element where that is larger),
+    // rounded down to a whole number of 16-byte chunks per batch where that
+    // leaves at least one element, so that every batch starts on a 16-byte
+    // boundary (else the copy is scalar)
+    static constexpr int AL = 16 / sizeof(T);
+    static constexpr int E0 = 24576 / (RAW * (int)sizeof(T)) > 0 ? 24576 / (RAW * (int)sizeof(T)) : 1;
+    static constexpr int step = RAW % AL == 0 ? 1 : (RAW % 2 == 0 ? AL / 2 : AL);
+    static constexpr int E = E0 >= step ? E0 / step * step : E0;
+    static constexpr bool VEC = (E * RAW) % AL == 0;
+};
+
+// Component v of flux_dot(U, nv) at one point: u[w * NS] is variable w there.
+// The same operations in the same order as flux_dot, so the same bits.
+template <typename T, int NS>
+__device__ __forceinline__ T flux_component(int v, const T *__restrict__ u, const T nv[3], T zeta,
+                                            T nu, T invT)
+{
+    if (v == 0) {
+        T vn = u[NS] * nv[0];
+        vn = fma(u[2 * NS], nv[1], vn);
+        vn = fma(u[3 * NS], nv[2], vn);
+        return zeta * vn;
+    }
+    if (v < 4) {
+        const int i = v - 1;
+        T vn = u[NS] * nv[0];
+        vn = fma(u[2 * NS], nv[1], vn);
+        vn = fma(u[3 * NS], nv[2], vn);
+        const T *S = u + (4 + 3 * i) * NS;
+        T sn = S[0] * nv[0];
+        sn = fma(S[NS], nv[1], sn);
+        sn = fma(S[2 * NS], nv[2], sn);
+        return fma(u[(1 + i) * NS], vn, fma(u[0], nv[i], -nu * sn));
+    }
+    const int i = (v - 4) / 3, k = v - 4 - 3 * i;
+    return -invT * u[(1 + i) * NS] * nv[k];
+}
+
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_u_flux_lds(const T *__restrict__ U, T *__restrict__ Fs,
+                                                    Consts<T> c, int64_t ne)
+{
+    using FS = FluxLdsShape<P, T>;
+    constexpr int NS = FS::NS, RAW = FS::RAW, E = FS::E, NT = FS::NT;
+    __shared__ __align__(16) T sU[E * RAW];
+    const int64_t e0 = (int64_t)blockIdx.x * E;
+    const int nel = (int)min((int64_t)E, ne - e0);
+    const int cnt = nel * RAW;
+    const T *src = U + e0 * RAW;
+    if constexpr (FS::VEC) {
+        using V = typename V16<T>::type;
+        constexpr int VW = 16 / sizeof(T);
+        const int nv = cnt / VW;
+        for (int k = threadIdx.x; k < nv; k += NT)
+            reinterpret_cast<V *>(sU)[k] = __builtin_nontemporal_load(reinterpret_cast<const V *>(src) + k);
+        for (int k = nv * VW + threadIdx.x; k < cnt; k += NT) sU[k] = __builtin_nontemporal_load(src + k);
+    } else {
+        for (int k = threadIdx.x; k < cnt; k += NT) sU[k] = __builtin_nontemporal_load(src + k);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+        const T nvd[3] = {c.nvec[d][0], c.nvec[d][1], c.nvec[d][2]};
+        T *dst = Fs + ((int64_t)d * ne + e0) * RAW;
+        for (int o = threadIdx.x; o < cnt; o += NT) {
+            const int el = o / RAW, r = o - el * RAW;
+            const int v = r / NS, q = r - v * NS;
+            __builtin_nontemporal_store(
+                flux_component<T, NS>(v, sU + el * RAW + q, nvd, c.zeta, c.nu, c.invT), dst + o);
+        }
+    }
+}
+
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_u_negsrc(const T *__restrict__ Dv, const T *__restrict__ U,
                                                   T *__restrict__ R, Consts<T> c, int64_t ne)
@@ -388,8 +478,13 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
     }
     {
         ProfScope ps(pl, FR_K_U_FLUX, s);
-        hipLaunchKernelGGL((k_u_flux<P, T>), g(ne * NS / FluxShape<P, T>::VW), dim3(nt), 0, s, U, Fs,
-                           c, ne);
+        if (unfused_flux_lds<P, T>())
+            hipLaunchKernelGGL((k_u_flux_lds<P, T>),
+                               dim3((unsigned)((ne + FluxLdsShape<P, T>::E - 1) / FluxLdsShape<P, T>::E)),
+                               dim3(FluxLdsShape<P, T>::NT), 0, s, U, Fs, c, ne);
+        else
+            hipLaunchKernelGGL((k_u_flux<P, T>), g(ne * NS / FluxShape<P, T>::VW), dim3(nt), 0, s, U,
+                               Fs, c, ne);
     }
     {
         ProfScope ps(pl, FR_K_U_DIV, s);

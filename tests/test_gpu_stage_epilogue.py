@@ -126,7 +126,7 @@ def test_halo_epilogue_workgroups_take_several_batches(prec):
 AUTO_STAGE = {B.FR_F64: {1: B.FR_STAGE_HALO, 2: B.FR_STAGE_HALO, 3: B.FR_STAGE_POINT,
                          4: B.FR_STAGE_POINT, 5: B.FR_STAGE_POINT, 6: B.FR_STAGE_HALO},
               B.FR_F32: {1: B.FR_STAGE_HALO, 2: B.FR_STAGE_HALO, 3: B.FR_STAGE_HALO,
-                         4: B.FR_STAGE_POINT, 5: B.FR_STAGE_POINT, 6: B.FR_STAGE_SEPARATE}}
+                         4: B.FR_STAGE_POINT, 5: B.FR_STAGE_POINT, 6: B.FR_STAGE_HALO}}
 
 
 @pytest.mark.parametrize("prec", [B.FR_F64, B.FR_F32])
