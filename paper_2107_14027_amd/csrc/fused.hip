@@ -354,6 +354,15 @@ __device__ __forceinline__ int opaque_tid()
     return t;
 }
 
+// Zero, hidden from the optimiser (a uniform value): an offset that keeps
+// loads of loop-invariant data inside a loop.
+__device__ __forceinline__ int opaque_zero()
+{
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return z;
+}
+
 // Neighbour element of every (element, face) of a batch, into an LDS table of
 // 6 nel entries filled by the NT threads of the workgroup.
 template <int NT>
@@ -1746,7 +1755,7 @@ constexpr int line_stage_chunk()
     return FR_LSTG_CHUNK;
 #else
     constexpr int d[PMAX + 1] = {0, 8, 8, 8, 8, 8, 8};
-    constexpr int f[PMAX + 1] = {0, 8, 8, 4, 8, 8, 8};
+    constexpr int f[PMAX + 1] = {0, 8, 8, 4, 4, 8, 8};
     return sizeof(T) == 8 ? d[P] : f[P];
 #endif
 }
@@ -1755,7 +1764,7 @@ template <int P, typename T, bool HALO, bool STG>
 __global__ void __launch_bounds__((LinesShape<P, T>::NT))
     __attribute__((amdgpu_waves_per_eu(STG ? 1 : LinesShape<P, T>::WPE, 8)))
     k_lines(const T *__restrict__ U, const T *__restrict__ TR, T *__restrict__ R,
-            const T *__restrict__ ops, Consts<T> c, int nx, int ny, int nz, StageSpec sp)
+            const T *__restrict__ ops0, Consts<T> c, int nx, int ny, int nz, StageSpec sp)
 {
     const int ne = nx * ny * nz;
     constexpr int M = P + 1, NS = M * M * M, NF = M * M;
@@ -1766,8 +1775,8 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
     using OL = OpsLayout<M>;
     constexpr int EP = LL::EP, RAW = LL::raw;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *sop = reinterpret_cast<T *>(smem_raw);  // operators
-    T *sU = sop + LL::OPS;                     // [E][EP] state tile
+    T *sop0 = reinterpret_cast<T *>(smem_raw);  // operators
+    T *sU = sop0 + LL::OPS;                      // [E][EP] state tile
     // P and momentum parts per direction, [3][E][4][NS] (XR = 1: the x
     // direction's stay in its lanes' registers and only y and z are here;
     // XR = 2: none here)
@@ -1777,12 +1786,15 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
     const int t = (wave - d * W) * 64 + (threadIdx.x & 63);
     const int el = t / NF, L = t - el * NF;
     const int64_t nb = ((int64_t)ne + E - 1) / E;
-    if (threadIdx.x < OL::size) sop[threadIdx.x] = ops[threadIdx.x];
+    if (threadIdx.x < OL::size) sop0[threadIdx.x] = ops0[threadIdx.x];
     // with STG: sum of (k*_V)^2 over this workgroup's stage updates
     double ss = 0.0;
-    auto run_batch = [&](int64_t bt) {
-    const int64_t e0 = bt * E;
-    const int nel = (int)min((int64_t)E, (int64_t)ne - e0);
+    auto run_batch = [&](int64_t e0, int nel) {
+    // the operator blocks through an offset the compiler cannot see, so that
+    // a loop over batches reloads them instead of holding them in registers
+    const int oz = opaque_zero();
+    const T *sop = sop0 + oz;
+    const T *ops = ops0 + oz;
     const bool act = el < nel;
     const int64_t e = e0 + el;
     // the neighbours' traces on this lane's line, requested before the state:
@@ -2017,15 +2029,19 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
             (unsigned)nel * RAW, e0, ss);
     }
     };
+    auto batch_at = [&](int64_t bt) {
+        const int64_t e0 = bt * E;
+        run_batch(e0, (int)min((int64_t)E, (int64_t)ne - e0));
+    };
     if constexpr (STG) {
         // the stage epilogue's grid is bounded by its partial sums, so a
         // workgroup may take several batches
         for (int64_t bt = blockIdx.x; bt < nb; bt += gridDim.x) {
             if (bt != (int64_t)blockIdx.x) __syncthreads();  // the tile is free again
-            run_batch(bt);
+            batch_at(bt);
         }
     } else {
-        run_batch(blockIdx.x);
+        batch_at(blockIdx.x);
     }
     if constexpr (STG) {
         if (sp.partial) {

@@ -167,6 +167,36 @@ __global__ void __launch_bounds__(256) k_u_negsrc(const T *__restrict__ Dv, cons
     R[t] = r;
 }
 
+// Stage 6 in 16-byte vectors, where a vector never straddles two variables
+// (m^3 a multiple of the vector width) and the arrays are aligned: the same
+// arithmetic, U read only for the auxiliary variables.
+template <int P, typename T>
+struct NegsrcVec {
+    static constexpr int NS = (P + 1) * (P + 1) * (P + 1), VW = 16 / (int)sizeof(T);
+    static constexpr bool value = NS % VW == 0;
+};
+
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_u_negsrc_vec(const T *__restrict__ Dv, const T *__restrict__ U,
+                                                      T *__restrict__ R, Consts<T> c, int64_t ne)
+{
+    constexpr int M = P + 1, NS = M * M * M, VW = NegsrcVec<P, T>::VW;
+    using V = typename V16<T>::type;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * NV * NS / VW) return;
+    const int v = (int)((t * VW / NS) % NV);
+    const V dv = __builtin_nontemporal_load(reinterpret_cast<const V *>(Dv) + t);
+    V r;
+#pragma unroll
+    for (int w = 0; w < VW; ++w) r[w] = -c.inv_det * dv[w];
+    if (v >= 4) {
+        const V u = __builtin_nontemporal_load(reinterpret_cast<const V *>(U) + t);
+#pragma unroll
+        for (int w = 0; w < VW; ++w) r[w] -= c.invT * u[w];
+    }
+    __builtin_nontemporal_store(r, reinterpret_cast<V *>(R) + t);
+}
+
 // Stage 1 as line tasks: a workgroup copies a batch of E consecutive elements
 // into LDS (the line form's tile), a lane owns one line of one direction d of
 // one element and projects all 13 variables to both of its ends.
@@ -393,6 +423,56 @@ __global__ void __launch_bounds__((CommonShape<P, T>::NT))
     block_copy_out<T, NT>(sO, FI + ((int64_t)d * ne + e0) * BL, nel * BL);
 }
 
+// Stage 4 without LDS: one thread per (direction d, element, face point) reads
+// the 13 values of both sides straight from the face blocks (for consecutive
+// threads, runs of m^2 consecutive values per variable) and writes its 13
+// common-flux values; many small independent threads keep the loads in flight.
+template <int P, typename T>
+__global__ void __launch_bounds__(256)
+    k_u_common_direct(const T *__restrict__ Uf, T *__restrict__ FI, Consts<T> c, int nx, int ny, int nz)
+{
+    constexpr int M = P + 1, NF = M * M, BL = NV * NF;
+    const int64_t ne = (int64_t)nx * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * ne * NF) return;
+    const int d = (int)(t / (ne * NF));
+    const int64_t r = t - (int64_t)d * ne * NF;
+    const int64_t e = r / NF;
+    const int fp = (int)(r - e * NF);
+    const int64_t nb = neighbour(e, 2 * d + 1, nx, ny, nz);
+    const T *Lp = Uf + ((int64_t)(2 * d + 1) * ne + e) * BL + fp;
+    const T *Rp = Uf + ((int64_t)(2 * d) * ne + nb) * BL + fp;
+    T L[NV], Rr[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        L[v] = __builtin_nontemporal_load(Lp + v * NF);
+        Rr[v] = __builtin_nontemporal_load(Rp + v * NF);
+    }
+    T nh[3] = {c.nhat[d][0], c.nhat[d][1], c.nhat[d][2]};
+    T fl[NV], fr[NV];
+    flux_dot<T>(L, nh, c.zeta, c.nu, c.invT, fl);
+    flux_dot<T>(Rr, nh, c.zeta, c.nu, c.invT, fr);
+    T vnl = L[1] * nh[0] + L[2] * nh[1] + L[3] * nh[2];
+    T vnr = Rr[1] * nh[0] + Rr[2] * nh[1] + Rr[3] * nh[2];
+    const T al = fabs(vnl) + sqrt(vnl * vnl + c.zeta);
+    const T ar = fabs(vnr) + sqrt(vnr * vnr + c.zeta);
+    const T lam = al > ar ? al : ar;
+    T *Op = FI + ((int64_t)d * ne + e) * BL + fp;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T f = T(0.5) * (fl[v] + fr[v]);
+        if (v < 4) f -= T(0.5) * lam * (Rr[v] - L[v]);
+        __builtin_nontemporal_store(c.nmag[d] * f, Op + v * NF);
+    }
+}
+
+// Which stage-4 kernel runs: without LDS from p = FR_UCOMMON_DIRECT_PMIN up
+// (measured: the staged form wins at p = 1, where a face block's runs are only
+// four values long).
+#ifndef FR_UCOMMON_DIRECT_PMIN
+#define FR_UCOMMON_DIRECT_PMIN 2
+#endif
+
 // Stage 5 with the common-flux blocks staged in LDS: a workgroup takes E
 // consecutive elements, copies for each direction their own blocks (+d faces)
 // and their -d neighbours' blocks, and corrects every point's 13 values.
@@ -495,8 +575,12 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
     {
         ProfScope ps(pl, FR_K_U_COMMON, s);
         using CS = CommonShape<P, T>;
-        hipLaunchKernelGGL((k_u_common_lds<P, T>), dim3((unsigned)(3 * ((ne + CS::E - 1) / CS::E))),
-                           dim3(CS::NT), 0, s, Uf, FI, c, pl->nx, pl->ny, pl->nz);
+        if (P >= FR_UCOMMON_DIRECT_PMIN)
+            hipLaunchKernelGGL((k_u_common_direct<P, T>), g(3 * ne * (P + 1) * (P + 1)), dim3(nt), 0, s,
+                               Uf, FI, c, pl->nx, pl->ny, pl->nz);
+        else
+            hipLaunchKernelGGL((k_u_common_lds<P, T>), dim3((unsigned)(3 * ((ne + CS::E - 1) / CS::E))),
+                               dim3(CS::NT), 0, s, Uf, FI, c, pl->nx, pl->ny, pl->nz);
     }
     {
         ProfScope ps(pl, FR_K_U_CORRECT, s);
@@ -507,7 +591,11 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
     }
     {
         ProfScope ps(pl, FR_K_U_NEGSRC, s);
-        hipLaunchKernelGGL((k_u_negsrc<P, T>), g(ne * NV * NS), dim3(nt), 0, s, Dv, U, R, c, ne);
+        if (NegsrcVec<P, T>::value && ((((uintptr_t)Dv | (uintptr_t)U | (uintptr_t)R) & 15) == 0))
+            hipLaunchKernelGGL((k_u_negsrc_vec<P, T>), g(ne * NV * NS / NegsrcVec<P, T>::VW), dim3(nt), 0,
+                               s, Dv, U, R, c, ne);
+        else
+            hipLaunchKernelGGL((k_u_negsrc<P, T>), g(ne * NV * NS), dim3(nt), 0, s, Dv, U, R, c, ne);
     }
     return check_hip(hipGetLastError(), "unfused launch");
 }
