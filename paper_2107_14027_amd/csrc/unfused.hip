@@ -312,19 +312,22 @@ template <int P, typename T>
 struct DivShape {
     static constexpr int M = P + 1, NS = M * M * M;
     static constexpr int E = NS >= 256 ? 1 : 256 / NS;
-    static constexpr int NT = 256;
+    // one point per thread (p = 6: 343 points on 384 threads)
+    static constexpr int NT = NS > 256 ? 64 * ((NS + 63) / 64) : 256;
     static constexpr int KP = (E * NS + NT - 1) / NT;   // points per thread
 };
 
 template <int P, typename T>
-__global__ void __launch_bounds__(256)
-    k_u_div_lds(const T *__restrict__ Fs, T *__restrict__ Dv, const T *__restrict__ ops, int64_t ne)
+__global__ void __launch_bounds__((DivShape<P, T>::NT))
+    k_u_div_lds(const T *__restrict__ Fs, T *__restrict__ Dv, const T *__restrict__ ops0, int64_t ne)
 {
     constexpr int M = P + 1, NS = M * M * M;
     constexpr int E = DivShape<P, T>::E, NT = DivShape<P, T>::NT, KP = DivShape<P, T>::KP;
     using OL = OpsLayout<M>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sF = reinterpret_cast<T *>(smem_raw);   // [E][13][NS] of one direction
+    __shared__ T ops[M * M];                   // the operator Dt
+    if (threadIdx.x < M * M) ops[threadIdx.x] = ops0[OL::Dt + threadIdx.x];
     const int64_t e0 = (int64_t)blockIdx.x * E;
     const int nel = (int)min((int64_t)E, ne - e0);
     T acc[KP][NV];
@@ -349,7 +352,7 @@ __global__ void __launch_bounds__(256)
             for (int v = 0; v < NV; ++v)
 #pragma unroll
                 for (int l = 0; l < M; ++l)
-                    acc[u][v] = fma(ops[OL::Dt + id * M + l], Fe[v * NS + l * str], acc[u][v]);
+                    acc[u][v] = fma(ops[id * M + l], Fe[v * NS + l * str], acc[u][v]);
         }
     }
 #pragma unroll
