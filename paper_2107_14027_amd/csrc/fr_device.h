@@ -169,6 +169,20 @@ struct LinesLds {
     }
 };
 
+// Whether the line form's tile loads are marked nontemporal.  They are not:
+// the halo form reads the neighbours' lines of the same state again, and
+// plain loads leave the state in the caches for them (measured 2-9% faster
+// at every order than nontemporal loads).
+#ifndef FR_TILE_NT
+#define FR_TILE_NT 0
+#endif
+template <typename V>
+__device__ __forceinline__ V tile_ld(const V *p)
+{
+    if constexpr (FR_TILE_NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 // A batch's contiguous state block (nel elements from src) into the line
 // form's LDS tile (element pitch EP), in 16-byte vectors where the element
 // size allows.
@@ -185,14 +199,14 @@ __device__ __forceinline__ void tile_load(const T *__restrict__ src, T *__restri
 #pragma unroll 4
         for (int k = threadIdx.x; k < nch; k += NT) {
             const int ek = k / CPE, o = k - ek * CPE;
-            reinterpret_cast<V *>(sU + ek * EP)[o] = __builtin_nontemporal_load(sv + k);
+            reinterpret_cast<V *>(sU + ek * EP)[o] = tile_ld(sv + k);
         }
     } else {
         const int nv = nel * RAW;
 #pragma unroll 4
         for (int k = threadIdx.x; k < nv; k += NT) {
             const int ek = k / RAW, o = k - ek * RAW;
-            sU[ek * EP + o] = __builtin_nontemporal_load(src + k);
+            sU[ek * EP + o] = tile_ld(src + k);
         }
     }
 }

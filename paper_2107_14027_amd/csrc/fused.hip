@@ -1323,7 +1323,7 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 // for (at least): 3 at p = 6 in double precision (168 VGPRs with a few values
 // spilled, against 171 VGPRs and two waves without the hint: 1.63 against
 // 2.13 ms per halo residual on 40^3 hexes); the stage-epilogue kernels take no
-// hint.
+// hint (three waves spill there and measured 15-58% slower in double precision).
 #ifndef FR_LV_DEFAULT
 #define FR_LV_DEFAULT 1
 #endif
