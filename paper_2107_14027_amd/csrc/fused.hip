@@ -522,6 +522,23 @@ constexpr int stage_chunk()
 #endif
 }
 
+// Global loads and stores of the stage update: streams read or written once
+// per stage, marked nontemporal (NTS) where that measured faster: always in
+// the halo form's epilogue (2-7%), in the point form's except at p = 4 (where
+// it measured 5-16% slower).
+template <bool NTS, typename X>
+__device__ __forceinline__ X stg_ld(const X *p)
+{
+    if constexpr (NTS) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NTS, typename X>
+__device__ __forceinline__ void stg_st(X *p, X v)
+{
+    if constexpr (NTS) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // The RK stage update of one batch whose residual (working precision) is in
 // LDS: tile(t) is the t-th of the batch's cnt values in global order
 // ([element][variable][point], from element e0).  The double arithmetic of the
@@ -531,7 +548,7 @@ constexpr int stage_chunk()
 // before the first is used, so that the loads of a wave overlap, with a
 // bounded register cost.  With tr_out the produced state replaces the
 // residual in the tile; ss accumulates the squared velocity pseudo-residual.
-template <int J, int C, int NS, typename T, typename Tile>
+template <int J, int C, int NS, typename T, bool NTS, typename Tile>
 __device__ __forceinline__ void stage_update_batch(const StageSpec &sp, Tile &&tile, unsigned tid,
                                                    unsigned nt, unsigned cnt, int64_t e0, double &ss)
 {
@@ -544,14 +561,14 @@ __device__ __forceinline__ void stage_update_batch(const StageSpec &sp, Tile &&t
             const unsigned t = tid + (j0 + j) * nt;
             if (t < cnt) {
                 const int64_t gi = g0 + t;
-                if (!sp.last) ou[j] = sp.U[gi];
-                if (!sp.first || sp.last) oa[j] = sp.acc[gi];
+                if (!sp.last) ou[j] = stg_ld<NTS>(sp.U + gi);
+                if (!sp.first || sp.last) oa[j] = stg_ld<NTS>(sp.acc + gi);
                 if (sp.B) {
                     const unsigned r = t / NS, q = t - r * NS;
                     const unsigned el = r / NV, v = r - el * NV;
                     if (v >= 1 && v <= 3) {
-                        os[j] = sp.s_in ? sp.s_in[gi] : sp.U[gi];
-                        ob[j] = sp.B[((int64_t)(e0 + el) * 3 + (v - 1)) * NS + q];
+                        os[j] = sp.s_in ? stg_ld<NTS>(sp.s_in + gi) : stg_ld<NTS>(sp.U + gi);
+                        ob[j] = stg_ld<NTS>(sp.B + ((int64_t)(e0 + el) * 3 + (v - 1)) * NS + q);
                     }
                 }
             }
@@ -569,14 +586,14 @@ __device__ __forceinline__ void stage_update_batch(const StageSpec &sp, Tile &&t
                 }
                 if (sp.last) {
                     const double un = fma(sp.b, kv, oa[j]);
-                    sp.U[gi] = un;
-                    if (sp.s_out) static_cast<T *>(sp.s_out)[gi] = (T)un;
+                    stg_st<NTS>(sp.U + gi, un);
+                    if (sp.s_out) stg_st<NTS>(static_cast<T *>(sp.s_out) + gi, (T)un);
                     if (sp.tr_out) tile(t) = (T)un;
                 } else {
-                    sp.acc[gi] = fma(sp.b, kv, sp.first ? ou[j] : oa[j]);
+                    stg_st<NTS>(sp.acc + gi, fma(sp.b, kv, sp.first ? ou[j] : oa[j]));
                     const double sn = fma(sp.cnext, kv, ou[j]);
-                    if (sp.s_out64) sp.s_out64[gi] = sn;
-                    static_cast<T *>(sp.s_out)[gi] = (T)sn;
+                    if (sp.s_out64) stg_st<NTS>(sp.s_out64 + gi, sn);
+                    stg_st<NTS>(static_cast<T *>(sp.s_out) + gi, (T)sn);
                     if (sp.tr_out) tile(t) = (T)sn;
                 }
             }
@@ -1061,7 +1078,7 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
             constexpr int J = (EMAX * NV * NS + NT - 1) / NT;
             constexpr int C = stage_chunk<P, T>() < J ? stage_chunk<P, T>() : J;
             __syncthreads();
-            stage_update_batch<J, C, NS, T>(sp, [&](unsigned t) -> T & { return sU[t]; }, tid, NT,
+            stage_update_batch<J, C, NS, T, P != 4>(sp, [&](unsigned t) -> T & { return sU[t]; }, tid, NT,
                                            (unsigned)nel * NV * NS, e0, ss);
             if (sp.tr_out) {
                 // ---- stage 1 of the next residual: the produced state's face
@@ -2024,7 +2041,7 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
         constexpr int J = (E * RAW + NT - 1) / NT;
         constexpr int C = line_stage_chunk<P, T>() < J ? line_stage_chunk<P, T>() : J;
         __syncthreads();
-        stage_update_batch<J, C, NS, T>(
+        stage_update_batch<J, C, NS, T, true>(
             sp, [&](unsigned q) -> T & { return sU[(q / RAW) * EP + q % RAW]; }, threadIdx.x, NT,
             (unsigned)nel * RAW, e0, ss);
     }
