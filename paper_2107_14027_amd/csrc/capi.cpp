@@ -138,7 +138,7 @@ int pseudo_iterate(fr_plan *pl, double *U, const double *B, double a, const doub
     // BDF constant's slot in the plan's dual scratch
     if (!f64)
         if (int rc = ensure_scratch(pl->dual, (nB + (size_t)n) * sizeof(double))) return rc;
-    const int cap = std::max(stage_blocks(n), MAX_PARTIALS);
+    const int cap = std::max(std::max(stage_blocks(n), MAX_PARTIALS), stage_partials(pl));
     if (int rc = ensure_scratch(pl->norm, (size_t)(cap + 1) * sizeof(double))) return rc;
     if (!pl->norm_host &&
         check_hip(hipHostMalloc((void **)&pl->norm_host, sizeof(double), hipHostMallocDefault),

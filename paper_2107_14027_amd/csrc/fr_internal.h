@@ -184,6 +184,9 @@ int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *
 // How fr_rk_step / fr_dual_step apply the RK stage update for this plan's
 // current settings (FR_STAGE_SEPARATE, FR_STAGE_POINT or FR_STAGE_HALO).
 int stage_path(const fr_plan *pl);
+// Partial norm sums the stage-epilogue launch of this plan writes at most (the
+// halo form's: one per batch; 0 for the other paths).
+int stage_partials(const fr_plan *pl);
 // kernel form fr_residual runs on this plan (FR_FORM_POINT or FR_FORM_LINES;
 // 0 for the unfused and matrix-core variants)
 int residual_form(const fr_plan *pl);

@@ -1394,13 +1394,13 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #define FR_SA2_D FR_STAGE_HALO
 #endif
 #ifndef FR_SA3_D
-#define FR_SA3_D FR_STAGE_POINT
+#define FR_SA3_D FR_STAGE_HALO
 #endif
 #ifndef FR_SA4_D
 #define FR_SA4_D FR_STAGE_POINT
 #endif
 #ifndef FR_SA5_D
-#define FR_SA5_D FR_STAGE_POINT
+#define FR_SA5_D FR_STAGE_HALO
 #endif
 #ifndef FR_SA6_D
 #define FR_SA6_D FR_STAGE_HALO
@@ -1415,7 +1415,7 @@ __global__ void __launch_bounds__((Shape<P, T>::NT))
 #define FR_SA3_F FR_STAGE_HALO
 #endif
 #ifndef FR_SA4_F
-#define FR_SA4_F FR_STAGE_POINT
+#define FR_SA4_F FR_STAGE_HALO
 #endif
 #ifndef FR_SA5_F
 #define FR_SA5_F FR_STAGE_POINT
@@ -1761,6 +1761,63 @@ __device__ __forceinline__ void nbr_trace(const T *__restrict__ Un, int L, const
     }
 }
 
+// Whether the halo form's stage-epilogue kernel loops over batches with a grid
+// bounded by the partial sums or takes one batch per workgroup.  The loop holds 20-50 more VGPRs (a wave of occupancy at p = 2-5)
+// but saves workgroup launches where batches are small; measured per order
+// and precision on the dual pseudo-step.
+#ifndef FR_SL1_D
+#define FR_SL1_D 1
+#endif
+#ifndef FR_SL2_D
+#define FR_SL2_D 0
+#endif
+#ifndef FR_SL3_D
+#define FR_SL3_D 0
+#endif
+#ifndef FR_SL4_D
+#define FR_SL4_D 0
+#endif
+#ifndef FR_SL5_D
+#define FR_SL5_D 0
+#endif
+#ifndef FR_SL6_D
+#define FR_SL6_D 1
+#endif
+#ifndef FR_SL1_F
+#define FR_SL1_F 1
+#endif
+#ifndef FR_SL2_F
+#define FR_SL2_F 0
+#endif
+#ifndef FR_SL3_F
+#define FR_SL3_F 0
+#endif
+#ifndef FR_SL4_F
+#define FR_SL4_F 0
+#endif
+#ifndef FR_SL5_F
+#define FR_SL5_F 1
+#endif
+#ifndef FR_SL6_F
+#define FR_SL6_F 1
+#endif
+template <int P, typename T> struct StageLoop;
+#define FR_SLOOP(PP, TT, S) \
+    template <> struct StageLoop<PP, TT> { static constexpr bool value = FR_SL##PP##_##S != 0; };
+FR_SLOOP(1, double, D)
+FR_SLOOP(2, double, D)
+FR_SLOOP(3, double, D)
+FR_SLOOP(4, double, D)
+FR_SLOOP(5, double, D)
+FR_SLOOP(6, double, D)
+FR_SLOOP(1, float, F)
+FR_SLOOP(2, float, F)
+FR_SLOOP(3, float, F)
+FR_SLOOP(4, float, F)
+FR_SLOOP(5, float, F)
+FR_SLOOP(6, float, F)
+#undef FR_SLOOP
+
 // Values per thread whose global operands the halo form's stage epilogue
 // requests at once, per order and precision (as stage_chunk for the point
 // form; measured: 16 spills, 1 leaves too few loads in flight).
@@ -1802,7 +1859,7 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
     const int d = wave / W;
     const int t = (wave - d * W) * 64 + (threadIdx.x & 63);
     const int el = t / NF, L = t - el * NF;
-    const int64_t nb = ((int64_t)ne + E - 1) / E;
+    const int64_t nbt = ((int64_t)ne + E - 1) / E;
     if (threadIdx.x < OL::size) sop0[threadIdx.x] = ops0[threadIdx.x];
     // with STG: sum of (k*_V)^2 over this workgroup's stage updates
     double ss = 0.0;
@@ -2050,14 +2107,15 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
         const int64_t e0 = bt * E;
         run_batch(e0, (int)min((int64_t)E, (int64_t)ne - e0));
     };
-    if constexpr (STG) {
-        // the stage epilogue's grid is bounded by its partial sums, so a
-        // workgroup may take several batches
-        for (int64_t bt = blockIdx.x; bt < nb; bt += gridDim.x) {
+    if constexpr (STG && StageLoop<P, T>::value) {
+        // the stage epilogue's grid bounded by its partial sums: a workgroup
+        // may take several batches
+        for (int64_t bt = blockIdx.x; bt < nbt; bt += gridDim.x) {
             if (bt != (int64_t)blockIdx.x) __syncthreads();  // the tile is free again
             batch_at(bt);
         }
     } else {
+        // one batch per workgroup (the partial sums take one slot per batch)
         batch_at(blockIdx.x);
     }
     if constexpr (STG) {
@@ -2415,8 +2473,10 @@ int fused_impl(fr_plan *pl, const T *U, T *R, const StageSpec *sp, int *nparts, 
         ProfScope ps(prof ? pl : nullptr, FR_K_FUSED, s);
         if constexpr (DIAG) {
             if (sp) {
-                // one partial norm sum per workgroup
-                const unsigned g = (unsigned)std::min<int64_t>(nb, MAX_PARTIALS);
+                // one partial norm sum per workgroup (the caller sizes the
+                // partial sums by stage_partials)
+                const unsigned g =
+                    (unsigned)(StageLoop<P, T>::value ? std::min<int64_t>(nb, MAX_PARTIALS) : nb);
                 if (nparts) *nparts = (int)g;
                 hipLaunchKernelGGL((k_lines<P, T, true, true>), dim3(g), dim3(LNT), lds_li, s, U,
                                    (const T *)nullptr, (T *)nullptr, ops, c, pl->nx, pl->ny, pl->nz,
@@ -2630,6 +2690,28 @@ int stage_path(const fr_plan *pl)
         case 6: a = pick(Dir<6>{}); break;
     }
     return a == FR_STAGE_POINT ? point : a;
+}
+
+int stage_partials(const fr_plan *pl)
+{
+    if (stage_path(pl) != FR_STAGE_HALO) return 0;
+    const bool f64 = pl->precision == FR_F64;
+    auto pick = [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        const int E = f64 ? LinesShape<P, double>::E : LinesShape<P, float>::E;
+        const bool loop = f64 ? StageLoop<P, double>::value : StageLoop<P, float>::value;
+        const int64_t nb = (pl->ne + E - 1) / E;
+        return (int)(loop ? std::min<int64_t>(nb, MAX_PARTIALS) : nb);
+    };
+    switch (pl->p) {
+        case 1: return pick(Dir<1>{});
+        case 2: return pick(Dir<2>{});
+        case 3: return pick(Dir<3>{});
+        case 4: return pick(Dir<4>{});
+        case 5: return pick(Dir<5>{});
+        case 6: return pick(Dir<6>{});
+    }
+    return 0;
 }
 
 int launch_residual_stage(fr_plan *pl, const void *U, const StageSpec &sp, int *nparts,

@@ -123,10 +123,10 @@ def test_halo_epilogue_workgroups_take_several_batches(prec):
 
 
 # FR_FORM_AUTO's stage path per order (diagonal Jacobian), as documented
-AUTO_STAGE = {B.FR_F64: {1: B.FR_STAGE_HALO, 2: B.FR_STAGE_HALO, 3: B.FR_STAGE_POINT,
-                         4: B.FR_STAGE_POINT, 5: B.FR_STAGE_POINT, 6: B.FR_STAGE_HALO},
+AUTO_STAGE = {B.FR_F64: {1: B.FR_STAGE_HALO, 2: B.FR_STAGE_HALO, 3: B.FR_STAGE_HALO,
+                         4: B.FR_STAGE_POINT, 5: B.FR_STAGE_HALO, 6: B.FR_STAGE_HALO},
               B.FR_F32: {1: B.FR_STAGE_HALO, 2: B.FR_STAGE_HALO, 3: B.FR_STAGE_HALO,
-                         4: B.FR_STAGE_POINT, 5: B.FR_STAGE_POINT, 6: B.FR_STAGE_HALO}}
+                         4: B.FR_STAGE_HALO, 5: B.FR_STAGE_POINT, 6: B.FR_STAGE_HALO}}
 
 
 @pytest.mark.parametrize("prec", [B.FR_F64, B.FR_F32])
