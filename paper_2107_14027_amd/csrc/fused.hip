@@ -1762,9 +1762,10 @@ __device__ __forceinline__ void nbr_trace(const T *__restrict__ Un, int L, const
 }
 
 // Whether the halo form's stage-epilogue kernel loops over batches with a grid
-// bounded by the partial sums or takes one batch per workgroup.  The loop holds 20-50 more VGPRs (a wave of occupancy at p = 2-5)
-// but saves workgroup launches where batches are small; measured per order
-// and precision on the dual pseudo-step.
+// bounded by the partial sums or takes one batch per workgroup.  The loop
+// holds 20-50 more VGPRs (a wave of occupancy at p = 2-5) but saves workgroup
+// launches where batches are small; measured per order and precision on the
+// dual pseudo-step.
 #ifndef FR_SL1_D
 #define FR_SL1_D 1
 #endif
@@ -1853,7 +1854,7 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
     T *sU = sop0 + LL::OPS;                      // [E][EP] state tile
     // P and momentum parts per direction, [3][E][4][NS] (XR = 1: the x
     // direction's stay in its lanes' registers and only y and z are here;
-    // XR = 2: none here)
+    // XR = 2, 3: none here)
     T *sC = sU + E * EP - (XR == 1 ? 4 * E * NS : 0);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int d = wave / W;
@@ -1864,244 +1865,244 @@ __global__ void __launch_bounds__((LinesShape<P, T>::NT))
     // with STG: sum of (k*_V)^2 over this workgroup's stage updates
     double ss = 0.0;
     auto run_batch = [&](int64_t e0, int nel) {
-    // the operator blocks through an offset the compiler cannot see, so that
-    // a loop over batches reloads them instead of holding them in registers
-    const int oz = opaque_zero();
-    const T *sop = sop0 + oz;
-    const T *ops = ops0 + oz;
-    const bool act = el < nel;
-    const int64_t e = e0 + el;
-    // the neighbours' traces on this lane's line, requested before the state:
-    // from the trace array, or with HALO from the neighbours' own states (from
-    // global memory for a neighbour outside the batch, from the tile after it
-    // is loaded otherwise)
-    T othm[NTR], othp[NTR];
-    int64_t nbm = 0, nbp = 0;
-    bool inm = false, inp = false;
-    if (act) {
-        if constexpr (HALO) {
-            nbm = neighbour(e, 2 * d, nx, ny, nz);
-            nbp = neighbour(e, 2 * d + 1, nx, ny, nz);
-            inm = nbm >= e0 && nbm < e0 + nel;
-            inp = nbp >= e0 && nbp < e0 + nel;
-            auto from_global = [&](auto dc) {
-                constexpr int DD = decltype(dc)::value;
-                if (!inm) nbr_trace<P, T, DD>(U + nbm * RAW, L, ops + OL::lp, othm);
-                if (!inp) nbr_trace<P, T, DD>(U + nbp * RAW, L, ops + OL::lm, othp);
-            };
-            if (d == 0) from_global(Dir<0>{});
-            else if (d == 1) from_global(Dir<1>{});
-            else from_global(Dir<2>{});
-        } else {
-            const T *tm = TR + ((int64_t)(2 * d) * ne + e) * TL::CHP + L;
-            const T *tp = TR + ((int64_t)(2 * d + 1) * ne + e) * TL::CHP + L;
-#pragma unroll
-            for (int cc = 0; cc < NTR; ++cc) {
-                othm[cc] = __builtin_nontemporal_load(tm + cc * NF);
-                othp[cc] = __builtin_nontemporal_load(tp + cc * NF);
-            }
-        }
-    }
-    // the batch's state block into LDS
-    tile_load<P, T, NT>(U + e0 * RAW, sU, nel);
-    __syncthreads();
-    if constexpr (HALO) {
-        if (act && (inm || inp)) {
-            auto from_tile = [&](auto dc) {
-                constexpr int DD = decltype(dc)::value;
-                if (inm) nbr_trace<P, T, DD>(sU + (nbm - e0) * EP, L, sop + OL::lp, othm);
-                if (inp) nbr_trace<P, T, DD>(sU + (nbp - e0) * EP, L, sop + OL::lm, othp);
-            };
-            if (d == 0) from_tile(Dir<0>{});
-            else if (d == 1) from_tile(Dir<1>{});
-            else from_tile(Dir<2>{});
-        }
-        // a neighbour's S_ad is replaced by its auxiliary residual in the line
-        // task; with several waves per direction that lane may be in another
-        // wave, so every wave finishes these reads first
-        if constexpr (W > 1) __syncthreads();
-    }
-    T ctb[4][M];
-    const T mid = -c.inv_det;
-    // the parts ctb[k0..k1) of this lane's line added over the tile's P and
-    // velocity values (x stores, y adds, z adds and scales by -1/det J)
-    auto add_lines = [&](auto dc, auto k0c, auto k1c) {
-        constexpr int DD = decltype(dc)::value;
-        constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
-        constexpr int STR = DD == 0 ? 1 : (DD == 1 ? M : M * M);
-        T *Ue = sU + el * EP + lt_base<P, T, DD>(L);
-#pragma unroll
-        for (int k = K0; k < K1; ++k) {
-            T o[M];
-            if constexpr (DD == 0) {
-#pragma unroll
-                for (int r = 0; r < M; ++r) o[r] = ctb[k][r];
+        // the operator blocks through an offset the compiler cannot see, so that
+        // a loop over batches reloads them instead of holding them in registers
+        const int oz = opaque_zero();
+        const T *sop = sop0 + oz;
+        const T *ops = ops0 + oz;
+        const bool act = el < nel;
+        const int64_t e = e0 + el;
+        // the neighbours' traces on this lane's line, requested before the state:
+        // from the trace array, or with HALO from the neighbours' own states (from
+        // global memory for a neighbour outside the batch, from the tile after it
+        // is loaded otherwise)
+        T othm[NTR], othp[NTR];
+        int64_t nbm = 0, nbp = 0;
+        bool inm = false, inp = false;
+        if (act) {
+            if constexpr (HALO) {
+                nbm = neighbour(e, 2 * d, nx, ny, nz);
+                nbp = neighbour(e, 2 * d + 1, nx, ny, nz);
+                inm = nbm >= e0 && nbm < e0 + nel;
+                inp = nbp >= e0 && nbp < e0 + nel;
+                auto from_global = [&](auto dc) {
+                    constexpr int DD = decltype(dc)::value;
+                    if (!inm) nbr_trace<P, T, DD>(U + nbm * RAW, L, ops + OL::lp, othm);
+                    if (!inp) nbr_trace<P, T, DD>(U + nbp * RAW, L, ops + OL::lm, othp);
+                };
+                if (d == 0) from_global(Dir<0>{});
+                else if (d == 1) from_global(Dir<1>{});
+                else from_global(Dir<2>{});
             } else {
-                line_load<M, STR>(Ue + k * NS, o);
+                const T *tm = TR + ((int64_t)(2 * d) * ne + e) * TL::CHP + L;
+                const T *tp = TR + ((int64_t)(2 * d + 1) * ne + e) * TL::CHP + L;
 #pragma unroll
-                for (int r = 0; r < M; ++r) o[r] = o[r] + ctb[k][r];
-                if constexpr (DD == 2) {
-#pragma unroll
-                    for (int r = 0; r < M; ++r) o[r] = mid * o[r];
+                for (int cc = 0; cc < NTR; ++cc) {
+                    othm[cc] = __builtin_nontemporal_load(tm + cc * NF);
+                    othp[cc] = __builtin_nontemporal_load(tp + cc * NF);
                 }
             }
-            line_put<M, STR>(Ue + k * NS, o);
         }
-    };
-    if constexpr (XR == 3) {
-        // the momentum parts are summed between the two halves of the line
-        // task, once every lane has read the tile's P and velocities, and the
-        // P parts after it: the fluxes' and the velocities' parts are never
-        // held in registers together
-        T FIm[NTR], FIp[NTR], X[3][M];
-        T *Ut = sU + el * EP;
-        if (act) {
-            auto ph1 = [&](auto dc) {
-                constexpr int DD = decltype(dc)::value;
-                lt_fluxes<P, T, DD, true>(Ut, sop, othm, othp, c, L, nullptr, ctb, FIm, FIp);
-                lt_velocities<P, T, DD>(Ut, L, X);
-            };
-            if (d == 0) ph1(Dir<0>{});
-            else if (d == 1) ph1(Dir<1>{});
-            else ph1(Dir<2>{});
-        }
+        // the batch's state block into LDS
+        tile_load<P, T, NT>(U + e0 * RAW, sU, nel);
         __syncthreads();
-        if (act && d == 0) add_lines(Dir<0>{}, Dir<1>{}, Dir<4>{});
-        __syncthreads();
-        if (act && d == 1) add_lines(Dir<1>{}, Dir<1>{}, Dir<4>{});
-        __syncthreads();
-        if (act && d == 2) add_lines(Dir<2>{}, Dir<1>{}, Dir<4>{});
-        if (act) {
-            if (d == 0) lt_derivs<P, T, 0, true>(Ut, sop, X, FIm, FIp, c, L, nullptr, ctb);
-            else if (d == 1) lt_derivs<P, T, 1, true>(Ut, sop, X, FIm, FIp, c, L, nullptr, ctb);
-            else lt_derivs<P, T, 2, true>(Ut, sop, X, FIm, FIp, c, L, nullptr, ctb);
-        }
-        if (act && d == 0) add_lines(Dir<0>{}, Dir<0>{}, Dir<1>{});
-        __syncthreads();
-        if (act && d == 1) add_lines(Dir<1>{}, Dir<0>{}, Dir<1>{});
-        __syncthreads();
-        if (act && d == 2) add_lines(Dir<2>{}, Dir<0>{}, Dir<1>{});
-    } else {
-        if (act) {
-            T *Ut = sU + el * EP;
-            T *sCd = sC + ((d * E + el) * 4) * NS;
-            if (d == 0) line_task<P, T, 0, (XR >= 1)>(Ut, sop, othm, othp, c, L, sCd, ctb);
-            else if (d == 1) line_task<P, T, 1, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
-            else line_task<P, T, 2, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
-        }
-        __syncthreads();
-    }
-    // R of the batch: P and momentum summed over the three directions in the
-    // order x, y, z and scaled by -1/det J, the auxiliary residuals from the
-    // tile.  Without STG it goes to R; with STG it stays in the tile for the
-    // stage update.
-    if constexpr (XR == 3) {
-        if constexpr (!STG) {
-            __syncthreads();
-            tile_store<P, T, NT>(sU, R + e0 * RAW, nel);
-        }
-    } else if constexpr (XR == 2) {
-        // summed over the tile's P and velocity values, one direction after
-        // the other
-        if (act && d == 0) add_lines(Dir<0>{}, Dir<0>{}, Dir<4>{});
-        __syncthreads();
-        if (act && d == 1) add_lines(Dir<1>{}, Dir<0>{}, Dir<4>{});
-        __syncthreads();
-        if (act && d == 2) add_lines(Dir<2>{}, Dir<0>{}, Dir<4>{});
-        if constexpr (!STG) {
-            __syncthreads();
-            tile_store<P, T, NT>(sU, R + e0 * RAW, nel);
-        }
-    } else if constexpr (XR == 1) {
-        // x lanes: their own parts plus those of y and z at the x-line's points
-        if (act && d == 0) {
-            const T *cy = sC + ((E + el) * 4) * NS + M * L;
-            const T *cz = sC + ((2 * E + el) * 4) * NS + M * L;
-            T *Re = R + e * (NV * NS) + M * L;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                T o[M];
-#pragma unroll
-                for (int r = 0; r < M; ++r) o[r] = mid * ((ctb[k][r] + cy[k * NS + r]) + cz[k * NS + r]);
-                if constexpr (STG) line_put<M, 1>(sU + el * EP + M * L + k * NS, o);
-                else line_store<M, 1>(Re + k * NS, o);
+        if constexpr (HALO) {
+            if (act && (inm || inp)) {
+                auto from_tile = [&](auto dc) {
+                    constexpr int DD = decltype(dc)::value;
+                    if (inm) nbr_trace<P, T, DD>(sU + (nbm - e0) * EP, L, sop + OL::lp, othm);
+                    if (inp) nbr_trace<P, T, DD>(sU + (nbp - e0) * EP, L, sop + OL::lm, othp);
+                };
+                if (d == 0) from_tile(Dir<0>{});
+                else if (d == 1) from_tile(Dir<1>{});
+                else from_tile(Dir<2>{});
             }
+            // a neighbour's S_ad is replaced by its auxiliary residual in the line
+            // task; with several waves per direction that lane may be in another
+            // wave, so every wave finishes these reads first
+            if constexpr (W > 1) __syncthreads();
         }
-        if constexpr (!STG) {
-            // every thread: the auxiliary residuals from the tile
+        T ctb[4][M];
+        const T mid = -c.inv_det;
+        // the parts ctb[k0..k1) of this lane's line added over the tile's P and
+        // velocity values (x stores, y adds, z adds and scales by -1/det J)
+        auto add_lines = [&](auto dc, auto k0c, auto k1c) {
+            constexpr int DD = decltype(dc)::value;
+            constexpr int K0 = decltype(k0c)::value, K1 = decltype(k1c)::value;
+            constexpr int STR = DD == 0 ? 1 : (DD == 1 ? M : M * M);
+            T *Ue = sU + el * EP + lt_base<P, T, DD>(L);
+#pragma unroll
+            for (int k = K0; k < K1; ++k) {
+                T o[M];
+                if constexpr (DD == 0) {
+#pragma unroll
+                    for (int r = 0; r < M; ++r) o[r] = ctb[k][r];
+                } else {
+                    line_load<M, STR>(Ue + k * NS, o);
+#pragma unroll
+                    for (int r = 0; r < M; ++r) o[r] = o[r] + ctb[k][r];
+                    if constexpr (DD == 2) {
+#pragma unroll
+                        for (int r = 0; r < M; ++r) o[r] = mid * o[r];
+                    }
+                }
+                line_put<M, STR>(Ue + k * NS, o);
+            }
+        };
+        if constexpr (XR == 3) {
+            // the momentum parts are summed between the two halves of the line
+            // task, once every lane has read the tile's P and velocities, and the
+            // P parts after it: the fluxes' and the velocities' parts are never
+            // held in registers together
+            T FIm[NTR], FIp[NTR], X[3][M];
+            T *Ut = sU + el * EP;
+            if (act) {
+                auto ph1 = [&](auto dc) {
+                    constexpr int DD = decltype(dc)::value;
+                    lt_fluxes<P, T, DD, true>(Ut, sop, othm, othp, c, L, nullptr, ctb, FIm, FIp);
+                    lt_velocities<P, T, DD>(Ut, L, X);
+                };
+                if (d == 0) ph1(Dir<0>{});
+                else if (d == 1) ph1(Dir<1>{});
+                else ph1(Dir<2>{});
+            }
+            __syncthreads();
+            if (act && d == 0) add_lines(Dir<0>{}, Dir<1>{}, Dir<4>{});
+            __syncthreads();
+            if (act && d == 1) add_lines(Dir<1>{}, Dir<1>{}, Dir<4>{});
+            __syncthreads();
+            if (act && d == 2) add_lines(Dir<2>{}, Dir<1>{}, Dir<4>{});
+            if (act) {
+                if (d == 0) lt_derivs<P, T, 0, true>(Ut, sop, X, FIm, FIp, c, L, nullptr, ctb);
+                else if (d == 1) lt_derivs<P, T, 1, true>(Ut, sop, X, FIm, FIp, c, L, nullptr, ctb);
+                else lt_derivs<P, T, 2, true>(Ut, sop, X, FIm, FIp, c, L, nullptr, ctb);
+            }
+            if (act && d == 0) add_lines(Dir<0>{}, Dir<0>{}, Dir<1>{});
+            __syncthreads();
+            if (act && d == 1) add_lines(Dir<1>{}, Dir<0>{}, Dir<1>{});
+            __syncthreads();
+            if (act && d == 2) add_lines(Dir<2>{}, Dir<0>{}, Dir<1>{});
+        } else {
+            if (act) {
+                T *Ut = sU + el * EP;
+                T *sCd = sC + ((d * E + el) * 4) * NS;
+                if (d == 0) line_task<P, T, 0, (XR >= 1)>(Ut, sop, othm, othp, c, L, sCd, ctb);
+                else if (d == 1) line_task<P, T, 1, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
+                else line_task<P, T, 2, (XR == 2)>(Ut, sop, othm, othp, c, L, sCd, ctb);
+            }
+            __syncthreads();
+        }
+        // R of the batch: P and momentum summed over the three directions in the
+        // order x, y, z and scaled by -1/det J, the auxiliary residuals from the
+        // tile.  Without STG it goes to R; with STG it stays in the tile for the
+        // stage update.
+        if constexpr (XR == 3) {
+            if constexpr (!STG) {
+                __syncthreads();
+                tile_store<P, T, NT>(sU, R + e0 * RAW, nel);
+            }
+        } else if constexpr (XR == 2) {
+            // summed over the tile's P and velocity values, one direction after
+            // the other
+            if (act && d == 0) add_lines(Dir<0>{}, Dir<0>{}, Dir<4>{});
+            __syncthreads();
+            if (act && d == 1) add_lines(Dir<1>{}, Dir<0>{}, Dir<4>{});
+            __syncthreads();
+            if (act && d == 2) add_lines(Dir<2>{}, Dir<0>{}, Dir<4>{});
+            if constexpr (!STG) {
+                __syncthreads();
+                tile_store<P, T, NT>(sU, R + e0 * RAW, nel);
+            }
+        } else if constexpr (XR == 1) {
+            // x lanes: their own parts plus those of y and z at the x-line's points
+            if (act && d == 0) {
+                const T *cy = sC + ((E + el) * 4) * NS + M * L;
+                const T *cz = sC + ((2 * E + el) * 4) * NS + M * L;
+                T *Re = R + e * (NV * NS) + M * L;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    T o[M];
+#pragma unroll
+                    for (int r = 0; r < M; ++r) o[r] = mid * ((ctb[k][r] + cy[k * NS + r]) + cz[k * NS + r]);
+                    if constexpr (STG) line_put<M, 1>(sU + el * EP + M * L + k * NS, o);
+                    else line_store<M, 1>(Re + k * NS, o);
+                }
+            }
+            if constexpr (!STG) {
+                // every thread: the auxiliary residuals from the tile
+                T *dst = R + e0 * RAW;
+                constexpr int A0 = 4 * NS, NA = 9 * NS;
+                if constexpr (LL::VEC && (A0 * sizeof(T)) % 16 == 0) {
+                    using V = typename V16<T>::type;
+                    constexpr int VW = 16 / sizeof(T), CPE = NA / VW;
+                    const int nch = nel * CPE;
+#pragma unroll 4
+                    for (int k = threadIdx.x; k < nch; k += NT) {
+                        const int ek = k / CPE, o = k - ek * CPE;
+                        __builtin_nontemporal_store(reinterpret_cast<const V *>(sU + ek * EP + A0)[o],
+                                                    reinterpret_cast<V *>(dst + ek * RAW + A0) + o);
+                    }
+                } else {
+                    const int nv = nel * NA;
+#pragma unroll 4
+                    for (int k = threadIdx.x; k < nv; k += NT) {
+                        const int ek = k / NA, o = k - ek * NA;
+                        __builtin_nontemporal_store(sU[ek * EP + A0 + o], dst + ek * RAW + A0 + o);
+                    }
+                }
+            }
+        } else {
+            // one pass over the batch: the three directions' parts from their
+            // slots, the auxiliary residuals from the tile
             T *dst = R + e0 * RAW;
-            constexpr int A0 = 4 * NS, NA = 9 * NS;
-            if constexpr (LL::VEC && (A0 * sizeof(T)) % 16 == 0) {
+            if constexpr (LL::VEC) {
                 using V = typename V16<T>::type;
-                constexpr int VW = 16 / sizeof(T), CPE = NA / VW;
+                constexpr int VW = 16 / sizeof(T), CPE = RAW / VW, C4 = 4 * NS / VW;
+                static_assert((4 * NS) % VW == 0, "P and momentum in whole chunks");
                 const int nch = nel * CPE;
 #pragma unroll 4
                 for (int k = threadIdx.x; k < nch; k += NT) {
                     const int ek = k / CPE, o = k - ek * CPE;
-                    __builtin_nontemporal_store(reinterpret_cast<const V *>(sU + ek * EP + A0)[o],
-                                                reinterpret_cast<V *>(dst + ek * RAW + A0) + o);
+                    V x;
+                    if (o < C4) {
+                        const V *cx = reinterpret_cast<const V *>(sC + (ek * 4) * NS) + o;
+                        const V *cy = reinterpret_cast<const V *>(sC + ((E + ek) * 4) * NS) + o;
+                        const V *cz = reinterpret_cast<const V *>(sC + ((2 * E + ek) * 4) * NS) + o;
+                        const V vx = *cx, vy = *cy, vz = *cz;
+#pragma unroll
+                        for (int w = 0; w < VW; ++w) x[w] = mid * ((vx[w] + vy[w]) + vz[w]);
+                        if constexpr (STG) reinterpret_cast<V *>(sU + ek * EP)[o] = x;
+                    } else {
+                        x = reinterpret_cast<const V *>(sU + ek * EP)[o];
+                    }
+                    if constexpr (!STG) __builtin_nontemporal_store(x, reinterpret_cast<V *>(dst) + k);
                 }
             } else {
-                const int nv = nel * NA;
+                const int nv = nel * RAW;
 #pragma unroll 4
                 for (int k = threadIdx.x; k < nv; k += NT) {
-                    const int ek = k / NA, o = k - ek * NA;
-                    __builtin_nontemporal_store(sU[ek * EP + A0 + o], dst + ek * RAW + A0 + o);
+                    const int ek = k / RAW, o = k - ek * RAW;
+                    T x;
+                    if (o < 4 * NS) {
+                        const T *cx = sC + (ek * 4) * NS + o;
+                        x = mid * ((cx[0] + cx[E * 4 * NS]) + cx[2 * E * 4 * NS]);
+                        if constexpr (STG) sU[ek * EP + o] = x;
+                    } else {
+                        x = sU[ek * EP + o];
+                    }
+                    if constexpr (!STG) __builtin_nontemporal_store(x, dst + k);
                 }
             }
         }
-    } else {
-        // one pass over the batch: the three directions' parts from their
-        // slots, the auxiliary residuals from the tile
-        T *dst = R + e0 * RAW;
-        if constexpr (LL::VEC) {
-            using V = typename V16<T>::type;
-            constexpr int VW = 16 / sizeof(T), CPE = RAW / VW, C4 = 4 * NS / VW;
-            static_assert((4 * NS) % VW == 0, "P and momentum in whole chunks");
-            const int nch = nel * CPE;
-#pragma unroll 4
-            for (int k = threadIdx.x; k < nch; k += NT) {
-                const int ek = k / CPE, o = k - ek * CPE;
-                V x;
-                if (o < C4) {
-                    const V *cx = reinterpret_cast<const V *>(sC + (ek * 4) * NS) + o;
-                    const V *cy = reinterpret_cast<const V *>(sC + ((E + ek) * 4) * NS) + o;
-                    const V *cz = reinterpret_cast<const V *>(sC + ((2 * E + ek) * 4) * NS) + o;
-                    const V vx = *cx, vy = *cy, vz = *cz;
-#pragma unroll
-                    for (int w = 0; w < VW; ++w) x[w] = mid * ((vx[w] + vy[w]) + vz[w]);
-                    if constexpr (STG) reinterpret_cast<V *>(sU + ek * EP)[o] = x;
-                } else {
-                    x = reinterpret_cast<const V *>(sU + ek * EP)[o];
-                }
-                if constexpr (!STG) __builtin_nontemporal_store(x, reinterpret_cast<V *>(dst) + k);
-            }
-        } else {
-            const int nv = nel * RAW;
-#pragma unroll 4
-            for (int k = threadIdx.x; k < nv; k += NT) {
-                const int ek = k / RAW, o = k - ek * RAW;
-                T x;
-                if (o < 4 * NS) {
-                    const T *cx = sC + (ek * 4) * NS + o;
-                    x = mid * ((cx[0] + cx[E * 4 * NS]) + cx[2 * E * 4 * NS]);
-                    if constexpr (STG) sU[ek * EP + o] = x;
-                } else {
-                    x = sU[ek * EP + o];
-                }
-                if constexpr (!STG) __builtin_nontemporal_store(x, dst + k);
-            }
+        if constexpr (STG) {
+            // ---- the RK stage update of the batch from its residual in the tile
+            constexpr int J = (E * RAW + NT - 1) / NT;
+            constexpr int C = line_stage_chunk<P, T>() < J ? line_stage_chunk<P, T>() : J;
+            __syncthreads();
+            stage_update_batch<J, C, NS, T, true>(
+                sp, [&](unsigned q) -> T & { return sU[(q / RAW) * EP + q % RAW]; }, threadIdx.x, NT,
+                (unsigned)nel * RAW, e0, ss);
         }
-    }
-    if constexpr (STG) {
-        // ---- the RK stage update of the batch from its residual in the tile
-        constexpr int J = (E * RAW + NT - 1) / NT;
-        constexpr int C = line_stage_chunk<P, T>() < J ? line_stage_chunk<P, T>() : J;
-        __syncthreads();
-        stage_update_batch<J, C, NS, T, true>(
-            sp, [&](unsigned q) -> T & { return sU[(q / RAW) * EP + q % RAW]; }, threadIdx.x, NT,
-            (unsigned)nel * RAW, e0, ss);
-    }
     };
     auto batch_at = [&](int64_t bt) {
         const int64_t e0 = bt * E;
