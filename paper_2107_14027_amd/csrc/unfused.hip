@@ -530,6 +530,53 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Stage 5 without LDS: one thread per point reads its six face values of every
+// variable straight from the common-flux blocks (its own +d blocks and the -d
+// neighbours' blocks) and corrects its 13 divergence values in place.
+template <int P, typename T>
+__global__ void __launch_bounds__(256)
+    k_u_correct_direct(T *__restrict__ Dv, const T *__restrict__ FI, const T *__restrict__ ops, int nx,
+                       int ny, int nz)
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M, BL = NV * NF;
+    using OL = OpsLayout<M>;
+    const int64_t ne = (int64_t)nx * ny * nz;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * NS) return;
+    const int64_t e = t / NS;
+    const int q = (int)(t - e * NS);
+    const int idx[3] = {q % M, (q / M) % M, q / (M * M)};
+    const int fps[3] = {idx[1] + M * idx[2], idx[0] + M * idx[2], idx[0] + M * idx[1]};
+    const T *fm[3], *fpl[3];
+    T glv[3], grv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int64_t nb = neighbour(e, 2 * d, nx, ny, nz);
+        fm[d] = FI + ((int64_t)d * ne + nb) * BL + fps[d];
+        fpl[d] = FI + ((int64_t)d * ne + e) * BL + fps[d];
+        glv[d] = ops[OL::gl + idx[d]];
+        grv[d] = ops[OL::gr + idx[d]];
+    }
+    T *Dq = Dv + (e * NV) * NS + q;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T acc = Dq[v * NS];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) acc = fma(glv[d], fm[d][v * NF], fma(grv[d], fpl[d][v * NF], acc));
+        Dq[v * NS] = acc;
+    }
+}
+
+// Which stage-5 kernel runs: without LDS at p = 2 (27-point elements, where
+// the staged form's six face blocks per element leave few workgroups per CU:
+// 0.39 -> 0.60 of its byte model in double precision) and p = 3 in single
+// precision; staged in LDS elsewhere (measured faster).
+template <int P, typename T>
+constexpr bool unfused_correct_direct()
+{
+    return P == 2 || (P == 3 && sizeof(T) == 4);
+}
+
 template <int P, typename T>
 int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const Consts<T> &c,
                  hipStream_t s)
@@ -588,9 +635,13 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
     {
         ProfScope ps(pl, FR_K_U_CORRECT, s);
         using RS = CorrectShape<P, T>;
-        hipLaunchKernelGGL((k_u_correct_lds<P, T>), dim3((unsigned)((ne + RS::E - 1) / RS::E)),
-                           dim3(RS::NT), (size_t)6 * RS::E * NV * NF * sizeof(T), s, Dv, FI, ops,
-                           pl->nx, pl->ny, pl->nz);
+        if (unfused_correct_direct<P, T>())
+            hipLaunchKernelGGL((k_u_correct_direct<P, T>), g(ne * NS), dim3(nt), 0, s, Dv, FI, ops,
+                               pl->nx, pl->ny, pl->nz);
+        else
+            hipLaunchKernelGGL((k_u_correct_lds<P, T>), dim3((unsigned)((ne + RS::E - 1) / RS::E)),
+                               dim3(RS::NT), (size_t)6 * RS::E * NV * NF * sizeof(T), s, Dv, FI, ops,
+                               pl->nx, pl->ny, pl->nz);
     }
     {
         ProfScope ps(pl, FR_K_U_NEGSRC, s);
