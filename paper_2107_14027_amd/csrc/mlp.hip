@@ -62,21 +62,17 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Hyperbolic tangent from the exponential identity tanh|x| = (1 - t) / (1 + t),
-// t = e^{-2|x|} = 2^{-2 log2(e) |x|}, on the hardware exp2 and reciprocal (no
-// overflow: the exponent is never positive); below |x| = 1/16, where 1 - t
-// cancels, the odd Taylor series to x^7 (truncation below 4e-13 relative).
-// Relative error about 1e-6, far below the BF16 rounding the activations get
-// next; both branches are straight-line code, so lanes do not diverge.
+// Hyperbolic tangent from the exponential identity tanh x = 1 - 2 / (1 + e^{2x}),
+// e^{2x} = 2^{2 log2(e) x}, on the hardware exp2 and reciprocal: four
+// instructions, no branch.  It saturates by itself (e^{2x} = inf gives 1, 0
+// gives -1).  The absolute error is a few units in the last place of 1 (below
+// 5e-7), against the BF16 rounding (2^-9 relative) the activations get next;
+// near x = 0 that is an absolute, not a relative, error, which is what the next
+// layer's sum sees.
 __device__ __forceinline__ float tanh_exp(float x)
 {
-    const float a = fabsf(x);
-    const float t = __builtin_amdgcn_exp2f(-2.88539008177792681f * a);
-    const float big = (1.0f - t) * __builtin_amdgcn_rcpf(1.0f + t);
-    const float s = a * a;
-    const float small =
-        a + a * s * (-1.0f / 3.0f + s * (2.0f / 15.0f + s * (-17.0f / 315.0f)));
-    return copysignf(a < 0.0625f ? small : big, x);
+    const float t = __builtin_amdgcn_exp2f(2.88539008177792681f * x);
+    return fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f + t), 1.0f);
 }
 
 __device__ __forceinline__ v4f mfma(v4s a, v4s b, v4f c)
@@ -92,29 +88,42 @@ struct Weights {
     float b1[4][4], b2[4][4], b3[4];  // bias of D rows 16r + 4(l/16) + t
 };
 
-__device__ __forceinline__ void load_weights(const float *__restrict__ P, Weights &w, int lane)
+// A operand k of lane l (k = r: W1 block r; k = 4 + 4 r2 + r: W2 block [r2][r];
+// k = 20 + r: W3 block r), packed to bf16.
+constexpr int NBLK = 24;
+
+__device__ __forceinline__ v4s weight_block(const float *__restrict__ P, int k, int lane)
 {
     const int i = lane & 15, g = lane >> 4;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        float v[4];
+    float v[4];
+    if (k < 4) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int k = 4 * g + j;
-            v[j] = k < NI ? P[OW1 + (16 * r + i) * NI + k] : 0.0f;
+            const int f = 4 * g + j;
+            v[j] = f < NI ? P[OW1 + (16 * k + i) * NI + f] : 0.0f;
         }
-        w.w1[r] = pack4(v[0], v[1], v[2], v[3]);
+    } else if (k < 20) {
+        const int r2 = (k - 4) >> 2, r = (k - 4) & 3;
+        const float *row = P + OW2 + (16 * r2 + i) * NH + 16 * r + 4 * g;
 #pragma unroll
-        for (int r2 = 0; r2 < 4; ++r2) {
-            const float *row = P + OW2 + (16 * r2 + i) * NH + 16 * r + 4 * g;
-            w.w2[r2][r] = pack4(row[0], row[1], row[2], row[3]);
-        }
-        if (i < NO) {
-            const float *row = P + OW3 + i * NH + 16 * r + 4 * g;
-            w.w3[r] = pack4(row[0], row[1], row[2], row[3]);
-        } else {
-            w.w3[r] = pack4(0.f, 0.f, 0.f, 0.f);
-        }
+        for (int j = 0; j < 4; ++j) v[j] = row[j];
+    } else {
+        const int r = k - 20;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = i < NO ? P[OW3 + i * NH + 16 * r + 4 * g + j] : 0.0f;
+    }
+    return pack4(v[0], v[1], v[2], v[3]);
+}
+
+__device__ __forceinline__ void load_weights(const float *__restrict__ P, Weights &w, int lane)
+{
+    const int g = lane >> 4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        w.w1[r] = weight_block(P, r, lane);
+#pragma unroll
+        for (int r2 = 0; r2 < 4; ++r2) w.w2[r2][r] = weight_block(P, 4 + 4 * r2 + r, lane);
+        w.w3[r] = weight_block(P, 20 + r, lane);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             w.b1[r][t] = P[OB1 + 16 * r + 4 * g + t];
@@ -183,62 +192,128 @@ __device__ __forceinline__ double extrap(double a, double b, double d, int order
     return order == 1 ? 2.0 * a - b : 3.0 * (a - b) + d;
 }
 
-// Guess kernel: waves loop over 16-point tiles (flat point index over (e, q)).
-__global__ void __launch_bounds__(256) k_mlp_guess(const float *__restrict__ S,
-                                                   const double *__restrict__ Un,
-                                                   const double *__restrict__ Unm1,
-                                                   const double *__restrict__ Unm2,
-                                                   double *__restrict__ G, int64_t npts, int ns,
-                                                   int order)
+// Guess kernel.  One lane per point, so every global load and store of a wave
+// covers 64 consecutive points (512 contiguous bytes of one variable); waves
+// loop over 64-point groups of the flat point index (e, q).  The weights sit in
+// LDS in A-operand order (read once per block), which keeps the registers to
+// the streaming state; each lane's normalised features go through LDS into the
+// B-operand layout of the four 16-point tiles, and the network outputs back to
+// the lane of their point.  Same operands and products as forward(), hence the
+// same bits.
+constexpr int GUESS_WAVES = 4;
+
+struct GuessLds {
+    v4s a[NBLK][64];            // weight_block(k, lane)
+    float b1[NH], b2[NH], b3[4];
+    v4s xs[GUESS_WAVES][4][64]; // per wave: features 4g..4g+3 of point pt at [g][pt]
+    v4f ys[GUESS_WAVES][64];    // per wave: network outputs of point pt
+};
+
+__device__ __forceinline__ v4f forward_lds(const GuessLds &L, int lane, v4s xb)
 {
-    const int lane = threadIdx.x & 63, g = lane >> 4, pi = lane & 15;
-    Weights w;
-    load_weights(S, w, lane);
-    float mu[4], isd[4], ysd[4];
+    const int g4 = 4 * (lane >> 4);
+    v4s hb[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int k = 4 * g + j;
-        mu[j] = k < NI ? S[ONORM + k] : 0.f;
-        isd[j] = k < NI ? S[ONORM + NI + k] : 0.f;
-        ysd[j] = S[ONORM + 2 * NI + j];
+    for (int r = 0; r < 4; ++r) {
+        v4f z = *(const v4f *)&L.b1[16 * r + g4];
+        z = mfma(L.a[r][lane], xb, z);
+        hb[r] = pack4(tanh_exp(z[0]), tanh_exp(z[1]), tanh_exp(z[2]), tanh_exp(z[3]));
     }
-    const int64_t ntile = (npts + 15) / 16;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t tile = wave; tile < ntile; tile += nwaves) {
-        const int64_t pt = tile * 16 + pi;
-        const bool ok = pt < npts;
-        const int64_t e = ok ? pt / ns : 0;
-        const int q = ok ? (int)(pt - e * ns) : 0;
-        const int64_t base = e * NV * ns + q;
-        float xv[4] = {0.f, 0.f, 0.f, 0.f};
-        if (ok && g < 3) {
+    v4s h2b[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t i = base + (int64_t)j * ns;   // variable j = P, u, v, w
-                const double a = Un[i], b = Unm1[i], d = Unm2[i];
-                const double raw = g == 0 ? a : (g == 1 ? a - b : (a - b) - (b - d));
-                xv[j] = (float)(raw - (double)mu[j]) * isd[j];
+    for (int r2 = 0; r2 < 4; ++r2) {
+        v4f z = *(const v4f *)&L.b2[16 * r2 + g4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z = mfma(L.a[4 + 4 * r2 + r][lane], hb[r], z);
+        h2b[r2] = pack4(tanh_exp(z[0]), tanh_exp(z[1]), tanh_exp(z[2]), tanh_exp(z[3]));
+    }
+    v4f y = g4 == 0 ? *(const v4f *)&L.b3[0] : v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y = mfma(L.a[20 + r][lane], h2b[r], y);
+    return y;
+}
+
+__global__ void __launch_bounds__(64 * GUESS_WAVES) k_mlp_guess(const float *__restrict__ S,
+                                                                const double *__restrict__ Un,
+                                                                const double *__restrict__ Unm1,
+                                                                const double *__restrict__ Unm2,
+                                                                double *__restrict__ G,
+                                                                int64_t npts, int ns, int order)
+{
+    __shared__ __align__(16) GuessLds L;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, g = lane >> 4, pi = lane & 15;
+    for (int i = threadIdx.x; i < NBLK * 64; i += 64 * GUESS_WAVES)
+        L.a[i >> 6][i & 63] = weight_block(S, i >> 6, i & 63);
+    if (threadIdx.x < NH) {
+        L.b1[threadIdx.x] = S[OB1 + threadIdx.x];
+        L.b2[threadIdx.x] = S[OB2 + threadIdx.x];
+    }
+    if (threadIdx.x < 4) L.b3[threadIdx.x] = S[OB3 + threadIdx.x];
+    L.xs[wv][3][lane] = pack4(0.f, 0.f, 0.f, 0.f);   // features 12..15: zero
+    __syncthreads();
+    const int64_t ngrp = (npts + 63) / 64;
+    const int64_t step = (int64_t)gridDim.x * GUESS_WAVES * 64;   // points per sweep of the grid
+    const int64_t de = step / ns;
+    const int dq = (int)(step - de * ns);
+    int64_t pt = ((int64_t)blockIdx.x * GUESS_WAVES + wv) * 64 + lane;
+    int64_t e = pt / ns;         // (e, q) of pt, advanced by step below
+    int q = (int)(pt - e * ns);
+    for (int64_t grp = pt >> 6; grp < ngrp; grp += step >> 6) {
+        const bool ok = pt < npts;
+        // lanes past the end read point 0 and write nothing
+        const int64_t base = ok ? e * NV * ns + q : 0;
+        // P, u, v, w: features (kind k: U^n, first, second difference) and extrapolation
+        float x[3][4];
+        double ex[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int64_t i = base + (int64_t)c * ns;
+            const double a = Un[i], b = Unm1[i], d = Unm2[i];
+            const double raw[3] = {a, a - b, (a - b) - (b - d)};
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                x[k][c] = ok ? (float)(raw[k] - (double)S[ONORM + 4 * k + c]) * S[ONORM + NI + 4 * k + c]
+                             : 0.0f;
+            ex[c] = extrap(a, b, d, order);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) L.xs[wv][k][lane] = pack4(x[k][0], x[k][1], x[k][2], x[k][3]);
+        wave_sync();
+        // the four 16-point tiles through the network; the nine auxiliary
+        // variables (the extrapolation alone) stream between them, their loads
+        // issued ahead of each tile's products
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int v0 = t == 0 ? 4 : 5 + 2 * t, v1 = 7 + 2 * t;   // 4-6, 7-8, 9-10, 11-12
+            double av[3], bv[3], dv[3];
+#pragma unroll
+            for (int v = v0; v < v1; ++v) {
+                const int64_t i = base + (int64_t)v * ns;
+                av[v - v0] = Un[i];
+                bv[v - v0] = Unm1[i];
+                dv[v - v0] = Unm2[i];
+            }
+            const v4f y = forward_lds(L, lane, L.xs[wv][g][16 * t + pi]);
+            if (g == 0) L.ys[wv][16 * t + pi] = y;
+            if (ok) {
+#pragma unroll
+                for (int v = v0; v < v1; ++v)
+                    G[base + (int64_t)v * ns] = extrap(av[v - v0], bv[v - v0], dv[v - v0], order);
             }
         }
-        Acts act;
-        const v4f y = forward(w, pack4(xv[0], xv[1], xv[2], xv[3]), act);
-        // every lane writes the extrapolation of some variables; lanes 0..15 add
-        // the network correction to P, u, v, w of their point
-        // lanes 0..15 (g = 0) write P, u, v, w of their point with the network
-        // correction; the nine auxiliary variables are split over the groups
+        wave_sync();
         if (ok) {
-            if (g == 0) {
+            const v4f y = L.ys[wv][lane];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t i = base + (int64_t)v * ns;
-                    G[i] = extrap(Un[i], Unm1[i], Unm2[i], order) + (double)(ysd[v] * y[v]);
-                }
-            }
-            for (int v = 4 + g; v < NV; v += 4) {
-                const int64_t i = base + (int64_t)v * ns;
-                G[i] = extrap(Un[i], Unm1[i], Unm2[i], order);
-            }
+            for (int c = 0; c < 4; ++c)
+                G[base + (int64_t)c * ns] = ex[c] + (double)(S[ONORM + 2 * NI + c] * y[c]);
+        }
+        pt += step;
+        e += de;
+        q += dq;
+        if (q >= ns) {
+            q -= ns;
+            ++e;
         }
     }
 }
@@ -839,10 +914,11 @@ int fr_mlp_guess(fr_plan *pl, const float *state, const double *Un, const double
     if (int rc = check_dev(G, "G")) return rc;
     const int ns = pl->m * pl->m * pl->m;
     const int64_t npts = pl->ne * ns;
-    const int64_t tiles = (npts + 15) / 16;
-    int64_t blocks = (tiles + 3) / 4;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_mlp_guess, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)s, state,
+    const int64_t groups = (npts + 63) / 64;   // 64 points per wave
+    int64_t blocks = (groups + GUESS_WAVES - 1) / GUESS_WAVES;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_mlp_guess, dim3((unsigned)blocks), dim3(64 * GUESS_WAVES), 0,
+                       (hipStream_t)s, state,
                        Un, Unm1, Unm2, G, npts, ns, pl->guess_base);
     return check_hip(hipGetLastError(), "k_mlp_guess launch");
 }

@@ -175,10 +175,13 @@ def test_sample_and_normalisation():
     plan.close()
 
 
-def test_guess_is_extrapolation_plus_network():
+@pytest.mark.parametrize("p,n", [(3, (2, 3, 2)), (2, (1, 2, 3)), (1, (3, 3, 5))])
+def test_guess_is_extrapolation_plus_network(p, n):
+    """64 points per wave: 768 points fill 12 groups, 162 and 360 end in a
+    ragged group."""
     t = torch()
-    p, n = 3, (2, 3, 2)
     plan = B.Plan(p, n, ZETA, NU, T_CFG)
+    ne, ns = n[0] * n[1] * n[2], (p + 1) ** 3
     Us = [t.tensor(inputs.tgv(p, n, noise=0.01, seed=k), device="cuda") for k in range(3)]
     G = t.empty_like(Us[0])
     E = t.empty_like(Us[0])
@@ -194,7 +197,7 @@ def test_guess_is_extrapolation_plus_network():
     B.fr_guess_extrap(plan.handle, Us[2], Us[1], Us[0], 2, E)
     st = random_state(14, scale=0.2)
     B.fr_mlp_guess(plan.handle, st, Us[2], Us[1], Us[0], G)
-    npts = 12 * 64
+    npts = ne * ns
     X = t.zeros((npts, 12), dtype=t.float32, device="cuda")
     Y = t.zeros((npts, 4), dtype=t.float32, device="cuda")
     B.fr_mlp_sample(plan.handle, Us[2], Us[1], Us[0], None, 0, 1, npts, X, Y)
@@ -202,10 +205,10 @@ def test_guess_is_extrapolation_plus_network():
     B.fr_mlp_forward(plan.handle, st, X, y)
     t.cuda.synchronize()
     ysd = st[5276:5280].double()
-    g4 = G.view(12, 13, 64)[:, :4].permute(0, 2, 1).reshape(npts, 4)
-    e4 = E.view(12, 13, 64)[:, :4].permute(0, 2, 1).reshape(npts, 4)
+    g4 = G.view(ne, 13, ns)[:, :4].permute(0, 2, 1).reshape(npts, 4)
+    e4 = E.view(ne, 13, ns)[:, :4].permute(0, 2, 1).reshape(npts, 4)
     assert t.allclose(g4 - e4, y.double() * ysd, rtol=0, atol=1e-6)
-    assert t.equal(G.view(12, 13, 64)[:, 4:], E.view(12, 13, 64)[:, 4:])
+    assert t.equal(G.view(ne, 13, ns)[:, 4:], E.view(ne, 13, ns)[:, 4:])
     plan.close()
 
 
