@@ -18,7 +18,8 @@ using namespace dev;
 
 // ---------------------------------------------------------------------------
 // Unfused pipeline: Table 1 stages as separate kernels through HBM.
-// Buffers: Uf[6][ne][13][NF], Fs[3][ne][13][NS], Dv[ne][13][NS], FI[3][ne][13][NF]
+// Buffers: Uf[6][ne][13][NF], Fs[3][ne][13][NS], Dv[ne][13][NS], FI[3][ne][13][NF],
+// one after another, each starting 256-byte aligned
 // ---------------------------------------------------------------------------
 
 // Stage 2: VW consecutive points of one element per thread (VW = 1 unless
@@ -167,34 +168,50 @@ __global__ void __launch_bounds__(256) k_u_negsrc(const T *__restrict__ Dv, cons
     R[t] = r;
 }
 
-// Stage 6 in 16-byte vectors, where a vector never straddles two variables
-// (m^3 a multiple of the vector width) and the arrays are aligned: the same
-// arithmetic, U read only for the auxiliary variables.
-template <int P, typename T>
-struct NegsrcVec {
-    static constexpr int NS = (P + 1) * (P + 1) * (P + 1), VW = 16 / (int)sizeof(T);
-    static constexpr bool value = NS % VW == 0;
-};
-
+// Stage 6 in 16-byte vectors over the flat [ne][13][m^3] arrays (all three
+// aligned): each component takes the variable of its own index, so a vector
+// may hold the end of one variable's block and the start of the next (m^3 >=
+// the vector width: at most one such boundary); U is read for the vectors that
+// hold an auxiliary variable.  The last n mod VW values (n = 13 ne m^3) go one
+// per thread to the first threads.  Per value the same arithmetic as k_u_negsrc.
 template <int P, typename T>
 __global__ void __launch_bounds__(256) k_u_negsrc_vec(const T *__restrict__ Dv, const T *__restrict__ U,
                                                       T *__restrict__ R, Consts<T> c, int64_t ne)
 {
-    constexpr int M = P + 1, NS = M * M * M, VW = NegsrcVec<P, T>::VW;
+    constexpr int M = P + 1, NS = M * M * M, VW = 16 / (int)sizeof(T);
+    static_assert(NS >= VW, "a vector crosses at most one variable boundary");
     using V = typename V16<T>::type;
+    const int64_t n = ne * NV * NS, nvec = n / VW;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ne * NV * NS / VW) return;
-    const int v = (int)((t * VW / NS) % NV);
-    const V dv = __builtin_nontemporal_load(reinterpret_cast<const V *>(Dv) + t);
-    V r;
+    if (t < nvec) {
+        const int64_t k0 = t * VW, blk = k0 / NS;   // blk = e * 13 + v of component 0
+        const int r0 = (int)(k0 - blk * NS);
+        const int v0 = (int)(blk % NV), v1 = v0 + 1 == NV ? 0 : v0 + 1;
+        int vw[VW];
+        bool aux = false;
 #pragma unroll
-    for (int w = 0; w < VW; ++w) r[w] = -c.inv_det * dv[w];
-    if (v >= 4) {
-        const V u = __builtin_nontemporal_load(reinterpret_cast<const V *>(U) + t);
+        for (int w = 0; w < VW; ++w) {
+            vw[w] = r0 + w < NS ? v0 : v1;
+            aux |= vw[w] >= 4;
+        }
+        const V dv = __builtin_nontemporal_load(reinterpret_cast<const V *>(Dv) + t);
+        V r;
 #pragma unroll
-        for (int w = 0; w < VW; ++w) r[w] -= c.invT * u[w];
+        for (int w = 0; w < VW; ++w) r[w] = -c.inv_det * dv[w];
+        if (aux) {
+            const V u = __builtin_nontemporal_load(reinterpret_cast<const V *>(U) + t);
+#pragma unroll
+            for (int w = 0; w < VW; ++w)
+                if (vw[w] >= 4) r[w] -= c.invT * u[w];
+        }
+        __builtin_nontemporal_store(r, reinterpret_cast<V *>(R) + t);
     }
-    __builtin_nontemporal_store(r, reinterpret_cast<V *>(R) + t);
+    if (t < n - nvec * VW) {
+        const int64_t k = nvec * VW + t;
+        T r = -c.inv_det * Dv[k];
+        if ((k / NS) % NV >= 4) r -= c.invT * U[k];
+        R[k] = r;
+    }
 }
 
 // Stage 1 as line tasks: a workgroup copies a batch of E consecutive elements
@@ -253,6 +270,11 @@ __global__ void __launch_bounds__((ProjectShape<P, T>::NT))
     }
 }
 
+// The staging copies below move CU values per thread per round: all CU loads
+// are issued before the first store, so each thread keeps CU loads in flight
+// instead of waiting out one memory latency per value.
+constexpr int CU = 8;
+
 // Copy of n contiguous values from global src to LDS dst (16-byte vectors
 // when both ends and the count allow).
 template <typename T, int NT>
@@ -261,10 +283,27 @@ __device__ __forceinline__ void block_copy_in(const T *__restrict__ src, T *__re
     using V = typename V16<T>::type;
     constexpr int VW = 16 / sizeof(T);
     if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0 && n % VW == 0) {
-        for (int k = threadIdx.x; k < n / VW; k += NT)
-            reinterpret_cast<V *>(dst)[k] = __builtin_nontemporal_load(reinterpret_cast<const V *>(src) + k);
+        const V *vs = reinterpret_cast<const V *>(src);
+        V *vd = reinterpret_cast<V *>(dst);
+        for (int k0 = threadIdx.x; k0 < n / VW; k0 += CU * NT) {
+            V r[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u)
+                if (k0 + u * NT < n / VW) r[u] = __builtin_nontemporal_load(vs + k0 + u * NT);
+#pragma unroll
+            for (int u = 0; u < CU; ++u)
+                if (k0 + u * NT < n / VW) vd[k0 + u * NT] = r[u];
+        }
     } else {
-        for (int k = threadIdx.x; k < n; k += NT) dst[k] = __builtin_nontemporal_load(src + k);
+        for (int k0 = threadIdx.x; k0 < n; k0 += CU * NT) {
+            T r[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u)
+                if (k0 + u * NT < n) r[u] = __builtin_nontemporal_load(src + k0 + u * NT);
+#pragma unroll
+            for (int u = 0; u < CU; ++u)
+                if (k0 + u * NT < n) dst[k0 + u * NT] = r[u];
+        }
     }
 }
 
@@ -291,23 +330,38 @@ __device__ __forceinline__ void copy_blocks(const T *__restrict__ src, const int
     constexpr int VW = 16 / sizeof(T);
     if constexpr ((BL * sizeof(T)) % 16 == 0) {
         constexpr int CB = BL / VW;
-        for (int k = threadIdx.x; k < nel * CB; k += NT) {
-            const int el = k / CB, o = k - el * CB;
-            reinterpret_cast<V *>(dst)[k] =
-                __builtin_nontemporal_load(reinterpret_cast<const V *>(src + nb[el] * BL) + o);
+        for (int k0 = threadIdx.x; k0 < nel * CB; k0 += CU * NT) {
+            V r[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                const int k = k0 + u * NT;
+                if (k < nel * CB) {
+                    const int el = k / CB, o = k - el * CB;
+                    r[u] = __builtin_nontemporal_load(reinterpret_cast<const V *>(src + nb[el] * BL) + o);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CU; ++u)
+                if (k0 + u * NT < nel * CB) reinterpret_cast<V *>(dst)[k0 + u * NT] = r[u];
         }
     } else {
-        for (int k = threadIdx.x; k < nel * BL; k += NT) {
-            const int el = k / BL, o = k - el * BL;
-            dst[k] = __builtin_nontemporal_load(src + nb[el] * BL + o);
+        for (int k0 = threadIdx.x; k0 < nel * BL; k0 += CU * NT) {
+            T r[CU];
+#pragma unroll
+            for (int u = 0; u < CU; ++u) {
+                const int k = k0 + u * NT;
+                if (k < nel * BL) {
+                    const int el = k / BL, o = k - el * BL;
+                    r[u] = __builtin_nontemporal_load(src + nb[el] * BL + o);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CU; ++u)
+                if (k0 + u * NT < nel * BL) dst[k0 + u * NT] = r[u];
         }
     }
 }
 
-// Stage 3 with the batch's transformed flux staged in LDS one direction at a
-// time (a contiguous block of E elements x 13 variables per direction); each
-// thread accumulates its point's 13 divergences over the three directions in
-// registers, in the order d = 0, 1, 2.
 template <int P, typename T>
 struct DivShape {
     static constexpr int M = P + 1, NS = M * M * M;
@@ -368,12 +422,13 @@ __global__ void __launch_bounds__((DivShape<P, T>::NT))
 // Stage 4 with the face blocks staged in LDS: a workgroup takes direction d and
 // E consecutive elements, copies their +d face blocks and the -d face blocks
 // of their +d neighbours (contiguous runs), forms the common flux of every face
-// point into LDS and writes the E output blocks as one contiguous run.
+// point, puts it in place of the +d blocks in LDS and writes the E output
+// blocks as one contiguous run.
 template <int P, typename T>
 struct CommonShape {
     static constexpr int M = P + 1, NF = M * M;
-    // as many elements as keep the three face-block buffers within 48 KB
-    static constexpr int EMAX = (48 * 1024) / (3 * NV * NF * (int)sizeof(T));
+    // as many elements as keep the two face-block buffers within 48 KB
+    static constexpr int EMAX = (48 * 1024) / (2 * NV * NF * (int)sizeof(T));
     static constexpr int E = EMAX < 32 ? EMAX : 32;
     static constexpr int NT = 64 * ((E * NF + 63) / 64);
 };
@@ -384,7 +439,7 @@ __global__ void __launch_bounds__((CommonShape<P, T>::NT))
 {
     constexpr int M = P + 1, NF = M * M, BL = NV * NF;
     constexpr int E = CommonShape<P, T>::E, NT = CommonShape<P, T>::NT;
-    __shared__ __align__(16) T sL[E * BL], sR[E * BL], sO[E * BL];
+    __shared__ __align__(16) T sL[E * BL], sR[E * BL];
     const int64_t ne = (int64_t)nx * ny * nz;
     const int64_t nb_blocks = (ne + E - 1) / E;
     const int d = (int)(blockIdx.x / nb_blocks);
@@ -398,8 +453,10 @@ __global__ void __launch_bounds__((CommonShape<P, T>::NT))
     copy_blocks<T, NT, BL>(Uf + (int64_t)(2 * d) * ne * BL, sNb, sR, nel);
     __syncthreads();
     const int t = threadIdx.x;
-    if (t < nel * NF) {
-        const int el = t / NF, fp = t - el * NF;
+    const bool act = t < nel * NF;
+    const int el = act ? t / NF : 0, fp = act ? t - el * NF : 0;
+    T out[NV];
+    if (act) {
         T L[NV], Rr[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -419,62 +476,17 @@ __global__ void __launch_bounds__((CommonShape<P, T>::NT))
         for (int v = 0; v < NV; ++v) {
             T f = T(0.5) * (fl[v] + fr[v]);
             if (v < 4) f -= T(0.5) * lam * (Rr[v] - L[v]);
-            sO[el * BL + v * NF + fp] = c.nmag[d] * f;
+            out[v] = c.nmag[d] * f;
         }
     }
+    __syncthreads();   // every thread has read its +d values
+    if (act) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sL[el * BL + v * NF + fp] = out[v];
+    }
     __syncthreads();
-    block_copy_out<T, NT>(sO, FI + ((int64_t)d * ne + e0) * BL, nel * BL);
+    block_copy_out<T, NT>(sL, FI + ((int64_t)d * ne + e0) * BL, nel * BL);
 }
-
-// Stage 4 without LDS: one thread per (direction d, element, face point) reads
-// the 13 values of both sides straight from the face blocks (for consecutive
-// threads, runs of m^2 consecutive values per variable) and writes its 13
-// common-flux values; many small independent threads keep the loads in flight.
-template <int P, typename T>
-__global__ void __launch_bounds__(256)
-    k_u_common_direct(const T *__restrict__ Uf, T *__restrict__ FI, Consts<T> c, int nx, int ny, int nz)
-{
-    constexpr int M = P + 1, NF = M * M, BL = NV * NF;
-    const int64_t ne = (int64_t)nx * ny * nz;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 3 * ne * NF) return;
-    const int d = (int)(t / (ne * NF));
-    const int64_t r = t - (int64_t)d * ne * NF;
-    const int64_t e = r / NF;
-    const int fp = (int)(r - e * NF);
-    const int64_t nb = neighbour(e, 2 * d + 1, nx, ny, nz);
-    const T *Lp = Uf + ((int64_t)(2 * d + 1) * ne + e) * BL + fp;
-    const T *Rp = Uf + ((int64_t)(2 * d) * ne + nb) * BL + fp;
-    T L[NV], Rr[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        L[v] = __builtin_nontemporal_load(Lp + v * NF);
-        Rr[v] = __builtin_nontemporal_load(Rp + v * NF);
-    }
-    T nh[3] = {c.nhat[d][0], c.nhat[d][1], c.nhat[d][2]};
-    T fl[NV], fr[NV];
-    flux_dot<T>(L, nh, c.zeta, c.nu, c.invT, fl);
-    flux_dot<T>(Rr, nh, c.zeta, c.nu, c.invT, fr);
-    T vnl = L[1] * nh[0] + L[2] * nh[1] + L[3] * nh[2];
-    T vnr = Rr[1] * nh[0] + Rr[2] * nh[1] + Rr[3] * nh[2];
-    const T al = fabs(vnl) + sqrt(vnl * vnl + c.zeta);
-    const T ar = fabs(vnr) + sqrt(vnr * vnr + c.zeta);
-    const T lam = al > ar ? al : ar;
-    T *Op = FI + ((int64_t)d * ne + e) * BL + fp;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        T f = T(0.5) * (fl[v] + fr[v]);
-        if (v < 4) f -= T(0.5) * lam * (Rr[v] - L[v]);
-        __builtin_nontemporal_store(c.nmag[d] * f, Op + v * NF);
-    }
-}
-
-// Which stage-4 kernel runs: without LDS from p = FR_UCOMMON_DIRECT_PMIN up
-// (measured: the staged form wins at p = 1, where a face block's runs are only
-// four values long).
-#ifndef FR_UCOMMON_DIRECT_PMIN
-#define FR_UCOMMON_DIRECT_PMIN 2
-#endif
 
 // Stage 5 with the common-flux blocks staged in LDS: a workgroup takes E
 // consecutive elements, copies for each direction their own blocks (+d faces)
@@ -567,14 +579,23 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// Which stage-5 kernel runs: without LDS at p = 2 (27-point elements, where
-// the staged form's six face blocks per element leave few workgroups per CU:
-// 0.39 -> 0.60 of its byte model in double precision) and p = 3 in single
-// precision; staged in LDS elsewhere (measured faster).
+// Which stage-5 kernel runs: without LDS at p = 3 in single precision, staged
+// in LDS elsewhere (measured faster).
+#ifndef FR_UCORRECT_DIRECT
+#define FR_UCORRECT_DIRECT 1
+#endif
+
 template <int P, typename T>
 constexpr bool unfused_correct_direct()
 {
-    return P == 2 || (P == 3 && sizeof(T) == 4);
+    return FR_UCORRECT_DIRECT != 0 && P == 3 && sizeof(T) == 4;
+}
+
+// Length of one stage buffer in the unfused scratch, rounded up to 64 values so
+// that every buffer starts 256-byte aligned (the 16-byte vector paths need it).
+inline size_t ubuf(size_t n)
+{
+    return (n + 63) & ~(size_t)63;
 }
 
 template <int P, typename T>
@@ -584,9 +605,9 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
     constexpr int M = P + 1, NS = M * M * M, NF = M * M;
     const int64_t ne = pl->ne;
     T *Uf = scratch;
-    T *Fs = Uf + (size_t)6 * ne * NV * NF;
-    T *Dv = Fs + (size_t)3 * ne * NV * NS;
-    T *FI = Dv + (size_t)ne * NV * NS;
+    T *Fs = Uf + ubuf((size_t)6 * ne * NV * NF);
+    T *Dv = Fs + ubuf((size_t)3 * ne * NV * NS);
+    T *FI = Dv + ubuf((size_t)ne * NV * NS);
     const int nt = 256;
     auto g = [&](int64_t n) { return dim3((unsigned)((n + nt - 1) / nt)); };
     {
@@ -625,12 +646,8 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
     {
         ProfScope ps(pl, FR_K_U_COMMON, s);
         using CS = CommonShape<P, T>;
-        if (P >= FR_UCOMMON_DIRECT_PMIN)
-            hipLaunchKernelGGL((k_u_common_direct<P, T>), g(3 * ne * (P + 1) * (P + 1)), dim3(nt), 0, s,
-                               Uf, FI, c, pl->nx, pl->ny, pl->nz);
-        else
-            hipLaunchKernelGGL((k_u_common_lds<P, T>), dim3((unsigned)(3 * ((ne + CS::E - 1) / CS::E))),
-                               dim3(CS::NT), 0, s, Uf, FI, c, pl->nx, pl->ny, pl->nz);
+        hipLaunchKernelGGL((k_u_common_lds<P, T>), dim3((unsigned)(3 * ((ne + CS::E - 1) / CS::E))),
+                           dim3(CS::NT), 0, s, Uf, FI, c, pl->nx, pl->ny, pl->nz);
     }
     {
         ProfScope ps(pl, FR_K_U_CORRECT, s);
@@ -645,9 +662,10 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
     }
     {
         ProfScope ps(pl, FR_K_U_NEGSRC, s);
-        if (NegsrcVec<P, T>::value && ((((uintptr_t)Dv | (uintptr_t)U | (uintptr_t)R) & 15) == 0))
-            hipLaunchKernelGGL((k_u_negsrc_vec<P, T>), g(ne * NV * NS / NegsrcVec<P, T>::VW), dim3(nt), 0,
-                               s, Dv, U, R, c, ne);
+        if ((((uintptr_t)Dv | (uintptr_t)U | (uintptr_t)R) & 15) == 0)
+            hipLaunchKernelGGL((k_u_negsrc_vec<P, T>), g((ne * NV * NS + 16 / sizeof(T) - 1) /
+                                                        (16 / sizeof(T))),
+                               dim3(nt), 0, s, Dv, U, R, c, ne);
         else
             hipLaunchKernelGGL((k_u_negsrc<P, T>), g(ne * NV * NS), dim3(nt), 0, s, Dv, U, R, c, ne);
     }
@@ -676,7 +694,9 @@ int launch_residual_unfused(fr_plan *pl, const void *U, void *R, hipStream_t s)
     const int m = pl->m;
     const size_t NS = (size_t)m * m * m, NF = (size_t)m * m;
     const size_t esz = pl->precision == FR_F64 ? 8 : 4;
-    const size_t n = (size_t)pl->ne * NV * (6 * NF + 3 * NS + NS + 3 * NF);
+    const size_t ne = (size_t)pl->ne;
+    const size_t n = ubuf(ne * NV * 6 * NF) + ubuf(ne * NV * 3 * NS) + ubuf(ne * NV * NS) +
+                     ubuf(ne * NV * 3 * NF);
     if (int rc = ensure_scratch(pl->unfused, n * esz)) return rc;
     if (pl->precision == FR_F64)
         return dispatch_unfused<double>(pl, (const double *)U, (double *)R,

@@ -100,6 +100,20 @@ def test_degenerate_lattices(n, prec):
         check_groups(R, Ro, prec, U, what="degenerate")
 
 
+@pytest.mark.parametrize("p", [2, 4, 6])
+@pytest.mark.parametrize("prec", PREC)
+def test_unfused_odd_lengths(p, prec):
+    """13 ne m^3 odd: the unfused pipeline's last stage runs 16-byte vectors
+    that straddle two variables' blocks and a scalar tail, in both precisions."""
+    n = (3, 1, 1)
+    U = rand_U(p, n, seed=500 + p)
+    say("unfused odd length p=%d prec=%d" % (p, prec))
+    R = gpu_residual(p, n, U, precision=prec, variant=B.FR_UNFUSED)
+    Ro = oracle.residual(p, n, U, ZETA, NU, T_CFG)
+    assert rel(R, Ro) <= TOL[prec], rel(R, Ro)
+    check_groups(R, Ro, prec, U, what="odd length p=%d" % p)
+
+
 def test_free_stream_and_paper_T():
     """Uniform state gives a zero residual; the paper's own T = 5e-3, zeta = 2.5."""
     p, n = 4, (3, 2, 2)
