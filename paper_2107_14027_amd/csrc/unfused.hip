@@ -2,7 +2,8 @@
 // paper's Table 1 as six kernels, every intermediate through HBM (the
 // baseline the fused kernels are measured against).
 //   k_u_project_lines  stage 1  U_f = solution projected to the six faces (13
-//                      values), line tasks on an LDS-staged batch
+//                      values), line tasks on an LDS-staged batch (k_u_project_flat:
+//                      the same tile, one output value per lane, contiguous stores)
 //   k_u_flux     stage 2  F_s  = transformed flux at the points (3 x 13 values)
 //   k_u_div_lds  stage 3  partially corrected divergence of F_s, staged in LDS
 //                         one direction at a time
@@ -268,6 +269,66 @@ __global__ void __launch_bounds__((ProjectShape<P, T>::NT))
         dm[v * NF] = am;
         dp[v * NF] = ap;
     }
+}
+
+// Stage 1 with contiguous stores: the same LDS tile, then for each direction d
+// the outputs of both faces flat over (element, variable, face point), the
+// layout of a face block, so that consecutive lanes store consecutive values.
+// Each output is its line's projection with the operations of
+// k_u_project_lines in the same order (the same bits).
+template <int P, typename T>
+__global__ void __launch_bounds__(256)
+    k_u_project_flat(const T *__restrict__ U, T *__restrict__ Uf, const T *__restrict__ ops, int64_t ne)
+{
+    constexpr int M = P + 1, NS = M * M * M, NF = M * M, BL = NV * NF, NT = 256;
+    constexpr int E = ProjectShape<P, T>::E;
+    using LL = LinesLds<P, T>;
+    using OL = OpsLayout<M>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sU = reinterpret_cast<T *>(smem_raw);
+    const int64_t e0 = (int64_t)blockIdx.x * E;
+    const int nel = (int)min((int64_t)E, ne - e0);
+    tile_load<P, T, NT>(U + e0 * LL::raw, sU, nel);
+    __syncthreads();
+    T lm[M], lp[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        lm[l] = ops[OL::lm + l];
+        lp[l] = ops[OL::lp + l];
+    }
+    const int n = nel * BL;
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+        const int str = d == 0 ? 1 : (d == 1 ? M : M * M);
+        T *dm = Uf + ((int64_t)(2 * d) * ne + e0) * BL;
+        T *dp = Uf + ((int64_t)(2 * d + 1) * ne + e0) * BL;
+        for (int o = threadIdx.x; o < n; o += NT) {
+            const int el = o / BL, r = o - el * BL, v = r / NF, L = r - v * NF;
+            const int a = L % M, b = L / M;
+            const int base = d == 0 ? M * L : (d == 1 ? a + M * M * b : L);
+            const T *x = sU + el * LL::EP + v * NS + base;
+            T am = T(0), ap = T(0);
+#pragma unroll
+            for (int l = 0; l < M; ++l) {
+                am = fma(lm[l], x[l * str], am);
+                ap = fma(lp[l], x[l * str], ap);
+            }
+            dm[o] = am;
+            dp[o] = ap;
+        }
+    }
+}
+
+// Which stage-1 kernel runs: the flat form at p <= 2 (the line form's stores
+// are runs of m^2 values scattered over 13 m^2-value blocks) and at p = 3 in
+// single precision, the line form elsewhere (measured faster or equal).
+#ifndef FR_UPROJECT_FLAT
+#define FR_UPROJECT_FLAT 1
+#endif
+template <int P, typename T>
+constexpr bool unfused_project_flat()
+{
+    return FR_UPROJECT_FLAT != 0 && (P <= 2 || (P == 3 && sizeof(T) == 4));
 }
 
 // The staging copies below move CU values per thread per round: all CU loads
@@ -616,16 +677,20 @@ int unfused_impl(fr_plan *pl, const T *U, T *R, T *scratch, const T *ops, const 
         const size_t lds = (size_t)PS::E * LinesLds<P, T>::EP * sizeof(T);
         int &set = pl->unfused_attr[P][sizeof(T) == 8];
         if (!set) {
-            if (int rc = check_hip(hipFuncSetAttribute((const void *)k_u_project_lines<P, T>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)lds),
-                                   "hipFuncSetAttribute"))
-                return rc;
+            for (const void *k : {(const void *)k_u_project_lines<P, T>, (const void *)k_u_project_flat<P, T>})
+                if (int rc = check_hip(
+                        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds),
+                        "hipFuncSetAttribute"))
+                    return rc;
             set = 1;
         }
         ProfScope ps(pl, FR_K_U_PROJECT, s);
-        hipLaunchKernelGGL((k_u_project_lines<P, T>), dim3((unsigned)((ne + PS::E - 1) / PS::E)),
-                           dim3(PS::NT), lds, s, U, Uf, ops, ne);
+        if (unfused_project_flat<P, T>())
+            hipLaunchKernelGGL((k_u_project_flat<P, T>), dim3((unsigned)((ne + PS::E - 1) / PS::E)),
+                               dim3(256), lds, s, U, Uf, ops, ne);
+        else
+            hipLaunchKernelGGL((k_u_project_lines<P, T>), dim3((unsigned)((ne + PS::E - 1) / PS::E)),
+                               dim3(PS::NT), lds, s, U, Uf, ops, ne);
     }
     {
         ProfScope ps(pl, FR_K_U_FLUX, s);
