@@ -7,7 +7,7 @@
 //
 // Network, per point:  x (12) -> h1 = tanh(W1 x + b1) (64) -> h2 = tanh(W2 h1 + b2) (64)
 //                      -> y = W3 h2 + b3 (4)
-// Features (normalised, x = (raw - mu) * inv_sd):
+// Features (normalised in FP32, x = ((float) raw - mu) * inv_sd):
 //   raw = [U^n_c,  U^n_c - U^{n-1}_c,  U^n_c - 2 U^{n-1}_c + U^{n-2}_c]  for c = P, u, v, w
 // Guess:  G_c = E_c + y_sd_c * y_c        (c = P, u, v, w)
 //         G_v = E_v                         (auxiliary v)
@@ -270,10 +270,11 @@ __global__ void __launch_bounds__(64 * GUESS_WAVES) k_mlp_guess(const float *__r
             const int64_t i = base + (int64_t)c * ns;
             const double a = Un[i], b = Unm1[i], d = Unm2[i];
             const double raw[3] = {a, a - b, (a - b) - (b - d)};
+            // normalised in FP32 from the raw feature rounded to FP32, as the
+            // training samples are (fr_mlp_sample, then k_mlp_forward / k_mlp_grad)
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                x[k][c] = ok ? (float)(raw[k] - (double)S[ONORM + 4 * k + c]) * S[ONORM + NI + 4 * k + c]
-                             : 0.0f;
+                x[k][c] = ok ? ((float)raw[k] - S[ONORM + 4 * k + c]) * S[ONORM + NI + 4 * k + c] : 0.0f;
             ex[c] = extrap(a, b, d, order);
         }
 #pragma unroll

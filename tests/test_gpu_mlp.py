@@ -175,10 +175,12 @@ def test_sample_and_normalisation():
     plan.close()
 
 
-@pytest.mark.parametrize("p,n", [(3, (2, 3, 2)), (2, (1, 2, 3)), (1, (3, 3, 5))])
+@pytest.mark.parametrize("p,n", [(3, (2, 3, 2)), (2, (1, 2, 3)), (1, (3, 3, 5)), (2, (30, 30, 30))])
 def test_guess_is_extrapolation_plus_network(p, n):
     """64 points per wave: 768 points fill 12 groups, 162 and 360 end in a
-    ragged group."""
+    ragged group; 729,000 points at p = 2 exceed one sweep of the launch grid
+    (2048 workgroups x 4 waves x 64 points), so waves take a second group, with
+    a point index that wraps (27 does not divide the sweep)."""
     t = torch()
     plan = B.Plan(p, n, ZETA, NU, T_CFG)
     ne, ns = n[0] * n[1] * n[2], (p + 1) ** 3
@@ -207,6 +209,8 @@ def test_guess_is_extrapolation_plus_network(p, n):
     ysd = st[5276:5280].double()
     g4 = G.view(ne, 13, ns)[:, :4].permute(0, 2, 1).reshape(npts, 4)
     e4 = E.view(ne, 13, ns)[:, :4].permute(0, 2, 1).reshape(npts, 4)
+    # the same features and products as the forward kernel: only the final
+    # FP32 product and FP64 additions round differently
     assert t.allclose(g4 - e4, y.double() * ysd, rtol=0, atol=1e-6)
     assert t.equal(G.view(ne, 13, ns)[:, 4:], E.view(ne, 13, ns)[:, 4:])
     plan.close()
